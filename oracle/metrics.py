@@ -1,0 +1,66 @@
+"""Quality metrics and the tie classification (oracle; test infrastructure only).
+
+PSNR against the uncompressed texture (Sec. 4.3): 10 log10(255^2 / MSE) over every texel and channel,
++inf when identical.  Block identity: the fraction of identical 64-bit words.
+
+Tie classification of a block that differs between an implementation under test and the oracle: the
+block is a quantisation-boundary tie when (1) packing the implementation's own head values with the
+oracle's float32 packer reproduces its word bit for bit, and (2) the oracle's smallest decision margin
+for that block (distance of an endpoint value to its rounding boundary, in y units; gap between the two
+nearest palette distances) is no larger than the head difference |Y_impl - Y_oracle|_inf of the block
+(twice that for the squared-distance gap, whose sensitivity is bounded by 2|dY| per unit distance).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ntbc
+
+
+def psnr(original, decoded):
+    a = np.asarray(original, dtype=np.float64)
+    b = np.asarray(decoded, dtype=np.float64)
+    mse = ((a - b) ** 2).mean()
+    return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+
+
+def identity(words_a, words_b):
+    a = np.asarray(words_a, dtype=np.uint64)
+    b = np.asarray(words_b, dtype=np.uint64)
+    return float((a == b).mean())
+
+
+def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
+    """Per texture: number of differing blocks and how many of them are boundary ties.
+
+    Returns dict with 'differ', 'ties', 'repack_exact' (condition 1 over all blocks)."""
+    lay = ntbc.Layout(formats)
+    Y_impl = np.asarray(Y_impl)
+    dy = np.abs(Y_impl.astype(np.float64) - Y_oracle).max(axis=1)
+    out = {"differ": 0, "ties": 0, "repack_exact": True, "max_dy": float(dy.max()) if len(dy) else 0.0}
+    for t in range(len(lay.formats)):
+        repacked = ntbc.pack_texture(Y_impl, lay, t, "f32")
+        if not np.array_equal(repacked, words_impl[t]):
+            out["repack_exact"] = False
+        diff = words_impl[t] != words_oracle[t]
+        if not diff.any():
+            continue
+        _, ep_m, idx_m = ntbc.pack_texture(Y_oracle[diff], lay, t, "f64", return_margin=True)
+        # the squared-distance gap moves by at most ~4|dY| (two distances, each 2|d||dY|, |d| <= 1)
+        tie = (ep_m <= dy[diff] * (1 + 1e-9)) | (idx_m <= 4.0 * dy[diff] * (1 + 1e-9))
+        out["differ"] += int(diff.sum())
+        out["ties"] += int(tie.sum())
+    return out
+
+
+def model_bytes(grids, mlps, bytes_per_feature: int = 1, bytes_per_param: int = 2):
+    """Stored size of a model: dense grids of res_l^2 vertices (res_l = base * 2^l) with
+    ``bytes_per_feature`` per feature, plus MLP weights and biases at ``bytes_per_param`` each.
+
+    grids: iterable of (n_levels, base_res, n_features); mlps: iterable of layer widths [in, ..., out]."""
+    total = 0
+    for n_levels, base_res, n_features in grids:
+        total += sum((base_res << l) ** 2 for l in range(n_levels)) * n_features * bytes_per_feature
+    for dims in mlps:
+        total += sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1)) * bytes_per_param
+    return total

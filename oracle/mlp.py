@@ -1,0 +1,80 @@
+"""The MLP trunk (oracle; test infrastructure only).
+
+Paper anchor: small MLPs with sigmoid outputs predicting values in [0,1] (Sec. 3.4, model
+configuration).  The workloads built here use one trunk with ReLU hidden layers (the paper's networks
+use SELU; a ReLU trunk is the reading used for these workloads):
+
+    h_0 = x,  h_{k+1} = ReLU(W_k h_k + b_k)  (hidden layers),   Y = sigmoid(W_out h + b_out).
+
+Weights are [out][in] float32 arrays, biases [out].  Arithmetic is float64 (``precision="f64"``), or
+emulates a reduced-precision matrix path with float64 accumulation:
+
+  * ``"bf16"``: every layer input and every weight rounded to bfloat16 (round-to-nearest-even);
+  * ``"fp8"``: per-layer scales (s_x, s_w); the layer input is rounded to E4M3 as x / s_x, the weight
+    as W * (1/s_w) evaluated in float32 (the GPU path's precision for this integer decision), and the
+    product is rescaled by s_x * s_w before the bias is added.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lowp
+
+
+def sigmoid(z):
+    with np.errstate(over="ignore"):
+        return 1.0 / (1.0 + np.exp(-z))
+
+
+def fp8_weight(w, s_w):
+    w32 = np.asarray(w, dtype=np.float32)
+    inv = np.float32(np.float32(1.0) / np.float32(s_w))
+    return lowp.round_e4m3((w32 * inv).astype(np.float64))
+
+
+def forward(layers, x, precision: str = "f64", scales=None):
+    """Returns (Y, cache) for inputs x [n, in].  cache = (inputs h_k, pre-activations z_k)."""
+    h = np.asarray(x, dtype=np.float64)
+    hs, zs = [], []
+    n_layers = len(layers)
+    for k, (w, b) in enumerate(layers):
+        w = np.asarray(w, dtype=np.float64)
+        b = np.asarray(b, dtype=np.float64)
+        hs.append(h)
+        if precision == "f64":
+            z = h @ w.T + b
+        elif precision == "bf16":
+            z = lowp.round_bf16(h) @ lowp.round_bf16(w).T + b
+        elif precision == "fp8":
+            s_x, s_w = float(scales[k][0]), float(scales[k][1])
+            xq = lowp.round_e4m3(h / s_x)
+            wq = fp8_weight(w, s_w)
+            z = (xq @ wq.T) * (s_x * s_w) + b
+        else:
+            raise ValueError(precision)
+        zs.append(z)
+        h = np.maximum(z, 0.0) if k < n_layers - 1 else sigmoid(z)
+    return h, (hs, zs)
+
+
+def backward(layers, cache, d_y, y):
+    """Gradients (dW list, db list, dx) of a scalar loss given dL/dY (float64)."""
+    hs, zs = cache
+    dz = d_y * y * (1.0 - y)
+    dws, dbs = [None] * len(layers), [None] * len(layers)
+    for k in range(len(layers) - 1, -1, -1):
+        w = np.asarray(layers[k][0], dtype=np.float64)
+        dws[k] = dz.T @ hs[k]
+        dbs[k] = dz.sum(axis=0)
+        dh = dz @ w
+        if k > 0:
+            dz = dh * (zs[k - 1] > 0)
+        else:
+            dx = dh
+    return dws, dbs, dx
+
+
+def activation_absmax(layers, x):
+    """max |input| of every layer over the rows of x (float64 forward); for FP8 scale calibration."""
+    _, (hs, _) = forward(layers, x, "f64")
+    return [float(np.abs(h).max()) for h in hs]
