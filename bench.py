@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""NTBC benchmark on one MI355X: inference blocks/s of a five-texture 4096^2 material in BF16 and
+FP32, with the decoded-PSNR delta between them, the reference-encoder and decoder rates, the encode
+time of a material, the roofline position of the fused inference kernel, and the CPU oracle timed on
+a bounded sample of the same workload.
+
+A timed step is one inference of every block of the material (1,048,576 block positions x 5
+textures = 5,242,880 BC blocks) with the inputs (grid, weights) resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NTBC inference blocks/s at 4096² BF16 vs FP32 @ ΔPSNR≤0.1dB; encode s/material"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_position(cfg):
+    """Algorithmic FLOP of the MLP per block position: 2 * sum(fan_in * fan_out)."""
+    return 2 * sum(i * o for i, o in cfg.layer_dims())
+
+
+def psnr(a, b):
+    mse = float(((a.astype(np.float64) - b.astype(np.float64)) ** 2).mean())
+    return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+
+
+def time_call(fn, steps, warmup, torch):
+    """Average ms per call over `steps` calls (HIP events on the current stream), after `warmup`."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
+    """The FP64 oracle (heads and packing) on a sample of block positions, timed on the host."""
+    from oracle import ntbc as ON
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = 1
+    levels = ON.grid_levels(cfg, codes=grid_codes, scales=scale, zeros=zero)
+    rng = np.random.default_rng(0)
+    n = 2048
+    t_used = 0.0
+    while True:
+        ids = rng.choice(cfg.n_positions, n, replace=False)
+        t0 = time.perf_counter()
+        ON.infer_blocks(cfg, levels, layers, ids)
+        t_used = time.perf_counter() - t0
+        if t_used * 2 > budget_s or n >= 262144:
+            break
+        n *= 2
+    blocks = n * len(cfg.formats)
+    return {"value": blocks / t_used, "unit": "blocks/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} random block positions of the 4096^2 five-texture material "
+                      f"({blocks} BC blocks), FP64 heads + packing, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(inference shards by block range with no communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_09543_amd import ntbc, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = synth.config_paper_scale(args.size)
+    log(f"generating {args.size}^2 five-texture material")
+    mat = synth.material_five(args.size, 3)
+    tex = [torch.from_numpy(t.texels).to(dev) for t in mat.textures]
+
+    # reference encoding of the targets (also the fallback), and decode
+    ref = [ntbc.encode_ref(t, f) for t, f in zip(tex, cfg.formats)]
+    enc_ms = time_call(lambda: [ntbc.encode_ref(t, f) for t, f in zip(tex, cfg.formats)], 3, 1, torch)
+    dec_ms = time_call(lambda: [ntbc.decode(r, args.size, args.size, f) for r, f in zip(ref, cfg.formats)],
+                       5, 1, torch)
+    ref_psnr = [psnr(ntbc.decode(r, args.size, args.size, f).cpu().numpy(), t.texels)
+                for r, f, t in zip(ref, cfg.formats, mat.textures)]
+
+    # model (random parameters of the paper-scale shape; values do not change the work)
+    layers = synth.init_weights(cfg, 3)
+    rng = np.random.default_rng(3)
+    layers = [(w, (0.3 * rng.standard_normal(len(b))).astype(np.float32)) for w, b in layers]
+    codes, _, _ = synth.random_u8_grid(cfg, 3)
+    scale = (np.full(cfg.n_levels, 0.7 / 128.0)).astype(np.float32)
+    zero = np.full(cfg.n_levels, 128, dtype=np.int32)
+    model = ntbc.Model(ntbc.desc_from_config(cfg), torch.from_numpy(synth.flatten_weights(layers)).to(dev),
+                       torch.from_numpy(codes).to(dev), torch.from_numpy(scale).to(dev),
+                       torch.from_numpy(zero).to(dev))
+    n_blocks = cfg.n_positions * len(cfg.formats)
+    out_bf = torch.empty((len(cfg.formats), cfg.n_positions), dtype=torch.int64, device=dev)
+    out_fp = torch.empty_like(out_bf)
+    model.infer(ntbc.BF16, out=out_bf)
+    model.infer(ntbc.FP32, out=out_fp)
+    torch.cuda.synchronize()
+
+    log(f"timing BF16 inference: {args.steps} steps after {args.warmup} warm-up")
+    torch.cuda.synchronize()
+    ms_bf = time_call(lambda: model.infer(ntbc.BF16, out=out_bf, reuse_packed=True), args.steps, args.warmup, torch)
+    steps_fp = max(2, args.steps // 4)
+    ms_fp = time_call(lambda: model.infer(ntbc.FP32, out=out_fp, reuse_packed=True), steps_fp, 1, torch)
+
+    # quality: BF16 vs FP32 blocks, decoded PSNR of each against the texture
+    wb, wf = out_bf.cpu().numpy(), out_fp.cpu().numpy()
+    identity = float((wb == wf).mean())
+    dpsnr = []
+    for t, (f, m) in enumerate(zip(cfg.formats, mat.textures)):
+        pb = psnr(ntbc.decode(out_bf[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
+        pf = psnr(ntbc.decode(out_fp[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
+        dpsnr.append(abs(pb - pf))
+
+    flop = flops_per_position(cfg) * cfg.n_positions
+    achieved = flop / (ms_bf * 1e-3) / 1e12
+    result = {
+        "metric": METRIC,
+        "value": n_blocks / (ms_bf * 1e-3),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_bf,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"ntbc-inference-{args.size}x{args.size}-five-texture",
+                   "texture_size": args.size, "textures": "2xBC1+3xBC4", "block_positions": cfg.n_positions,
+                   "blocks_per_step": n_blocks, "mlp": "64-256x3-162 relu/sigmoid",
+                   "grid": "8 levels 8..1024 x 8 uint8", "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                     "kernel": "k_infer_bf16<256>", "flop_per_launch": flop},
+        "fp32": {"blocks_per_s": n_blocks / (ms_fp * 1e-3), "ms_per_step": ms_fp,
+                 "tflops": flop / (ms_fp * 1e-3) / 1e12, "frac_fp32_peak": flop / (ms_fp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
+        "speedup_bf16_vs_fp32": ms_fp / ms_bf,
+        "identity_bf16_vs_fp32": identity,
+        "dpsnr_db_bf16_vs_fp32": {"per_texture": dpsnr, "max": max(dpsnr)},
+        "ref_encoder": {"ms_per_material": enc_ms, "blocks_per_s": n_blocks / (enc_ms * 1e-3), "psnr_db": ref_psnr},
+        "decoder": {"ms_per_material": dec_ms, "blocks_per_s": n_blocks / (dec_ms * 1e-3)},
+        "encode_s_per_material": None,
+        "model_note": "random parameters of the paper-scale shape (inference cost does not depend on values)",
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(cfg, layers, codes, scale, zero, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * libntbc -- Neural Texture Block Compression (BC1/BC4) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library.  Every entry point:
+ *   - takes plain pointers and sizes (no C++ or framework types);
+ *   - takes DEVICE pointers for every array (caller-owned; the library never frees them) unless the
+ *     argument is documented as a host struct;
+ *   - is asynchronous on the HIP stream passed as `stream` (a hipStream_t, NULL = the null stream):
+ *     it validates its arguments on the host, enqueues kernels and returns without synchronising;
+ *   - returns NTBC_OK (0) or a negative status; on error nothing has been enqueued (argument errors)
+ *     or the HIP error is reported (NTBC_EHIP) and ntbc_last_error() describes it;
+ *   - allocates no device memory: scratch comes from the caller's `workspace` (size from
+ *     ntbc_workspace_size) where an entry point has one.
+ *
+ * Data layouts
+ *   Textures   row-major uint8, `row_pitch` bytes between rows; BC1 textures have 3 channels (RGB),
+ *              BC4 textures 1.  Width and height are multiples of 4.
+ *   Blocks     uint64 little-endian BC words, row-major over the block grid: block id
+ *              b = by * (width/4) + bx.  BC1: c0 = bits 0-15, c1 = bits 16-31 (RGB565, R in the top
+ *              5 bits), 2-bit code of texel i = 4y+x at bit 32+2i.  BC4: e0 = bits 0-7, e1 = bits 8-15,
+ *              3-bit code of texel i at bit 16+3i.
+ *   Grid       level-major, then vertex j*res_l + i (j = row), then feature: res_l = base_res << l,
+ *              sum_l res_l^2 vertices of n_features each.  FP32 grids hold real values; U8 grids hold
+ *              codes q with value scale_l * (q - zero_l).
+ *   Weights    FP32, canonical flat order W_1, b_1, W_2, b_2, ..., W_out, b_out with W_k row-major
+ *              [fan_out][fan_in].  Layers: in_dim = n_levels * n_features -> hidden_width (n_hidden
+ *              times, ReLU) -> head_dim (sigmoid).
+ *   Heads      head_dim floats per block position: the endpoint head (per texture in order: BC1 ->
+ *              R0 G0 B0 R1 G1 B1, BC4 -> e0 e1) followed by the colour head, texel-major
+ *              [texel 0..15][channels of every texture in order].
+ *
+ * Paper: S. Fujieda and T. Harada, "Neural Texture Block Compression" (arXiv 2407.09543).  Section
+ * numbers below refer to it.
+ */
+#ifndef NTBC_H
+#define NTBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------------ */
+#define NTBC_OK 0
+#define NTBC_EINVAL (-1)          /* null pointer, bad size, bad enum, dims not multiples of 4     */
+#define NTBC_EUNSUPPORTED (-2)    /* a valid combination this build does not implement            */
+#define NTBC_EHIP (-3)            /* a HIP runtime error; see ntbc_last_error()                    */
+#define NTBC_ENOWORKSPACE (-5)    /* workspace NULL or smaller than ntbc_workspace_size()          */
+
+/* ---- enums ------------------------------------------------------------------------------------- */
+#define NTBC_BC1 1
+#define NTBC_BC4 4
+
+#define NTBC_FP32 0               /* MLP in FP32 (FP32 matrix cores), FP32 accumulation             */
+#define NTBC_BF16 1               /* MLP weights and layer inputs in BF16, FP32 accumulation         */
+#define NTBC_FP8_E4M3 2           /* MLP weights and layer inputs in FP8 E4M3 with per-layer scales  */
+
+#define NTBC_GRID_F32 0
+#define NTBC_GRID_U8 1
+
+#define NTBC_MAX_TEXTURES 8
+#define NTBC_MAX_LEVELS 12
+
+/* One material's model shape (host struct; sizes only). */
+typedef struct {
+  int32_t n_levels;       /* grid levels L, 1..NTBC_MAX_LEVELS                                      */
+  int32_t base_res;       /* res_0 >= 2; res_l = base_res << l                                       */
+  int32_t n_features;     /* F per level: 1, 2, 4, 8 or 16                                           */
+  int32_t grid_dtype;     /* NTBC_GRID_F32 or NTBC_GRID_U8 (inference input only)                   */
+  int32_t hidden_width;   /* multiple of 32, 32..256                                                 */
+  int32_t n_hidden;       /* hidden layers, 1..4                                                      */
+  int32_t n_textures;     /* 1..NTBC_MAX_TEXTURES                                                    */
+  int32_t formats[NTBC_MAX_TEXTURES]; /* NTBC_BC1 or NTBC_BC4 per texture, in head order            */
+  int32_t blocks_w;       /* block grid = texture size / 4                                           */
+  int32_t blocks_h;
+} ntbc_model_desc;
+
+/* Model parameters for inference (host struct of device pointers). */
+typedef struct {
+  const void* grid;         /* FP32: float[V][F]; U8: uint8[V][F]                                   */
+  const float* grid_scale;  /* U8 only: [n_levels] scale_l                                           */
+  const int32_t* grid_zero; /* U8 only: [n_levels] zero point z_l in 0..255                          */
+  const float* weights;     /* FP32 canonical flat layout                                            */
+  const float* fp8_scales;  /* FP8 only: [n_layers][2] = (s_x, s_w) per layer: the layer input is
+                               rounded to E4M3 as x/s_x, the weight as W*(1/s_w)                      */
+  int32_t flags;            /* NTBC_REUSE_PACKED: the workspace already holds the packed weights of
+                               these same weights and precision from an earlier call; skip packing */
+} ntbc_params;
+
+#define NTBC_REUSE_PACKED 1
+
+/* Message describing the last error returned on the calling host thread ("" if none).  The string
+ * is owned by the library and valid until the next failing call on the same thread. */
+const char* ntbc_last_error(void);
+
+/* ---- sizes -------------------------------------------------------------------------------------- */
+
+/* Number of FP32 values in the canonical weight layout of `d`; head_dim = 6*nBC1 + 2*nBC4 +
+ * 16*(3*nBC1 + nBC4); grid vertex count sum_l res_l^2.  Host only.  Returns NTBC_EINVAL on a bad desc. */
+int ntbc_model_sizes(const ntbc_model_desc* d, int64_t* n_weights, int32_t* head_dim,
+                     int64_t* grid_vertices);
+
+/* Workspace bytes needed by ntbc_infer_blocks (batch = 0), ntbc_forward / ntbc_backward and
+ * ntbc_train_step for `batch` block positions at `precision`.  Host only. */
+int ntbc_workspace_size(const ntbc_model_desc* d, int32_t precision, int64_t batch, size_t* bytes);
+
+/* ---- BC format ---------------------------------------------------------------------------------- */
+
+/* Reference encoder (Sec. 3.2 and Sec. 4.1: the reference blocks that are the training targets;
+ * also the fallback).  The encoding is the project's integer REF-BC1 / REF-BC4 algorithm (two
+ * candidates, exact nearest-code selection, two least-squares refinement steps in exact integer
+ * arithmetic), bit-reproducible.  texels: uint8 texture (3 channels for BC1, 1 for BC4), `row_pitch`
+ * bytes per row.  blocks_out: uint64[(height/4)*(width/4)].  Optional sse_out (may be NULL): int32
+ * per block, integer squared error of the decoded block against the texels. */
+int ntbc_bc_encode_ref(const uint8_t* texels, int32_t width, int32_t height, int32_t row_pitch,
+                       int32_t format, uint64_t* blocks_out, int32_t* sse_out, void* stream);
+
+/* Decoder (Sec. 1 and Sec. 2.1; Eq. palette): BC1 four-colour mode (c0 > c1) and three-colour mode
+ * (c0 <= c1: midpoint rounded half up, code 3 = black), BC4 eight-value (e0 > e1) and six-value mode
+ * (codes 6, 7 = 0, 255).  Endpoints expand 565 -> 888 by bit replication; interpolants are rounded to
+ * the nearest integer.  texels_out: uint8 texture with `row_pitch` bytes per row. */
+int ntbc_bc_decode(const uint64_t* blocks, int32_t width, int32_t height, int32_t format,
+                   uint8_t* texels_out, int32_t row_pitch, void* stream);
+
+/* Per-block integer squared error between decoded `blocks` and `texels` -> sse_out int32[n blocks]. */
+int ntbc_block_sse(const uint64_t* blocks, const uint8_t* texels, int32_t width, int32_t height,
+                   int32_t row_pitch, int32_t format, int32_t* sse_out, void* stream);
+
+/* Per-block judge and fallback (Sec. 4.3: standard BC remains available for what NTBC compresses
+ * badly, applied here per block): out[b] = (sse_ntbc[b] > kappa * sse_ref[b] + delta) ? ref[b] :
+ * ntbc[b]; the number of replaced blocks is added to *n_fallback (device int32).  `out` may alias
+ * `ntbc`. */
+int ntbc_fallback(const uint64_t* ntbc, const uint64_t* ref, const int32_t* sse_ntbc,
+                  const int32_t* sse_ref, int64_t n_blocks, float kappa, float delta, uint64_t* out,
+                  int32_t* n_fallback, void* stream);
+
+/* ---- inference ---------------------------------------------------------------------------------- */
+
+/* NTBC inference (Sec. 3.2, Fig. NTBC inference; Eq. palette, Eq. dist) for block positions
+ * [first_block, first_block + n_blocks): block coordinate -> bilinear lookups in every grid level ->
+ * MLP (`precision`) -> sigmoid heads -> endpoints quantised as floor(y*(2^b-1)+1/2) (b = 5/6/5 or 8)
+ * -> palette of the stored endpoints -> per texel the palette entry nearest to the predicted colour
+ * (ties: smallest weight index) -> packed words.  BC1 endpoints are swapped when c0 < c1; equal
+ * endpoints give all-zero codes.  BC4's mode follows the stored endpoint order.
+ * blocks_out: uint64[n_textures][n_blocks].  heads_out (optional, may be NULL): float
+ * [n_blocks][head_dim] sigmoid outputs.  workspace: >= ntbc_workspace_size(d, precision, 0). */
+int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t precision,
+                      int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTBC_H */

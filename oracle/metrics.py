@@ -7,8 +7,10 @@ Tie classification of a block that differs between an implementation under test 
 block is a quantisation-boundary tie when (1) packing the implementation's own head values with the
 oracle's float32 packer reproduces its word bit for bit, and (2) the oracle's smallest decision margin
 for that block (distance of an endpoint value to its rounding boundary, in y units; gap between the two
-nearest palette distances) is no larger than the head difference |Y_impl - Y_oracle|_inf of the block
-(twice that for the squared-distance gap, whose sensitivity is bounded by 2|dY| per unit distance).
+nearest squared palette distances) is within what the head difference d = |Y_impl - Y_oracle|_inf of
+the block can move it: d for an endpoint; 2*ch*d for the gap of a texel with ch channels, since
+D_a - D_b changes by 2 * sum_c (p_b,c - p_a,c) delta_c under a colour change delta, and palette values
+lie in [0, 1].
 """
 from __future__ import annotations
 
@@ -37,7 +39,8 @@ def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
     lay = ntbc.Layout(formats)
     Y_impl = np.asarray(Y_impl)
     dy = np.abs(Y_impl.astype(np.float64) - Y_oracle).max(axis=1)
-    out = {"differ": 0, "ties": 0, "repack_exact": True, "max_dy": float(dy.max()) if len(dy) else 0.0}
+    out = {"differ": 0, "ties": 0, "repack_exact": True, "max_dy": float(dy.max()) if len(dy) else 0.0,
+           "non_ties": []}
     for t in range(len(lay.formats)):
         repacked = ntbc.pack_texture(Y_impl, lay, t, "f32")
         if not np.array_equal(repacked, words_impl[t]):
@@ -46,10 +49,13 @@ def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
         if not diff.any():
             continue
         _, ep_m, idx_m = ntbc.pack_texture(Y_oracle[diff], lay, t, "f64", return_margin=True)
-        # the squared-distance gap moves by at most ~4|dY| (two distances, each 2|d||dY|, |d| <= 1)
-        tie = (ep_m <= dy[diff] * (1 + 1e-9)) | (idx_m <= 4.0 * dy[diff] * (1 + 1e-9))
+        ch = lay.channels(t)
+        tie = (ep_m <= dy[diff] * (1 + 1e-9)) | (idx_m <= 2.0 * ch * dy[diff] * (1 + 1e-9))
         out["differ"] += int(diff.sum())
         out["ties"] += int(tie.sum())
+        idx = np.nonzero(diff)[0]
+        for i in np.nonzero(~tie)[0][:10]:
+            out["non_ties"].append((t, int(idx[i]), float(dy[idx[i]]), float(ep_m[i]), float(idx_m[i])))
     return out
 
 

@@ -1,0 +1,280 @@
+// Device helpers shared by the inference and training kernels: block-centre grid sampling, bilinear
+// blend, float -> bfloat16 rounding, and the BC packing of one texture of one block position.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ntbc.h"
+
+namespace ntbc {
+namespace dev {
+
+// Grid sampling (paper Sec. 3.1 / Sec. 3.4: grids indexed by the normalised block coordinate).  Block b
+// of a grid of `blocks` blocks samples a level of `res` vertices at p = (b + 1/2) res / blocks - 1/2,
+// clamped to [0, res-1]: p = num / (2 blocks) with num = (2b + 1) res - blocks, so the lower corner
+// i0 = min(floor(p), res-2) is an integer decision and the fraction f = fnum / (2 blocks) is exact
+// whenever 2*blocks is a power of two.
+struct Corner {
+  int i0;
+  float f;
+};
+
+__device__ __forceinline__ Corner corner(int b, int blocks, int res) {
+  const int64_t den = 2 * (int64_t)blocks;
+  const int64_t num = (int64_t)(2 * b + 1) * res - blocks;
+  Corner c;
+  if (num <= 0) {
+    c.i0 = 0;
+    c.f = 0.0f;
+  } else if (num >= (int64_t)(res - 1) * den) {
+    c.i0 = res - 2;
+    c.f = 1.0f;
+  } else {
+    c.i0 = (int)(num / den);
+    c.f = (float)(num - (int64_t)c.i0 * den) / (float)den;
+  }
+  return c;
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return bf16_bits(lo) | (bf16_bits(hi) << 16);
+}
+
+// Loads FE consecutive features of one grid vertex and returns them as floats (real values).
+template <int FE>
+__device__ __forceinline__ void load_u8(const uint8_t* p, float v[FE]) {
+  if constexpr (FE == 8) {
+    const uint2 w = *reinterpret_cast<const uint2*>(p);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = (float)((w.x >> (8 * m)) & 0xFF);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[4 + m] = (float)((w.y >> (8 * m)) & 0xFF);
+  } else if constexpr (FE == 4) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = (float)((w >> (8 * m)) & 0xFF);
+  } else {
+#pragma unroll
+    for (int m = 0; m < FE; ++m) v[m] = (float)p[m];
+  }
+}
+
+template <int FE>
+__device__ __forceinline__ void load_f32(const float* p, float v[FE]) {
+  if constexpr (FE % 4 == 0) {
+#pragma unroll
+    for (int m = 0; m < FE; m += 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p + m);
+      v[m] = q.x;
+      v[m + 1] = q.y;
+      v[m + 2] = q.z;
+      v[m + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < FE; ++m) v[m] = p[m];
+  }
+}
+
+struct GridView {
+  const uint8_t* u8;     // U8 codes, or
+  const float* f32;      // real values
+  const float* scale;    // per level (U8)
+  const int32_t* zero;   // per level (U8)
+  int n_levels, base_res, n_features, blocks_w, blocks_h;
+  int64_t level_offset[NTBC_MAX_LEVELS + 1];
+};
+
+// Bilinear feature values of features [f0, f0+FE) of `level` at block (bx, by):
+// sum over the four corners of w_c * value_c, value = scale*(q - zero) for U8 grids.
+template <int FE>
+__device__ __forceinline__ void sample(const GridView& g, int level, int f0, int bx, int by, float out[FE]) {
+  const int res = g.base_res << level;
+  const Corner cx = corner(bx, g.blocks_w, res);
+  const Corner cy = corner(by, g.blocks_h, res);
+  const int64_t v00 = g.level_offset[level] + (int64_t)cy.i0 * res + cx.i0;
+  const int64_t F = g.n_features;
+  const float w00 = (1.0f - cx.f) * (1.0f - cy.f), w10 = cx.f * (1.0f - cy.f);
+  const float w01 = (1.0f - cx.f) * cy.f, w11 = cx.f * cy.f;
+  float a[FE], b[FE], c[FE], d[FE];
+  if (g.u8) {
+    load_u8<FE>(g.u8 + v00 * F + f0, a);
+    load_u8<FE>(g.u8 + (v00 + 1) * F + f0, b);
+    load_u8<FE>(g.u8 + (v00 + res) * F + f0, c);
+    load_u8<FE>(g.u8 + (v00 + res + 1) * F + f0, d);
+    const float s = g.scale[level];
+    const float z = (float)g.zero[level];
+#pragma unroll
+    for (int m = 0; m < FE; ++m)
+      out[m] = s * (fmaf(w00, a[m], fmaf(w10, b[m], fmaf(w01, c[m], w11 * d[m]))) - z);
+  } else {
+    load_f32<FE>(g.f32 + v00 * F + f0, a);
+    load_f32<FE>(g.f32 + (v00 + 1) * F + f0, b);
+    load_f32<FE>(g.f32 + (v00 + res) * F + f0, c);
+    load_f32<FE>(g.f32 + (v00 + res + 1) * F + f0, d);
+#pragma unroll
+    for (int m = 0; m < FE; ++m) out[m] = fmaf(w00, a[m], fmaf(w10, b[m], fmaf(w01, c[m], w11 * d[m])));
+  }
+}
+
+// Input features c0 .. c0+NV-1 of the concatenation [level 0 features, level 1 features, ...], zero
+// past in_dim.  NV is 8 (BF16/FP8 operands) or 1 (FP32 operands); n_features is 1, 2, 4, 8 or 16.
+template <int NV>
+__device__ __forceinline__ void features(const GridView& g, int c0, int bx, int by, float v[NV]) {
+  const int in_dim = g.n_levels * g.n_features;
+  if constexpr (NV == 1) {
+    if (c0 < in_dim) {
+      float t[1];
+      sample<1>(g, c0 / g.n_features, c0 % g.n_features, bx, by, t);
+      v[0] = t[0];
+    } else {
+      v[0] = 0.0f;
+    }
+  } else {
+    static_assert(NV == 8, "feature groups of 8");
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = 0.0f;
+    if (c0 >= in_dim) return;
+    switch (g.n_features) {
+      case 16:
+        sample<8>(g, c0 / 16, c0 % 16, bx, by, v);
+        break;
+      case 8:
+        sample<8>(g, c0 / 8, 0, bx, by, v);
+        break;
+      case 4:
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (c0 + 4 * h < in_dim) sample<4>(g, c0 / 4 + h, 0, bx, by, v + 4 * h);
+        break;
+      case 2:
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          if (c0 + 2 * h < in_dim) sample<2>(g, c0 / 2 + h, 0, bx, by, v + 2 * h);
+        break;
+      default:
+#pragma unroll
+        for (int h = 0; h < 8; ++h)
+          if (c0 + h < in_dim) sample<1>(g, c0 + h, 0, bx, by, v + h);
+        break;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Heads -> BC words (paper Sec. 3.2, Eq. palette, Eq. dist).  Decisions are taken in float32 with
+// uncontracted operations: q = floor(y*(2^b-1) + 0.5) clamped; palette entry = code/255; squared
+// distance ((d0*d0 + d1*d1) + d2*d2); first minimum in weight order.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ int quant_bits(float y, float mx) {
+  float t = floorf(__fadd_rn(__fmul_rn(y, mx), 0.5f));
+  t = fminf(fmaxf(t, 0.0f), mx);
+  return (int)t;
+}
+
+__device__ __forceinline__ int expand5d(int v) { return (v << 3) | (v >> 2); }
+__device__ __forceinline__ int expand6d(int v) { return (v << 2) | (v >> 4); }
+
+struct Bc1Pal {
+  uint32_t c0, c1;
+  float pal[4][3];  // weight order
+};
+
+__device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep) {
+  const int r0 = quant_bits(ep[0], 31.0f), g0 = quant_bits(ep[1], 63.0f), b0 = quant_bits(ep[2], 31.0f);
+  const int r1 = quant_bits(ep[3], 31.0f), g1 = quant_bits(ep[4], 63.0f), b1 = quant_bits(ep[5], 31.0f);
+  uint32_t c0 = ((uint32_t)r0 << 11) | ((uint32_t)g0 << 5) | (uint32_t)b0;
+  uint32_t c1 = ((uint32_t)r1 << 11) | ((uint32_t)g1 << 5) | (uint32_t)b1;
+  if (c0 < c1) {
+    const uint32_t t = c0;
+    c0 = c1;
+    c1 = t;
+  }
+  Bc1Pal p;
+  p.c0 = c0;
+  p.c1 = c1;
+  const int a[3] = {expand5d((c0 >> 11) & 31), expand6d((c0 >> 5) & 63), expand5d(c0 & 31)};
+  const int b[3] = {expand5d((c1 >> 11) & 31), expand6d((c1 >> 5) & 63), expand5d(c1 & 31)};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    p.pal[0][c] = (float)a[c] / 255.0f;
+    p.pal[1][c] = (float)((2 * a[c] + b[c] + 1) / 3) / 255.0f;
+    p.pal[2][c] = (float)((a[c] + 2 * b[c] + 1) / 3) / 255.0f;
+    p.pal[3][c] = (float)b[c] / 255.0f;
+  }
+  return p;
+}
+
+// 2-bit stored code of the nearest palette entry to colour (r, g, b).
+__device__ __forceinline__ uint32_t bc1_code(const Bc1Pal& p, float r, float g, float b) {
+  float best = 0.0f;
+  int bn = 0;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const float d0 = __fsub_rn(r, p.pal[n][0]), d1 = __fsub_rn(g, p.pal[n][1]), d2 = __fsub_rn(b, p.pal[n][2]);
+    const float e = __fadd_rn(__fadd_rn(__fmul_rn(d0, d0), __fmul_rn(d1, d1)), __fmul_rn(d2, d2));
+    if (n == 0 || e < best) {
+      best = e;
+      bn = n;
+    }
+  }
+  if (p.c0 == p.c1) bn = 0;
+  return (0x78u >> (2 * bn)) & 3u;  // weight order 0,1,2,3 -> codes 0,2,3,1
+}
+
+struct Bc4Pal {
+  int e0, e1;
+  bool eight;
+  float pal[8];  // weight order
+};
+
+__device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep) {
+  Bc4Pal p;
+  p.e0 = quant_bits(ep[0], 255.0f);
+  p.e1 = quant_bits(ep[1], 255.0f);
+  p.eight = p.e0 > p.e1;
+  int v[8];
+  if (p.eight) {
+    v[0] = p.e0;
+    v[7] = p.e1;
+#pragma unroll
+    for (int j = 1; j <= 6; ++j) v[j] = ((7 - j) * p.e0 + j * p.e1 + 3) / 7;
+  } else {
+    v[0] = 0;
+    v[1] = p.e0;
+    v[6] = p.e1;
+    v[7] = 255;
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) v[1 + j] = ((5 - j) * p.e0 + j * p.e1 + 2) / 5;
+  }
+#pragma unroll
+  for (int n = 0; n < 8; ++n) p.pal[n] = (float)v[n] / 255.0f;
+  return p;
+}
+
+__device__ __forceinline__ uint32_t bc4_code(const Bc4Pal& p, float x) {
+  float best = 0.0f;
+  int bn = 0;
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const float d = __fsub_rn(x, p.pal[n]);
+    const float e = __fmul_rn(d, d);
+    if (n == 0 || e < best) {
+      best = e;
+      bn = n;
+    }
+  }
+  if (p.eight) return bn == 0 ? 0u : (bn == 7 ? 1u : (uint32_t)(bn + 1));
+  return bn == 0 ? 6u : (bn == 1 ? 0u : (bn == 6 ? 1u : (bn == 7 ? 7u : (uint32_t)bn)));
+}
+
+}  // namespace dev
+}  // namespace ntbc

@@ -1,0 +1,548 @@
+// NTBC inference on gfx950 (paper Sec. 3.2, Fig. NTBC inference): block coordinate -> bilinear grid
+// features -> MLP -> sigmoid heads -> quantised endpoints, nearest-palette indices, packed BC words,
+// fused into one kernel per precision.
+//
+// Layout of the MLP on the matrix cores.  Block positions are the N (column) dimension of every
+// product, neurons the M (row) dimension: D[neuron][position] = W[neuron][k] * H[k][position].  A wave
+// owns P positions for the whole network; its activations never leave registers: the accumulator
+// layout of one layer's output tile is reused directly as the B operand of the next layer, and the
+// next layer's weight columns are permuted on the host side of the kernel (k_pack_weights) to match.
+//
+//   BF16 (v_mfma_f32_32x32x16_bf16, P = 32): lane l holds position j = l%32 and row group g = l/32;
+//     accumulator v of output tile t is neuron 32t + 8(v/4) + 4g + v%4.  Values v = 8h..8h+7 of tile
+//     t become the eight B-operand values of K-step s = 2t+h; so K-step s, lane group g, element m
+//     of a hidden layer's input is neuron 32(s/2) + 16(s%2) + 8(m/4) + 4g + m%4.  The first layer's
+//     input (grid features) uses the identity order c = 16s + 8g + m.
+//   FP32 (v_mfma_f32_16x16x4f32, P = 16): lane l holds position j = l%16 and row group g = l/16;
+//     accumulator v of tile t is neuron 16t + 4g + v and becomes K-step s = 4t+v: K-step s, group g
+//     of a hidden layer's input is neuron 16(s/4) + 4g + s%4; first layer c = 4s + g.
+//
+// Weights (A operands) are read from the packed copy in the workspace, each lane's operand being one
+// contiguous 16-byte (BF16) or 4-byte (FP32) load; the copy is made by k_pack_weights on every call.
+#include "common.h"
+#include "device.h"
+
+namespace {
+
+using namespace ntbc;
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxLayers = 5;
+constexpr int kWaves = 2;  // waves per workgroup
+
+struct PackArgs {
+  const float* w;           // canonical FP32 weights
+  int n_layers;
+  int in_dim[kMaxLayers], out_dim[kMaxLayers];
+  int64_t w_off[kMaxLayers], b_off[kMaxLayers];
+  int ksteps[kMaxLayers], otiles[kMaxLayers];
+  int64_t pack_off[kMaxLayers];  // in operand units (uint4 for BF16, float for FP32)
+  int64_t bias_off[kMaxLayers];  // floats
+  int pos_hidden;                // hidden layers use the chained input permutation
+};
+
+struct InferArgs {
+  dev::GridView grid;
+  const void* wpack;            // packed A operands
+  const float* bias;            // padded biases
+  int64_t pack_off[kMaxLayers];
+  int64_t bias_off[kMaxLayers];
+  int ksteps[kMaxLayers], otiles[kMaxLayers];
+  int n_layers;
+  int head_dim, head_stride;
+  int n_textures, formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
+  int endpoint_dim, channels;
+  int64_t first, n;
+  uint64_t* out;                // [n_textures][n]
+  float* heads;                 // optional [n][head_dim]
+};
+
+// ------------------------------------------------------------------------------ weight packing
+// BF16: element (tile t, step s, lane l, m) = W[32t + l%32][col(s, l/32, m)] as bfloat16.
+__device__ __forceinline__ int bf16_col(int layer, int s, int g, int m) {
+  if (layer == 0) return 16 * s + 8 * g + m;
+  return 32 * (s / 2) + 16 * (s % 2) + 8 * (m / 4) + 4 * g + (m % 4);
+}
+
+__device__ __forceinline__ int f32_col(int layer, int s, int g) {
+  if (layer == 0) return 4 * s + g;
+  return 16 * (s / 4) + 4 * g + (s % 4);
+}
+
+__global__ void k_pack_bf16(PackArgs a, uint4* __restrict__ pack, float* __restrict__ bias) {
+  const int layer = blockIdx.y;
+  if (layer >= a.n_layers) return;
+  const int64_t total = (int64_t)a.otiles[layer] * a.ksteps[layer] * 64;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e % 64);
+    const int s = (int)((e / 64) % a.ksteps[layer]);
+    const int t = (int)(e / (64 * (int64_t)a.ksteps[layer]));
+    const int row = 32 * t + (l % 32);
+    float v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int col = bf16_col(layer, s, l / 32, m);
+      v[m] = (row < a.out_dim[layer] && col < a.in_dim[layer])
+                 ? a.w[a.w_off[layer] + (int64_t)row * a.in_dim[layer] + col]
+                 : 0.0f;
+    }
+    uint4 q;
+    q.x = dev::pack_bf16x2(v[0], v[1]);
+    q.y = dev::pack_bf16x2(v[2], v[3]);
+    q.z = dev::pack_bf16x2(v[4], v[5]);
+    q.w = dev::pack_bf16x2(v[6], v[7]);
+    pack[a.pack_off[layer] + e] = q;
+  }
+  const int nb = a.otiles[layer] * 32;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
+    bias[a.bias_off[layer] + i] = i < a.out_dim[layer] ? a.w[a.b_off[layer] + i] : 0.0f;
+}
+
+__global__ void k_pack_f32(PackArgs a, float* __restrict__ pack, float* __restrict__ bias) {
+  const int layer = blockIdx.y;
+  if (layer >= a.n_layers) return;
+  const int64_t total = (int64_t)a.otiles[layer] * a.ksteps[layer] * 64;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e % 64);
+    const int s = (int)((e / 64) % a.ksteps[layer]);
+    const int t = (int)(e / (64 * (int64_t)a.ksteps[layer]));
+    const int row = 16 * t + (l % 16);
+    const int col = f32_col(layer, s, l / 16);
+    pack[a.pack_off[layer] + e] = (row < a.out_dim[layer] && col < a.in_dim[layer])
+                                      ? a.w[a.w_off[layer] + (int64_t)row * a.in_dim[layer] + col]
+                                      : 0.0f;
+  }
+  const int nb = a.otiles[layer] * 16;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
+    bias[a.bias_off[layer] + i] = i < a.out_dim[layer] ? a.w[a.b_off[layer] + i] : 0.0f;
+}
+
+// ------------------------------------------------------------------------------ common epilogue
+// XCD-aware order: consecutive workgroup ids are dispatched round-robin over the 8 XCDs; give each
+// XCD a contiguous run of position tiles so its L2 holds one band of the fine grid levels.
+__device__ __forceinline__ int64_t xcd_tile(int64_t wg, int64_t nwg) {
+  const int64_t per = nwg / 8, extra = nwg % 8;
+  const int64_t x = wg % 8, k = wg / 8;
+  return x * per + (x < extra ? x : extra) + k;
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Packs the blocks of the wave's P positions from the sigmoid heads in LDS (y: [P][head_stride]).
+// Lane layout: position j = lane % P, texel group q = lane / P handles texels q*TPL .. q*TPL+TPL-1.
+template <int P>
+__device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int lane, int64_t pos0) {
+  constexpr int LPP = 64 / P;   // lanes per position
+  constexpr int TPL = 16 / LPP; // texels per lane
+  const int j = lane % P, q = lane / P;
+  const float* yj = y + j * a.head_stride;
+  const int64_t id = pos0 + j;
+  const bool valid = id < a.first + a.n;
+  for (int t = 0; t < a.n_textures; ++t) {
+    const float* ep = yj + a.ep_off[t];
+    const float* col = yj + a.endpoint_dim + a.ch_off[t];
+    uint64_t bits;
+    if (a.formats[t] == NTBC_BC1) {
+      const dev::Bc1Pal p = dev::bc1_from_heads(ep);
+      uint32_t codes = 0;
+#pragma unroll
+      for (int i = 0; i < TPL; ++i) {
+        const int tx = q * TPL + i;
+        const float* c = col + tx * a.channels;
+        codes |= dev::bc1_code(p, c[0], c[1], c[2]) << (2 * tx);
+      }
+#pragma unroll
+      for (int o = P; o < 64; o <<= 1) codes |= __shfl_xor(codes, o);
+      bits = (uint64_t)p.c0 | ((uint64_t)p.c1 << 16) | ((uint64_t)codes << 32);
+    } else {
+      const dev::Bc4Pal p = dev::bc4_from_heads(ep);
+      uint64_t codes = 0;
+#pragma unroll
+      for (int i = 0; i < TPL; ++i) {
+        const int tx = q * TPL + i;
+        codes |= (uint64_t)dev::bc4_code(p, col[tx * a.channels]) << (3 * tx);
+      }
+#pragma unroll
+      for (int o = P; o < 64; o <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)codes, o);
+        const uint32_t hi = __shfl_xor((uint32_t)(codes >> 32), o);
+        codes |= ((uint64_t)hi << 32) | lo;
+      }
+      bits = (uint64_t)p.e0 | ((uint64_t)p.e1 << 8) | (codes << 16);
+    }
+    if (q == 0 && valid) a.out[(int64_t)t * a.n + (id - a.first)] = bits;
+  }
+  if (a.heads) {
+    for (int e = lane; e < P * a.head_dim; e += 64) {
+      const int jj = e / a.head_dim, k = e % a.head_dim;
+      const int64_t idj = pos0 + jj;
+      if (idj < a.first + a.n) a.heads[(idj - a.first) * a.head_dim + k] = y[jj * a.head_stride + k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ BF16 kernel
+template <int HID>
+__global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
+  constexpr int S = HID / 16;  // K-steps of a hidden input
+  constexpr int T = HID / 32;  // output tiles of a hidden layer
+  constexpr int TC = T < 4 ? T : 4;  // output tiles per pass
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 31, g = lane >> 5;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t pos0 = a.first + (tile * kWaves + wave) * 32;
+  const int64_t last = a.first + a.n - 1;
+  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
+
+  uint4 bin[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float v[8];
+    if (s < a.ksteps[0]) {
+      dev::features<8>(a.grid, 16 * s + 8 * g, bx, by, v);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] = 0.0f;
+    }
+    bin[s] = make_uint4(dev::pack_bf16x2(v[0], v[1]), dev::pack_bf16x2(v[2], v[3]),
+                        dev::pack_bf16x2(v[4], v[5]), dev::pack_bf16x2(v[6], v[7]));
+  }
+
+  const uint4* wp = reinterpret_cast<const uint4*>(a.wpack);
+  // hidden layers
+  for (int layer = 0; layer < a.n_layers - 1; ++layer) {
+    const int ks = a.ksteps[layer];
+    const uint4* wl = wp + a.pack_off[layer];
+    const float* bl = a.bias + a.bias_off[layer];
+    uint4 bout[S];
+#pragma unroll
+    for (int t0 = 0; t0 < T; t0 += TC) {
+      f32x16_t acc[TC];
+#pragma unroll
+      for (int u = 0; u < TC; ++u) acc[u] = f32x16_t{};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s < ks) {
+#pragma unroll
+          for (int u = 0; u < TC; ++u) {
+            const uint4 w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
+            acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w),
+                                                             __builtin_bit_cast(bf16x8_t, bin[s]), acc[u], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TC; ++u) {
+        const int t = t0 + u;
+        float r[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int neuron = 32 * t + 8 * (v / 4) + 4 * g + (v % 4);
+          r[v] = fmaxf(acc[u][v] + bl[neuron], 0.0f);
+        }
+        bout[2 * t] = make_uint4(dev::pack_bf16x2(r[0], r[1]), dev::pack_bf16x2(r[2], r[3]),
+                                 dev::pack_bf16x2(r[4], r[5]), dev::pack_bf16x2(r[6], r[7]));
+        bout[2 * t + 1] = make_uint4(dev::pack_bf16x2(r[8], r[9]), dev::pack_bf16x2(r[10], r[11]),
+                                     dev::pack_bf16x2(r[12], r[13]), dev::pack_bf16x2(r[14], r[15]));
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  // head layer: sigmoid outputs into LDS
+  float* y = lds + wave * 32 * a.head_stride;
+  {
+    const int layer = a.n_layers - 1;
+    const int ks = a.ksteps[layer];
+    const uint4* wl = wp + a.pack_off[layer];
+    const float* bl = a.bias + a.bias_off[layer];
+    for (int t0 = 0; t0 < a.otiles[layer]; t0 += 2) {
+      f32x16_t acc[2] = {f32x16_t{}, f32x16_t{}};
+      const int nt = a.otiles[layer] - t0 < 2 ? 1 : 2;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s < ks) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (u < nt) {
+              const uint4 w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
+              acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w),
+                                                               __builtin_bit_cast(bf16x8_t, bin[s]), acc[u], 0, 0, 0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (u < nt) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int neuron = 32 * (t0 + u) + 8 * (v / 4) + 4 * g + (v % 4);
+            if (neuron < a.head_dim) y[j * a.head_stride + neuron] = sigmoid(acc[u][v] + bl[neuron]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  pack_blocks<32>(a, y, lane, pos0);
+}
+
+// ------------------------------------------------------------------------------ FP32 kernel
+template <int HID>
+__global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
+  constexpr int S = HID / 4;   // K-steps (of 4) of a hidden input
+  constexpr int T = HID / 16;  // output tiles of a hidden layer
+  constexpr int TC = T < 4 ? T : 4;
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t pos0 = a.first + (tile * kWaves + wave) * 16;
+  const int64_t last = a.first + a.n - 1;
+  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
+
+  float bin[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float v[1] = {0.0f};
+    if (s < a.ksteps[0]) dev::features<1>(a.grid, 4 * s + g, bx, by, v);
+    bin[s] = v[0];
+  }
+  const float* wp = reinterpret_cast<const float*>(a.wpack);
+  for (int layer = 0; layer < a.n_layers - 1; ++layer) {
+    const int ks = a.ksteps[layer];
+    const float* wl = wp + a.pack_off[layer];
+    const float* bl = a.bias + a.bias_off[layer];
+    float bout[S];
+#pragma unroll
+    for (int t0 = 0; t0 < T; t0 += TC) {
+      f32x4_t acc[TC];
+#pragma unroll
+      for (int u = 0; u < TC; ++u) acc[u] = f32x4_t{};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s < ks) {
+#pragma unroll
+          for (int u = 0; u < TC; ++u) {
+            const float w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
+            acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, bin[s], acc[u], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TC; ++u) {
+        const int t = t0 + u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bout[4 * t + v] = fmaxf(acc[u][v] + bl[16 * t + 4 * g + v], 0.0f);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  float* y = lds + wave * 16 * a.head_stride;
+  {
+    const int layer = a.n_layers - 1;
+    const int ks = a.ksteps[layer];
+    const float* wl = wp + a.pack_off[layer];
+    const float* bl = a.bias + a.bias_off[layer];
+    for (int t0 = 0; t0 < a.otiles[layer]; t0 += 4) {
+      f32x4_t acc[4] = {f32x4_t{}, f32x4_t{}, f32x4_t{}, f32x4_t{}};
+      const int nt = min(4, a.otiles[layer] - t0);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s < ks) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (u < nt) {
+              const float w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
+              acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w, bin[s], acc[u], 0, 0, 0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < nt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int neuron = 16 * (t0 + u) + 4 * g + v;
+            if (neuron < a.head_dim) y[j * a.head_stride + neuron] = sigmoid(acc[u][v] + bl[neuron]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  pack_blocks<16>(a, y, lane, pos0);
+}
+
+// ------------------------------------------------------------------------------ host side
+struct Plan {
+  Shape s;
+  int precision;
+  int hid_inst;       // kernel instance hidden width (>= shape hidden)
+  int rows;           // output-tile rows (32 BF16, 16 FP32)
+  int kstep;          // K per step (16 BF16, 4 FP32)
+  int ksteps[kMaxLayers], otiles[kMaxLayers];
+  int64_t pack_off[kMaxLayers], bias_off[kMaxLayers];
+  int64_t pack_bytes, bias_bytes, total_bytes;
+  int positions_per_wave;
+};
+
+int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
+  int st = make_shape(d, &p->s);
+  if (st != NTBC_OK) return st;
+  if (precision != NTBC_FP32 && precision != NTBC_BF16)
+    return fail(precision == NTBC_FP8_E4M3 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
+                "precision %d not available for inference", precision);
+  if (p->s.n_layers > kMaxLayers) return fail(NTBC_EUNSUPPORTED, "at most %d layers", kMaxLayers);
+  p->precision = precision;
+  const int h = p->s.hidden;
+  p->hid_inst = h <= 64 ? 64 : (h <= 128 ? 128 : 256);
+  if (p->s.in_dim > p->hid_inst) return fail(NTBC_EUNSUPPORTED, "in_dim %d > kernel width %d", p->s.in_dim, p->hid_inst);
+  const bool bf = precision == NTBC_BF16;
+  p->rows = bf ? 32 : 16;
+  p->kstep = bf ? 16 : 4;
+  p->positions_per_wave = bf ? 32 : 16;
+  const int64_t unit = bf ? 16 : 4;  // bytes per lane operand
+  int64_t off = 0, boff = 0;
+  for (int k = 0; k < p->s.n_layers; ++k) {
+    const int in = k == 0 ? p->s.in_dim : p->hid_inst;
+    const int out = k == p->s.n_layers - 1 ? p->s.head_dim : p->hid_inst;
+    p->ksteps[k] = (int)ceil_div(in, p->kstep);
+    p->otiles[k] = (int)ceil_div(out, p->rows);
+    p->pack_off[k] = off;
+    off += (int64_t)p->otiles[k] * p->ksteps[k] * 64;
+    p->bias_off[k] = boff;
+    boff += (int64_t)p->otiles[k] * p->rows;
+  }
+  p->pack_bytes = off * unit;
+  p->bias_bytes = boff * 4;
+  p->total_bytes = ((p->pack_bytes + 255) / 256) * 256 + p->bias_bytes;
+  return NTBC_OK;
+}
+
+}  // namespace
+
+extern "C" int ntbc_workspace_size(const ntbc_model_desc* d, int32_t precision, int64_t batch, size_t* bytes) {
+  NTBC_REQUIRE(bytes != nullptr, "bytes is NULL");
+  NTBC_REQUIRE(batch >= 0, "batch %lld < 0", (long long)batch);
+  Plan p;
+  int st = make_plan(d, precision, &p);
+  if (st != NTBC_OK) return st;
+  *bytes = (size_t)p.total_bytes;
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* prm, int32_t precision,
+                                 int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  Plan p;
+  int st = make_plan(d, precision, &p);
+  if (st != NTBC_OK) return st;
+  const Shape& s = p.s;
+  NTBC_REQUIRE(prm != nullptr && prm->grid != nullptr && prm->weights != nullptr, "params, grid or weights is NULL");
+  if (d->grid_dtype == NTBC_GRID_U8)
+    NTBC_REQUIRE(prm->grid_scale != nullptr && prm->grid_zero != nullptr, "U8 grid needs grid_scale and grid_zero");
+  NTBC_REQUIRE(first_block >= 0 && n_blocks >= 0 && first_block + n_blocks <= s.n_positions,
+               "block range [%lld, %lld) outside 0..%lld", (long long)first_block,
+               (long long)(first_block + n_blocks), (long long)s.n_positions);
+  if (n_blocks == 0) return NTBC_OK;
+  NTBC_REQUIRE(blocks_out != nullptr, "blocks_out is NULL");
+  if (workspace == nullptr || workspace_bytes < (size_t)p.total_bytes)
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)p.total_bytes);
+  hipStream_t strm = as_stream(stream);
+
+  char* ws = static_cast<char*>(workspace);
+  void* wpack = ws;
+  float* bias = reinterpret_cast<float*>(ws + ((p.pack_bytes + 255) / 256) * 256);
+
+  PackArgs pa{};
+  pa.w = prm->weights;
+  pa.n_layers = s.n_layers;
+  for (int k = 0; k < s.n_layers; ++k) {
+    pa.in_dim[k] = s.layer_in[k];
+    pa.out_dim[k] = s.layer_out[k];
+    pa.w_off[k] = s.w_off[k];
+    pa.b_off[k] = s.b_off[k];
+    pa.ksteps[k] = p.ksteps[k];
+    pa.otiles[k] = p.otiles[k];
+    pa.pack_off[k] = p.pack_off[k];
+    pa.bias_off[k] = p.bias_off[k];
+  }
+  if (!(prm->flags & NTBC_REUSE_PACKED)) {
+    const dim3 pgrid(64, s.n_layers);
+    if (precision == NTBC_BF16)
+      hipLaunchKernelGGL(k_pack_bf16, pgrid, dim3(256), 0, strm, pa, static_cast<uint4*>(wpack), bias);
+    else
+      hipLaunchKernelGGL(k_pack_f32, pgrid, dim3(256), 0, strm, pa, static_cast<float*>(wpack), bias);
+    st = check_launch("ntbc_infer_blocks: weight packing");
+    if (st != NTBC_OK) return st;
+  }
+
+  InferArgs a{};
+  a.grid.u8 = d->grid_dtype == NTBC_GRID_U8 ? static_cast<const uint8_t*>(prm->grid) : nullptr;
+  a.grid.f32 = d->grid_dtype == NTBC_GRID_F32 ? static_cast<const float*>(prm->grid) : nullptr;
+  a.grid.scale = prm->grid_scale;
+  a.grid.zero = prm->grid_zero;
+  a.grid.n_levels = s.n_levels;
+  a.grid.base_res = s.base_res;
+  a.grid.n_features = s.n_features;
+  a.grid.blocks_w = s.blocks_w;
+  a.grid.blocks_h = s.blocks_h;
+  for (int l = 0; l <= s.n_levels; ++l) a.grid.level_offset[l] = s.level_offset[l];
+  a.wpack = wpack;
+  a.bias = bias;
+  for (int k = 0; k < s.n_layers; ++k) {
+    a.pack_off[k] = p.pack_off[k];
+    a.bias_off[k] = p.bias_off[k];
+    a.ksteps[k] = p.ksteps[k];
+    a.otiles[k] = p.otiles[k];
+  }
+  a.n_layers = s.n_layers;
+  a.head_dim = s.head_dim;
+  a.head_stride = s.head_dim | 1;
+  a.n_textures = s.n_textures;
+  for (int t = 0; t < s.n_textures; ++t) {
+    a.formats[t] = s.formats[t];
+    a.ep_off[t] = s.ep_off[t];
+    a.ch_off[t] = s.ch_off[t];
+  }
+  a.endpoint_dim = s.endpoint_dim;
+  a.channels = s.channels;
+  a.first = first_block;
+  a.n = n_blocks;
+  a.out = blocks_out;
+  a.heads = heads_out;
+
+  const int ppw = p.positions_per_wave;
+  const int64_t nwg = ceil_div(n_blocks, (int64_t)ppw * kWaves);
+  const size_t lds = (size_t)kWaves * ppw * a.head_stride * sizeof(float);
+  const dim3 grid((unsigned)nwg), block(64 * kWaves);
+  NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
+  if (lds > 64 * 1024) {
+    const void* fn = precision == NTBC_BF16
+                         ? (p.hid_inst == 64 ? (const void*)k_infer_bf16<64>
+                                             : (p.hid_inst == 128 ? (const void*)k_infer_bf16<128> : (const void*)k_infer_bf16<256>))
+                         : (p.hid_inst == 64 ? (const void*)k_infer_f32<64>
+                                             : (p.hid_inst == 128 ? (const void*)k_infer_f32<128> : (const void*)k_infer_f32<256>));
+    NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  if (precision == NTBC_BF16) {
+    if (p.hid_inst == 64) hipLaunchKernelGGL(k_infer_bf16<64>, grid, block, lds, strm, a);
+    else if (p.hid_inst == 128) hipLaunchKernelGGL(k_infer_bf16<128>, grid, block, lds, strm, a);
+    else hipLaunchKernelGGL(k_infer_bf16<256>, grid, block, lds, strm, a);
+  } else {
+    if (p.hid_inst == 64) hipLaunchKernelGGL(k_infer_f32<64>, grid, block, lds, strm, a);
+    else if (p.hid_inst == 128) hipLaunchKernelGGL(k_infer_f32<128>, grid, block, lds, strm, a);
+    else hipLaunchKernelGGL(k_infer_f32<256>, grid, block, lds, strm, a);
+  }
+  return check_launch("ntbc_infer_blocks");
+}

@@ -1,0 +1,231 @@
+"""ctypes binding of libntbc (argument marshalling only; every step runs in the HIP library).
+
+Tensors are PyTorch CUDA (HIP) tensors; they provide device memory and the current stream.  Block
+words are stored in int64 tensors (bit patterns of the uint64 little-endian BC words).  If the shared
+library is not built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libntbc.so")
+
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOWORKSPACE = 0, -1, -2, -3, -5
+BC1, BC4 = 1, 4
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+GRID_F32, GRID_U8 = 0, 1
+MAX_TEXTURES = 8
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+
+
+class NtbcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libntbc status {status}: {msg}")
+        self.status = status
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("base_res", ctypes.c_int32),
+                ("n_features", ctypes.c_int32), ("grid_dtype", ctypes.c_int32),
+                ("hidden_width", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_textures", ctypes.c_int32), ("formats", ctypes.c_int32 * MAX_TEXTURES),
+                ("blocks_w", ctypes.c_int32), ("blocks_h", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("grid_scale", ctypes.c_void_p),
+                ("grid_zero", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("fp8_scales", ctypes.c_void_p), ("flags", ctypes.c_int32)]
+
+REUSE_PACKED = 1
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_F = ctypes.c_float
+
+_SIGNATURES = {
+    "ntbc_last_error": ([], ctypes.c_char_p),
+    "ntbc_model_sizes": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                          ctypes.POINTER(_I64)], ctypes.c_int),
+    "ntbc_workspace_size": ([ctypes.POINTER(ModelDesc), _I32, _I64, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ntbc_bc_encode_ref": ([_P, _I32, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "ntbc_bc_decode": ([_P, _I32, _I32, _I32, _P, _I32, _P], ctypes.c_int),
+    "ntbc_block_sse": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
+    "ntbc_fallback": ([_P, _P, _P, _P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
+    "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
+                           _P, _SZ, _P], ctypes.c_int),
+}
+
+
+def lib():
+    """Loads libntbc.so (built in-tree by paper_2407_09543_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2407_09543_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(handle, name, None)
+            if fn is None:
+                continue
+            fn.argtypes = args
+            fn.restype = res
+        _lib = handle
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise NtbcError(status, lib().ntbc_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libntbc takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libntbc takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_desc(n_levels, base_res, n_features, grid_u8, hidden, n_hidden, formats: Sequence[int],
+              blocks_w, blocks_h) -> ModelDesc:
+    d = ModelDesc()
+    d.n_levels, d.base_res, d.n_features = n_levels, base_res, n_features
+    d.grid_dtype = GRID_U8 if grid_u8 else GRID_F32
+    d.hidden_width, d.n_hidden = hidden, n_hidden
+    d.n_textures = len(formats)
+    for i, f in enumerate(formats):
+        d.formats[i] = int(f)
+    d.blocks_w, d.blocks_h = blocks_w, blocks_h
+    return d
+
+
+def desc_from_config(cfg) -> ModelDesc:
+    """ModelDesc of a config object with the fields of synth.ModelConfig."""
+    return make_desc(cfg.n_levels, cfg.base_res, cfg.n_features, cfg.grid_u8, cfg.hidden, cfg.n_hidden,
+                     cfg.formats, cfg.blocks_w, cfg.blocks_h)
+
+
+def model_sizes(desc: ModelDesc):
+    nw, hd, gv = _I64(), _I32(), _I64()
+    _check(lib().ntbc_model_sizes(ctypes.byref(desc), ctypes.byref(nw), ctypes.byref(hd), ctypes.byref(gv)))
+    return nw.value, hd.value, gv.value
+
+
+def workspace_size(desc: ModelDesc, precision: int, batch: int = 0) -> int:
+    out = _SZ()
+    _check(lib().ntbc_workspace_size(ctypes.byref(desc), precision, batch, ctypes.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------------------------- BC
+def _tex_dims(texels: torch.Tensor, fmt: int):
+    ch = 3 if fmt == BC1 else 1
+    if fmt == BC1 and (texels.dim() != 3 or texels.shape[2] != 3):
+        raise ValueError("BC1 textures are [H, W, 3] uint8")
+    if fmt == BC4 and texels.dim() not in (2, 3):
+        raise ValueError("BC4 textures are [H, W] uint8")
+    if texels.dtype != torch.uint8:
+        raise ValueError("textures are uint8")
+    h, w = texels.shape[0], texels.shape[1]
+    return w, h, w * ch
+
+
+def encode_ref(texels: torch.Tensor, fmt: int, return_sse: bool = False):
+    """Reference BC encoding of a device texture -> int64 tensor of BC words [H/4 * W/4]."""
+    w, h, pitch = _tex_dims(texels, fmt)
+    out = torch.empty((h // 4) * (w // 4), dtype=torch.int64, device=texels.device)
+    sse = torch.empty(out.shape, dtype=torch.int32, device=texels.device) if return_sse else None
+    _check(lib().ntbc_bc_encode_ref(_ptr(texels), w, h, pitch, fmt, _ptr(out), _ptr(sse), _stream()))
+    return (out, sse) if return_sse else out
+
+
+def decode(blocks: torch.Tensor, width: int, height: int, fmt: int) -> torch.Tensor:
+    ch = 3 if fmt == BC1 else 1
+    shape = (height, width, 3) if fmt == BC1 else (height, width)
+    out = torch.empty(shape, dtype=torch.uint8, device=blocks.device)
+    _check(lib().ntbc_bc_decode(_ptr(blocks), width, height, fmt, _ptr(out), width * ch, _stream()))
+    return out
+
+
+def block_sse(blocks: torch.Tensor, texels: torch.Tensor, fmt: int) -> torch.Tensor:
+    w, h, pitch = _tex_dims(texels, fmt)
+    out = torch.empty(blocks.shape, dtype=torch.int32, device=blocks.device)
+    _check(lib().ntbc_block_sse(_ptr(blocks), _ptr(texels), w, h, pitch, fmt, _ptr(out), _stream()))
+    return out
+
+
+def fallback(ntbc_words, ref_words, sse_ntbc, sse_ref, kappa: float, delta: float):
+    """Per-block judge: (words, replaced count as a device int32 tensor)."""
+    out = torch.empty_like(ntbc_words)
+    count = torch.zeros(1, dtype=torch.int32, device=ntbc_words.device)
+    _check(lib().ntbc_fallback(_ptr(ntbc_words), _ptr(ref_words), _ptr(sse_ntbc), _ptr(sse_ref),
+                               ntbc_words.numel(), kappa, delta, _ptr(out), _ptr(count), _stream()))
+    return out, count
+
+
+# -------------------------------------------------------------------------------------- inference
+class Model:
+    """Device-resident inference parameters of one material (the caller keeps the tensors alive)."""
+
+    def __init__(self, desc: ModelDesc, weights: torch.Tensor, grid: torch.Tensor,
+                 grid_scale: Optional[torch.Tensor] = None, grid_zero: Optional[torch.Tensor] = None,
+                 fp8_scales: Optional[torch.Tensor] = None):
+        self.desc = desc
+        self.weights = weights.contiguous()
+        self.grid = grid.contiguous()
+        self.grid_scale = grid_scale
+        self.grid_zero = grid_zero
+        self.fp8_scales = fp8_scales
+        self.n_weights, self.head_dim, self.grid_vertices = model_sizes(desc)
+        self._ws = {}
+
+    def params(self) -> Params:
+        p = Params()
+        p.grid = self.grid.data_ptr()
+        p.grid_scale = self.grid_scale.data_ptr() if self.grid_scale is not None else None
+        p.grid_zero = self.grid_zero.data_ptr() if self.grid_zero is not None else None
+        p.weights = self.weights.data_ptr()
+        p.fp8_scales = self.fp8_scales.data_ptr() if self.fp8_scales is not None else None
+        return p
+
+    def workspace(self, precision: int) -> torch.Tensor:
+        if precision not in self._ws:
+            n = workspace_size(self.desc, precision, 0)
+            self._ws[precision] = torch.empty(max(n, 1), dtype=torch.uint8, device=self.weights.device)
+        return self._ws[precision]
+
+    def infer(self, precision: int = BF16, first_block: int = 0, n_blocks: Optional[int] = None,
+              heads: bool = False, out: Optional[torch.Tensor] = None, reuse_packed: bool = False):
+        """Packed blocks int64 [n_textures, n_blocks] (and heads float32 [n_blocks, head_dim]).
+
+        reuse_packed: skip re-packing the weights (valid only after an earlier call at the same
+        precision with unchanged weights)."""
+        if n_blocks is None:
+            n_blocks = self.desc.blocks_w * self.desc.blocks_h - first_block
+        dev = self.weights.device
+        if out is None:
+            out = torch.empty((self.desc.n_textures, n_blocks), dtype=torch.int64, device=dev)
+        h = torch.empty((n_blocks, self.head_dim), dtype=torch.float32, device=dev) if heads else None
+        ws = self.workspace(precision)
+        p = self.params()
+        p.flags = REUSE_PACKED if reuse_packed else 0
+        _check(lib().ntbc_infer_blocks(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
+                                       n_blocks, _ptr(out), _ptr(h), _ptr(ws), ws.numel(), _stream()))
+        return (out, h) if heads else out

@@ -1,0 +1,66 @@
+"""Seeded model/material cases shared by the GPU tests (inputs only; expected values come from the
+oracle)."""
+import numpy as np
+
+from oracle import grid as G
+from oracle import ntbc as ON
+from paper_2407_09543_amd import synth
+
+
+def model_inputs(cfg, seed, u8=None, grid_scale=0.7):
+    """(flat fp32 weights, grid arrays) with O(1) features so outputs spread over (0, 1)."""
+    layers = synth.init_weights(cfg, seed)
+    rng = np.random.default_rng(seed + 101)
+    layers = [(w, (0.3 * rng.standard_normal(len(b))).astype(np.float32)) for w, b in layers]
+    flat = synth.flatten_weights(layers)
+    use_u8 = cfg.grid_u8 if u8 is None else u8
+    if use_u8:
+        codes, scale, zero = synth.random_u8_grid(cfg, seed)
+        # rescale so features are O(1): s * (q - z) with q - z ~ +-128
+        scale = (np.full(cfg.n_levels, grid_scale / 128.0) * (1 + 0.1 * np.arange(cfg.n_levels))).astype(np.float32)
+        zero = np.full(cfg.n_levels, 128, dtype=np.int32) - np.arange(cfg.n_levels, dtype=np.int32)
+        return flat, layers, dict(codes=codes, scale=scale, zero=zero)
+    grid = synth.random_grid(cfg, seed, grid_scale)
+    return flat, layers, dict(grid=grid)
+
+
+def oracle_levels(cfg, g):
+    if "codes" in g:
+        return ON.grid_levels(cfg, codes=g["codes"], scales=g["scale"], zeros=g["zero"])
+    return ON.grid_levels(cfg, grid=g["grid"])
+
+
+def exact_model_inputs(cfg, seed):
+    """Parameters on which float32 accumulation is exact (so the BF16 and FP32 paths can only differ
+    from the oracle in the final sigmoid): grid values k/8 on a float grid; every weight row has four
+    nonzero entries +-1 (hidden layers) or +-2^-6 (head); biases k/8.  The block grid must be a power
+    of two so the bilinear fractions are dyadic.  Returns (flat, layers, grid dict)."""
+    rng = np.random.default_rng(seed + 555)
+    layers = []
+    dims = cfg.layer_dims()
+    for k, (fan_in, fan_out) in enumerate(dims):
+        w = np.zeros((fan_out, fan_in), dtype=np.float32)
+        mag = 1.0 if k < len(dims) - 1 else 2.0 ** -6
+        for r in range(fan_out):
+            cols = rng.choice(fan_in, min(4, fan_in), replace=False)
+            w[r, cols] = mag * rng.choice([-1.0, 1.0], len(cols))
+        b = (rng.integers(-8, 9, fan_out) / 8.0).astype(np.float32)
+        layers.append((w, b))
+    grid = (rng.integers(-8, 9, (cfg.grid_vertices, cfg.n_features)) / 8.0).astype(np.float32)
+    return synth.flatten_weights(layers), layers, dict(grid=grid)
+
+
+def assert_exact_in_float32(cfg, layers, g, ids):
+    """Host check of the construction: the float64 forward equals a float32 forward at every layer."""
+    from oracle import grid as OG, lowp
+    lv = oracle_levels(cfg, g)
+    ids = np.asarray(ids)
+    x = OG.features(lv, ids % cfg.blocks_w, ids // cfg.blocks_w, cfg.blocks_w, cfg.blocks_h)
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+    h = x
+    for k, (w, b) in enumerate(layers):
+        hb = lowp.round_bf16(h)
+        z = hb @ w.astype(np.float64).T + b
+        assert np.abs(z).max() < 2.0 ** 12
+        assert np.array_equal(z, z.astype(np.float32).astype(np.float64))
+        h = np.maximum(z, 0.0)

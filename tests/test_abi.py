@@ -1,0 +1,67 @@
+"""The C-ABI library loads, exports every function the header declares, and validates arguments on
+the host (no GPU needed: nothing here reaches a HIP call)."""
+import ctypes
+import re
+
+import pytest
+
+from util import ROOT, ensure_built
+from paper_2407_09543_amd import ntbc, synth
+
+
+def _declared():
+    text = open(f"{ROOT}/include/ntbc.h").read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ntbc_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    ensure_built()
+    handle = ctypes.CDLL(ntbc.LIB_PATH)
+    names = _declared()
+    assert "ntbc_infer_blocks" in names and "ntbc_bc_encode_ref" in names
+    missing = [n for n in names if not hasattr(handle, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    assert set(_declared()) <= set(ntbc._SIGNATURES)
+
+
+@pytest.mark.parametrize("cfg", [synth.config_small(), synth.config_mid(), synth.config_paper_scale()])
+def test_model_sizes(cfg):
+    ensure_built()
+    nw, hd, gv = ntbc.model_sizes(ntbc.desc_from_config(cfg))
+    assert nw == cfg.n_weights and hd == cfg.head_dim and gv == cfg.grid_vertices
+
+
+def test_paper_scale_sizes_closed_form():
+    cfg = synth.config_paper_scale()
+    assert cfg.head_dim == 2 * 6 + 3 * 2 + 16 * (2 * 3 + 3) == 162
+    assert cfg.grid_vertices == sum((8 << l) ** 2 for l in range(8)) == 1398080
+    assert cfg.n_weights == 64 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 162 + 162 == 189858
+
+
+def test_invalid_arguments_rejected_on_host():
+    ensure_built()
+    lib = ntbc.lib()
+    # NULL texture, bad format, width not a multiple of 4, pitch too small
+    assert lib.ntbc_bc_encode_ref(None, 8, 8, 24, 1, None, None, None) == ntbc.EINVAL
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.ntbc_bc_encode_ref(dummy, 8, 8, 24, 2, dummy, None, None) == ntbc.EINVAL
+    assert lib.ntbc_bc_encode_ref(dummy, 10, 8, 30, 1, dummy, None, None) == ntbc.EINVAL
+    assert lib.ntbc_bc_encode_ref(dummy, 8, 8, 20, 1, dummy, None, None) == ntbc.EINVAL
+    assert b"row_pitch" in lib.ntbc_last_error()
+    assert lib.ntbc_bc_decode(dummy, 8, 0, 4, dummy, 8, None) == ntbc.EINVAL
+    bad = ntbc.desc_from_config(synth.config_small())
+    bad.n_features = 3
+    with pytest.raises(ntbc.NtbcError):
+        ntbc.model_sizes(bad)
+    bad = ntbc.desc_from_config(synth.config_small())
+    bad.formats[1] = 7
+    with pytest.raises(ntbc.NtbcError):
+        ntbc.model_sizes(bad)
+    bad = ntbc.desc_from_config(synth.config_small())
+    bad.hidden_width = 48
+    with pytest.raises(ntbc.NtbcError):
+        ntbc.model_sizes(bad)
