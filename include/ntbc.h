@@ -150,6 +150,91 @@ int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t pr
                       int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- training ----------------------------------------------------------------------------------- */
+
+/* Training state (host struct of device pointers, caller-owned).  Master parameters in FP32; Adam
+ * moments of the same shapes (zero before the first step); gradient buffers overwritten by each step. */
+typedef struct {
+  float* grid;        /* [V][F] master grid                                                            */
+  float* weights;     /* [n_weights] master weights, canonical layout                                  */
+  float* m_grid;      /* Adam first moments                                                            */
+  float* v_grid;      /* Adam second moments                                                           */
+  float* m_weights;
+  float* v_weights;
+  float* d_grid;      /* gradient of the last step                                                     */
+  float* d_weights;
+} ntbc_train_state;
+
+/* Training targets (host struct of device pointers): the reference blocks and the textures. */
+typedef struct {
+  const uint64_t* ref_blocks;                 /* [n_textures][n_positions] reference BC words          */
+  const uint8_t* texels[NTBC_MAX_TEXTURES];   /* per texture, row-major, tightly packed (pitch =
+                                                 4*blocks_w*channels)                                   */
+} ntbc_targets;
+
+/* Hyper-parameters (host struct).  Paper Sec. 3.4: Adam beta1 0.9, beta2 0.999, eps 1e-15; learning
+ * rates 0.01 (grid) and 0.005 (MLP); 10 warm-up steps then cosine annealing to 0 at total_steps;
+ * T = 0.01.  Sec. 3.3: qat = 1 fake-quantises every grid level to 8 bits with its current min/max. */
+typedef struct {
+  float lr_grid, lr_mlp;
+  float beta1, beta2, eps;
+  float temperature;
+  int32_t warmup, total_steps;
+  int32_t qat;
+  int32_t precision;        /* NTBC_FP32 */
+  float loss_weights[4];    /* weights of L_e, L_c, L_cd(endpoint), L_cd(colour) in the gradient; 1 = paper */
+} ntbc_hparams;
+
+/* Block ids passed to the training entry points are clamped into [0, blocks_w*blocks_h). */
+
+/* Forward pass for a batch (paper Sec. 3.2, Fig. NTBC training, network part): the sigmoid heads of
+ * block positions ids[0..n) from the FP32 master grid (fake-quantised per level when qat = 1: Sec. 3.3,
+ * Eq. quantizer with s, z from the level's min/max) and FP32 weights.  heads_out: float[n][head_dim].
+ * Nothing is kept for the backward pass; ntbc_backward recomputes the activations. */
+int ntbc_forward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
+                 int32_t precision, const int32_t* ids, int32_t n, float* heads_out, void* workspace,
+                 size_t workspace_bytes, void* stream);
+
+/* Backward pass: given dL/d(heads) for the same batch, recomputes the forward activations and ADDS the
+ * gradients to d_grid ([V][F], scatter through the bilinear weights; with qat = 1 the quantiser's
+ * straight-through pass-through: 1 inside the level's range, 0 where clamped) and d_weights (canonical
+ * layout).  The caller zeroes them first. */
+int ntbc_backward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
+                  int32_t precision, const int32_t* ids, int32_t n, const float* d_heads, float* d_grid,
+                  float* d_weights, void* workspace, size_t workspace_bytes, void* stream);
+
+/* NTBC loss (Sec. 3.2, Eqs. lossNTBC; App. A): for heads of block positions ids, losses_out[0..3] =
+ * L_e, L_c, L_cd(endpoint branch), L_cd(colour branch), each a mean over its elements; d_heads_out =
+ * dL/d(heads) of loss_weights . losses, with the argmax of the decoded-colour terms differentiated as
+ * the softmax(d/T) expectation of the reference palette (straight-through).  losses_out (device
+ * float[5]) is overwritten; losses_out[4] = 1 if a head or gradient was not finite. */
+int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float* heads, const int32_t* ids,
+                   int32_t n, float temperature, const float* loss_weights, float* losses_out,
+                   float* d_heads_out, void* stream);
+
+/* One training iteration: forward, loss, backward, then dense Adam on grid and weights with the
+ * learning rates of step `step` (0-based) of the schedule.  losses_out (device float[5]) receives the
+ * four losses and the skip flag: when a non-finite value is seen the parameters and moments are left
+ * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions. */
+int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const ntbc_targets* t,
+                    const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
+                    float* losses_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Training batch `step`: `batch` block-position ids drawn uniformly with replacement from
+ * [0, n_positions) (the paper leaves the sampling unspecified).  Generator: SplitMix64 (Steele, Lea &
+ * Flood 2014).  The stream key is k = mix(mix(mix(0, seed), 0xBA7C4), step) with
+ * mix(h, p) = splitmix64_output((h ^ p) + 0x9E3779B97F4A7C15); draw i (0-based) is
+ * z = splitmix64_output(k + (i+1) * 0x9E3779B97F4A7C15) and id = ((z >> 32) * n_positions) >> 32.
+ * ids_out: device int32[batch]. */
+int ntbc_batch_ids(uint64_t seed, int64_t step, int32_t batch, int64_t n_positions, int32_t* ids_out,
+                   void* stream);
+
+/* 8-bit grid for inference (Sec. 3.3): per level l, s_l = (max-min)/255 and z_l = clamp(rne(-min/s_l),
+ * 0, 255) (s = 1, z = 0 for a flat level), codes q = clamp(rne(g/s_l) + z_l, 0, 255); all in float32.
+ * codes: uint8[V][F]; scale: float[n_levels]; zero: int32[n_levels]. */
+int ntbc_quantize_grid(const ntbc_model_desc* d, const float* grid, uint8_t* codes, float* scale,
+                       int32_t* zero, void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

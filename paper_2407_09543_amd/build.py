@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libntbc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "codec.hip", "infer.hip"]
+SOURCES = ["api.cpp", "codec.hip", "infer.hip", "train.hip"]
 
 # Packed FP32 instructions are disabled (-packed-fp32-ops); contraction of a*b+c into FMA is disabled so
 # that the integer decisions taken in float32 (endpoint rounding, nearest palette entry) are the exact

@@ -50,4 +50,7 @@ int make_shape(const ntbc_model_desc* d, Shape* s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Workspace bytes of the training / forward / backward entry points for `batch` positions.
+int64_t train_workspace_bytes(const Shape& s, int64_t batch);
+
 }  // namespace ntbc

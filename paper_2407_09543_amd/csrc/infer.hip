@@ -434,6 +434,16 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
 extern "C" int ntbc_workspace_size(const ntbc_model_desc* d, int32_t precision, int64_t batch, size_t* bytes) {
   NTBC_REQUIRE(bytes != nullptr, "bytes is NULL");
   NTBC_REQUIRE(batch >= 0, "batch %lld < 0", (long long)batch);
+  if (batch > 0) {
+    Shape s;
+    int st = make_shape(d, &s);
+    if (st != NTBC_OK) return st;
+    int64_t need = train_workspace_bytes(s, batch);
+    Plan p;
+    if (make_plan(d, precision, &p) == NTBC_OK && p.total_bytes > need) need = p.total_bytes;
+    *bytes = (size_t)need;
+    return NTBC_OK;
+  }
   Plan p;
   int st = make_plan(d, precision, &p);
   if (st != NTBC_OK) return st;

@@ -1,0 +1,963 @@
+// NTBC training on gfx950 (paper Sec. 3.2 training procedure, Sec. 3.3 grid QAT, Sec. 3.4 optimiser,
+// App. A straight-through estimator).  One step for a batch of block positions:
+//
+//   k_level_minmax / k_qat_params   per-level min/max of the FP32 master grid -> (s_l, z_l) (QAT on)
+//   k_features                      bilinear features of the (fake-quantised) grid -> X [B][in]
+//   k_gemm (bias+ReLU / sigmoid)    MLP forward, every layer's input kept for the batch
+//   k_loss_grad                     L_e, L_c and both decoded-colour terms, dL/dY with the STE
+//   k_dsigmoid                      dZ_out = dY * Y (1 - Y)
+//   k_gemm (mask / split-K atomic)  dH_k = dZ_k W_k masked by ReLU, dW_k = dZ_k^T H_k, db by k_colsum
+//   k_scatter                       dX through the bilinear weights into d_grid (atomic), QAT
+//                                   pass-through mask
+//   k_adam                          dense bias-corrected Adam, learning rate from the host schedule
+//
+// The autograd entry points (ntbc_forward / ntbc_backward) keep nothing between calls: the backward
+// pass recomputes the forward activations of its batch.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "device.h"
+
+namespace {
+
+using namespace ntbc;
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------------------------------ layout
+struct TrainLayout {
+  // float offsets into the workspace
+  int64_t stats;  // [4][NTBC_MAX_LEVELS]: min (ordered int), max (ordered int), s (float), z (int)
+  int64_t x, h[4], y, dy, da, db;
+  int64_t total;
+};
+
+TrainLayout train_layout(const Shape& s, int64_t batch) {
+  TrainLayout t{};
+  int64_t o = 0;
+  auto take = [&](int64_t n) {
+    const int64_t r = o;
+    o += (n + 63) / 64 * 64;
+    return r;
+  };
+  t.stats = take(4 * NTBC_MAX_LEVELS);
+  t.x = take(batch * s.in_dim);
+  for (int k = 0; k < s.n_hidden; ++k) t.h[k] = take(batch * s.hidden);
+  t.y = take(batch * s.head_dim);
+  t.dy = take(batch * s.head_dim);
+  const int w = s.hidden > s.in_dim ? s.hidden : s.in_dim;
+  t.da = take(batch * w);
+  t.db = take(batch * w);
+  t.total = o;
+  return t;
+}
+
+// ------------------------------------------------------------------------------------------ helpers
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__device__ __forceinline__ int ordered(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float unordered(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
+
+__global__ void k_init_stats(int* __restrict__ stats) {
+  const int l = threadIdx.x;
+  if (l < NTBC_MAX_LEVELS) {
+    stats[l] = 0x7FFFFFFF;
+    stats[NTBC_MAX_LEVELS + l] = (int)0x80000000;
+  }
+}
+
+struct LevelArgs {
+  int n_levels;
+  int64_t begin[NTBC_MAX_LEVELS], count[NTBC_MAX_LEVELS];  // in floats
+};
+
+// Per-level min/max of the master grid: blockIdx.y = level, block-reduced, one atomic per block.
+__global__ void __launch_bounds__(kBlock) k_level_minmax(const float* __restrict__ g, LevelArgs la, int* __restrict__ stats) {
+  const int l = blockIdx.y;
+  if (l >= la.n_levels) return;
+  const int64_t n = la.count[l];
+  const float* p = g + la.begin[l];
+  int mn = 0x7FFFFFFF, mx = (int)0x80000000;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const int o = ordered(p[i]);
+    mn = min(mn, o);
+    mx = max(mx, o);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = min(mn, __shfl_xor(mn, off));
+    mx = max(mx, __shfl_xor(mx, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&stats[l], mn);
+    atomicMax(&stats[NTBC_MAX_LEVELS + l], mx);
+  }
+}
+
+// (s, z) of every level in float32: s = (max-min)/255, z = clamp(rne(-min/s), 0, 255); flat: s=1, z=0.
+__global__ void k_qat_params(int* __restrict__ stats, int n_levels) {
+  const int l = threadIdx.x;
+  if (l >= n_levels) return;
+  const float lo = unordered(stats[l]), hi = unordered(stats[NTBC_MAX_LEVELS + l]);
+  float s = 1.0f, z = 0.0f;
+  if (hi != lo) {
+    s = __fdiv_rn(__fsub_rn(hi, lo), 255.0f);
+    z = fminf(fmaxf(rintf(__fdiv_rn(-lo, s)), 0.0f), 255.0f);
+  }
+  reinterpret_cast<float*>(stats)[2 * NTBC_MAX_LEVELS + l] = s;
+  stats[3 * NTBC_MAX_LEVELS + l] = (int)z;
+}
+
+// Block ids come from the caller; out-of-range ids are clamped into [0, n_positions) so that no input
+// can address outside the grid or the targets.
+__device__ __forceinline__ int clamp_id(int id, int64_t n_positions) {
+  return id < 0 ? 0 : (id >= n_positions ? (int)(n_positions - 1) : id);
+}
+
+// Eq. quantizer Q(w) = s (clamp(rne(w/s) + z, 0, 255) - z) and its pass-through mask.
+__device__ __forceinline__ float fake_quant(float w, float s, int z, bool* inside) {
+  const float t = rintf(__fdiv_rn(w, s)) + (float)z;
+  *inside = t >= 0.0f && t <= 255.0f;
+  const float q = fminf(fmaxf(t, 0.0f), 255.0f);
+  return s * (q - (float)z);
+}
+
+struct FeatArgs {
+  const float* grid;
+  const int* stats;  // null when QAT is off
+  const int32_t* ids;
+  int64_t n;
+  int n_levels, base_res, F, blocks_w, blocks_h;
+  int64_t level_offset[NTBC_MAX_LEVELS + 1];
+  float* x;          // [n][L*F]
+};
+
+// One thread per (position, level): four corners, F features each.
+__global__ void __launch_bounds__(kBlock) k_features(FeatArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.n * a.n_levels) return;
+  const int64_t p = gid / a.n_levels;
+  const int l = (int)(gid % a.n_levels);
+  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int res = a.base_res << l;
+  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+  const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
+  const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
+  const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
+  const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
+  const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
+  float* xo = a.x + p * (int64_t)(a.n_levels * a.F) + l * a.F;
+  for (int f = 0; f < a.F; ++f) {
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float g = a.grid[vtx[c] * a.F + f];
+      bool inside;
+      v[c] = a.stats ? fake_quant(g, s, z, &inside) : g;
+    }
+    xo[f] = fmaf(w[0], v[0], fmaf(w[1], v[1], fmaf(w[2], v[2], w[3] * v[3])));
+  }
+}
+
+// d_grid[corner] += w_corner * dX (times the pass-through mask of the corner value with QAT).
+__global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.n * a.n_levels) return;
+  const int64_t p = gid / a.n_levels;
+  const int l = (int)(gid % a.n_levels);
+  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int res = a.base_res << l;
+  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+  const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
+  const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
+  const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
+  const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
+  const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
+  const float* d = dx + p * (int64_t)(a.n_levels * a.F) + l * a.F;
+  for (int f = 0; f < a.F; ++f) {
+    const float df = d[f];
+    if (df == 0.0f) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (w[c] == 0.0f) continue;
+      float m = 1.0f;
+      if (a.stats) {
+        bool inside;
+        fake_quant(a.grid[vtx[c] * a.F + f], s, z, &inside);
+        m = inside ? 1.0f : 0.0f;
+      }
+      if (m != 0.0f) atomicAdd(&dgrid[vtx[c] * a.F + f], w[c] * df);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------ GEMM
+enum Epi { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS_SIGMOID = 2, EPI_MASK = 3, EPI_ATOMIC = 4 };
+
+struct GemmArgs {
+  const float* a;
+  int64_t sam, sak;  // A(m, k) = a[m*sam + k*sak]
+  const float* b;
+  int64_t sbk, sbn;  // B(k, n) = b[k*sbk + n*sbn]
+  float* c;
+  int64_t ldc;
+  int M, N, K, k_split;
+  const float* bias;  // [N]
+  const float* mask;  // C(m, n) *= (mask[m*ldm + n] > 0)
+  int64_t ldm;
+};
+
+// C = A * B with a fused epilogue; 64x64 tiles, 16-deep K slices, 4x4 outputs per thread.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ __align__(16) float As[TK][TM + 4];
+  __shared__ __align__(16) float Bs[TK][TN + 4];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int mm, kk;
+      if (g.sak == 1) {
+        kk = e % TK;
+        mm = e / TK;
+      } else {
+        mm = e % TM;
+        kk = e / TM;
+      }
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < kend) ? g.a[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.0f;
+      int nn, kb;
+      if (g.sbn == 1) {
+        nn = e % TN;
+        kb = e / TN;
+      } else {
+        kb = e % TK;
+        nn = e / TK;
+      }
+      const int n = n0 + nn, kq = k0 + kb;
+      Bs[kb][nn] = (n < g.N && kq < kend) ? g.b[(int64_t)kq * g.sbk + (int64_t)n * g.sbn] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      const float4 av = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
+      const float4 bv = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4]);
+      const float a4[4] = {av.x, av.y, av.z, av.w};
+      const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a4[i], b4[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty * 4 + i;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx * 4 + j;
+      if (n >= g.N) continue;
+      float v = acc[i][j];
+      float* out = g.c + (int64_t)m * g.ldc + n;
+      if (EPI == EPI_BIAS_RELU) {
+        *out = fmaxf(v + g.bias[n], 0.0f);
+      } else if (EPI == EPI_BIAS_SIGMOID) {
+        *out = 1.0f / (1.0f + expf(-(v + g.bias[n])));
+      } else if (EPI == EPI_MASK) {
+        *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
+      } else if (EPI == EPI_ATOMIC) {
+        atomicAdd(out, v);
+      } else {
+        *out = v;
+      }
+    }
+  }
+}
+
+template <int EPI>
+int gemm(const GemmArgs& g, int splits, hipStream_t s) {
+  const dim3 grid((unsigned)ceil_div(g.N, 64), (unsigned)ceil_div(g.M, 64), (unsigned)splits);
+  hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, s, g);
+  return check_launch("k_gemm");
+}
+
+// db[n] += sum over rows of dz[m][n]
+__global__ void __launch_bounds__(kBlock) k_colsum(const float* __restrict__ dz, int64_t rows, int cols, int rows_per_block,
+                                             float* __restrict__ db) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(rows, r0 + rows_per_block);
+  for (int c = threadIdx.x; c < cols; c += kBlock) {
+    float acc = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) acc += dz[r * cols + c];
+    atomicAdd(&db[c], acc);
+  }
+}
+
+__global__ void k_dsigmoid(const float* __restrict__ dy, const float* __restrict__ y, float* __restrict__ dz, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dz[i] = dy[i] * y[i] * (1.0f - y[i]);
+}
+
+// ------------------------------------------------------------------------------------------ loss
+struct LossArgs {
+  const float* y;
+  float* dy;
+  const int32_t* ids;
+  int64_t n, n_positions;
+  int head_dim, E, C, n_textures, blocks_w;
+  int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
+  const uint64_t* ref;
+  const uint8_t* tex[NTBC_MAX_TEXTURES];
+  float inv_t, w_e, w_c, w_cde, w_cdc;
+  float inv_ne, inv_nc;  // 1/(n E), 1/(n 16 C)
+  float* losses;         // [5]
+};
+
+// Palette coefficients of logical index n (Eq. palette, Eq. weightBC4): c_n = a e0 + b e1 + k.
+__device__ __forceinline__ void palette_coef(bool bc1, bool eight, int n, float* a, float* b, float* k) {
+  *k = 0.0f;
+  if (bc1) {
+    *b = (float)n / 3.0f;
+    *a = 1.0f - *b;
+  } else if (eight) {
+    *b = (float)n / 7.0f;
+    *a = 1.0f - *b;
+  } else if (n == 0 || n == 7) {
+    *a = 0.0f;
+    *b = 0.0f;
+    *k = n == 7 ? 1.0f : 0.0f;
+  } else {
+    *b = (float)(n - 1) / 5.0f;
+    *a = 1.0f - *b;
+  }
+}
+
+// Straight-through decoded-colour term for one texel: distances dist[0..N) (d_n = -dist_n), the
+// reference palette pr and the texel colour c.  Adds (x - c)^2 to *loss for the hard choice x and
+// returns dL/d(d_n) = (1/T) s_n sum_c g_c (pr_n,c - xs_c), g = 2 (x - c) / N_cd, xs = sum_n s_n pr_n.
+template <int CH>
+__device__ __forceinline__ void cd_term(const float* dist, int N, const float (*pr)[3], const float* c, float inv_ncd,
+                                        float inv_t, float* loss, float* dd) {
+  int k = 0;
+  float dmin = dist[0];
+  for (int n = 1; n < N; ++n)
+    if (dist[n] < dmin) {
+      dmin = dist[n];
+      k = n;
+    }
+  float gx[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    const float d = pr[k][ch] - c[ch];
+    *loss += d * d;
+    gx[ch] = 2.0f * d * inv_ncd;
+  }
+  float s[8], tot = 0.0f;
+  for (int n = 0; n < N; ++n) {
+    s[n] = expf(-(dist[n] - dmin) * inv_t);
+    tot += s[n];
+  }
+  float xs[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) xs[ch] = 0.0f;
+  for (int n = 0; n < N; ++n) {
+    s[n] /= tot;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) xs[ch] += s[n] * pr[n][ch];
+  }
+  for (int n = 0; n < N; ++n) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) acc += gx[ch] * (pr[n][ch] - xs[ch]);
+    dd[n] = s[n] * inv_t * acc;
+  }
+}
+
+template <int CH>
+__device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float* le, float* lc, float* lcde,
+                             float* lcdc, bool* bad) {
+  const bool bc1 = CH == 3;
+  const int N = bc1 ? 4 : 8;
+  const float* yp = a.y + p * a.head_dim;
+  float* dyp = a.dy + p * a.head_dim;
+  const uint64_t w = a.ref[(int64_t)t * a.n_positions + id];
+  float er0[3] = {0, 0, 0}, er1[3] = {0, 0, 0};
+  bool eight_ref = true;
+  if (bc1) {
+    const uint32_t c0 = (uint32_t)(w & 0xFFFF), c1 = (uint32_t)((w >> 16) & 0xFFFF);
+    er0[0] = (float)dev::expand5d((c0 >> 11) & 31) / 255.0f;
+    er0[1] = (float)dev::expand6d((c0 >> 5) & 63) / 255.0f;
+    er0[2] = (float)dev::expand5d(c0 & 31) / 255.0f;
+    er1[0] = (float)dev::expand5d((c1 >> 11) & 31) / 255.0f;
+    er1[1] = (float)dev::expand6d((c1 >> 5) & 63) / 255.0f;
+    er1[2] = (float)dev::expand5d(c1 & 31) / 255.0f;
+  } else {
+    const int b0 = (int)(w & 0xFF), b1 = (int)((w >> 8) & 0xFF);
+    er0[0] = (float)b0 / 255.0f;
+    er1[0] = (float)b1 / 255.0f;
+    eight_ref = b0 > b1;
+  }
+  float pr[8][3], ph[8][3], ca[8], cb[8];
+  const int e = a.ep_off[t];
+  float eh0[3], eh1[3];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    eh0[ch] = yp[e + ch];
+    eh1[ch] = yp[e + CH + ch];
+  }
+  const bool eight_hat = bc1 ? true : eh0[0] > eh1[0];
+  for (int n = 0; n < N; ++n) {
+    float ar, br, kr;
+    palette_coef(bc1, eight_ref, n, &ar, &br, &kr);
+    float ah, bh, kh;
+    palette_coef(bc1, eight_hat, n, &ah, &bh, &kh);
+    ca[n] = ah;
+    cb[n] = bh;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      pr[n][ch] = ar * er0[ch] + br * er1[ch] + kr;
+      ph[n][ch] = ah * eh0[ch] + bh * eh1[ch] + kh;
+    }
+  }
+  // L_e
+  float de0[CH], de1[CH];
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    const float d0 = eh0[ch] - er0[ch], d1 = eh1[ch] - er1[ch];
+    *le += d0 * d0 + d1 * d1;
+    de0[ch] = a.w_e * 2.0f * d0 * a.inv_ne;
+    de1[ch] = a.w_e * 2.0f * d1 * a.inv_ne;
+    *bad |= !isfinite(eh0[ch]) || !isfinite(eh1[ch]);
+  }
+  const uint8_t* tex = a.tex[t];
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
+  for (int i = 0; i < 16; ++i) {
+    const uint8_t* tp = tex + (int64_t)(4 * by + i / 4) * pitch + (int64_t)(4 * bx + i % 4) * CH;
+    float c[CH], chat[CH], dchat[CH];
+    const int ci = a.E + i * a.C + a.ch_off[t];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      c[ch] = (float)tp[ch] / 255.0f;
+      chat[ch] = yp[ci + ch];
+      const float d = chat[ch] - c[ch];
+      *lc += d * d;
+      dchat[ch] = a.w_c * 2.0f * d * a.inv_nc;
+      *bad |= !isfinite(chat[ch]);
+    }
+    // endpoint branch: d_n = -||c - c^_n|| over the palette of the predicted endpoints
+    float dist[8], dd[8];
+    for (int n = 0; n < N; ++n) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        const float d = c[ch] - ph[n][ch];
+        acc += d * d;
+      }
+      dist[n] = sqrtf(acc);
+    }
+    cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcde, dd);
+    for (int n = 0; n < N; ++n) {
+      if (dist[n] <= 0.0f) continue;
+      const float g = a.w_cde * dd[n] / dist[n];
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        const float u = g * (c[ch] - ph[n][ch]);
+        de0[ch] += u * ca[n];
+        de1[ch] += u * cb[n];
+      }
+    }
+    // colour branch: d_n = -||c^ - c_n|| over the reference palette
+    for (int n = 0; n < N; ++n) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) {
+        const float d = chat[ch] - pr[n][ch];
+        acc += d * d;
+      }
+      dist[n] = sqrtf(acc);
+    }
+    cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcdc, dd);
+    for (int n = 0; n < N; ++n) {
+      if (dist[n] <= 0.0f) continue;
+      const float g = a.w_cdc * dd[n] / dist[n];
+#pragma unroll
+      for (int ch = 0; ch < CH; ++ch) dchat[ch] -= g * (chat[ch] - pr[n][ch]);
+    }
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      dyp[ci + ch] = dchat[ch];
+      *bad |= !isfinite(dchat[ch]);
+    }
+  }
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    dyp[e + ch] = de0[ch];
+    dyp[e + CH + ch] = de1[ch];
+    *bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
+  bool bad = false;
+  if (gid < a.n * a.n_textures) {
+    const int64_t p = gid / a.n_textures;
+    const int t = (int)(gid % a.n_textures);
+    const int id = clamp_id(a.ids[p], a.n_positions);
+    if (a.formats[t] == NTBC_BC1)
+      texture_loss<3>(a, p, t, id, &le, &lc, &lcde, &lcdc, &bad);
+    else
+      texture_loss<1>(a, p, t, id, &le, &lc, &lcde, &lcdc, &bad);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    le += __shfl_xor(le, off);
+    lc += __shfl_xor(lc, off);
+    lcde += __shfl_xor(lcde, off);
+    lcdc += __shfl_xor(lcdc, off);
+  }
+  const unsigned long long anybad = __ballot(bad);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&a.losses[0], le * a.inv_ne);
+    atomicAdd(&a.losses[1], lc * a.inv_nc);
+    atomicAdd(&a.losses[2], lcde * a.inv_nc);
+    atomicAdd(&a.losses[3], lcdc * a.inv_nc);
+    if (anybad) atomicExch(&a.losses[4], 1.0f);
+  }
+}
+
+// ------------------------------------------------------------------------------------------ Adam
+struct AdamArgs {
+  float lr, b1, b2, eps, bc1, bc2;  // bc = 1 / (1 - beta^t)
+  const float* flag;                // skip when *flag != 0
+};
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int64_t n, AdamArgs a) {
+  if (*a.flag != 0.0f) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= a.lr * (mi * a.bc1) / (sqrtf(vi * a.bc2) + a.eps);
+  }
+}
+
+// ------------------------------------------------------------------------------------------ quantise
+__global__ void k_quantize(const float* __restrict__ g, LevelArgs la, const int* __restrict__ stats,
+                           uint8_t* __restrict__ codes) {
+  const int l = blockIdx.y;
+  if (l >= la.n_levels) return;
+  const float s = reinterpret_cast<const float*>(stats)[2 * NTBC_MAX_LEVELS + l];
+  const int z = stats[3 * NTBC_MAX_LEVELS + l];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < la.count[l]; i += (int64_t)gridDim.x * blockDim.x) {
+    const float t = rintf(__fdiv_rn(g[la.begin[l] + i], s)) + (float)z;
+    codes[la.begin[l] + i] = (uint8_t)fminf(fmaxf(t, 0.0f), 255.0f);
+  }
+}
+
+__global__ void k_export_qparams(const int* __restrict__ stats, int n_levels, float* __restrict__ scale, int32_t* __restrict__ zero) {
+  const int l = threadIdx.x;
+  if (l < n_levels) {
+    scale[l] = reinterpret_cast<const float*>(stats)[2 * NTBC_MAX_LEVELS + l];
+    zero[l] = stats[3 * NTBC_MAX_LEVELS + l];
+  }
+}
+
+// ------------------------------------------------------------------------------------------ batches
+__host__ __device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__global__ void k_batch_ids(uint64_t key, int32_t batch, uint64_t n_positions, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const uint64_t z = splitmix_out(key + (uint64_t)(i + 1) * kGamma);
+  out[i] = (int32_t)(((z >> 32) * n_positions) >> 32);
+}
+
+// ------------------------------------------------------------------------------------------ host
+int fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return NTBC_OK;
+  const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, 256), 4096);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return check_launch("k_fill");
+}
+
+LevelArgs level_args(const Shape& s) {
+  LevelArgs la{};
+  la.n_levels = s.n_levels;
+  for (int l = 0; l < s.n_levels; ++l) {
+    la.begin[l] = s.level_offset[l] * s.n_features;
+    la.count[l] = (s.level_offset[l + 1] - s.level_offset[l]) * s.n_features;
+  }
+  return la;
+}
+
+int qat_range(const Shape& s, const float* grid, int* stats, hipStream_t strm) {
+  hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(64), 0, strm, stats);
+  const LevelArgs la = level_args(s);
+  int64_t mx = 0;
+  for (int l = 0; l < s.n_levels; ++l) mx = la.count[l] > mx ? la.count[l] : mx;
+  const unsigned bx = (unsigned)std::min<int64_t>(ceil_div(mx, 256 * 8), 1024);
+  hipLaunchKernelGGL(k_level_minmax, dim3(bx, s.n_levels), dim3(kBlock), 0, strm, grid, la, stats);
+  hipLaunchKernelGGL(k_qat_params, dim3(1), dim3(64), 0, strm, stats, s.n_levels);
+  return check_launch("qat range");
+}
+
+FeatArgs feat_args(const Shape& s, const float* grid, const int* stats, const int32_t* ids, int64_t n, float* x) {
+  FeatArgs f{};
+  f.grid = grid;
+  f.stats = stats;
+  f.ids = ids;
+  f.n = n;
+  f.n_levels = s.n_levels;
+  f.base_res = s.base_res;
+  f.F = s.n_features;
+  f.blocks_w = s.blocks_w;
+  f.blocks_h = s.blocks_h;
+  for (int l = 0; l <= s.n_levels; ++l) f.level_offset[l] = s.level_offset[l];
+  f.x = x;
+  return f;
+}
+
+struct Ctx {
+  Shape s;
+  TrainLayout lay;
+  float* ws;
+  int64_t n;
+  hipStream_t strm;
+  int* stats() { return reinterpret_cast<int*>(ws + lay.stats); }
+  float* act_in(int k) { return k == 0 ? ws + lay.x : ws + lay.h[k - 1]; }
+};
+
+int check_common(const ntbc_model_desc* d, int precision, const int32_t* ids, int32_t n, void* workspace,
+                 size_t workspace_bytes, Ctx* c) {
+  int st = make_shape(d, &c->s);
+  if (st != NTBC_OK) return st;
+  if (precision != NTBC_FP32)
+    return fail(precision == NTBC_BF16 || precision == NTBC_FP8_E4M3 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
+                "training runs in FP32 (precision %d)", precision);
+  NTBC_REQUIRE(n >= 0, "n %d < 0", n);
+  NTBC_REQUIRE(n == 0 || ids != nullptr, "ids is NULL");
+  c->lay = train_layout(c->s, n);
+  if (workspace == nullptr || workspace_bytes < (size_t)c->lay.total * sizeof(float))
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)(c->lay.total * sizeof(float)));
+  c->ws = static_cast<float*>(workspace);
+  c->n = n;
+  return NTBC_OK;
+}
+
+// Forward of the batch: X, hidden activations, heads (into y).
+int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int32_t* ids, float* y) {
+  const Shape& s = c.s;
+  int st;
+  if (qat) {
+    st = qat_range(s, grid, c.stats(), c.strm);
+    if (st != NTBC_OK) return st;
+  }
+  const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, c.ws + c.lay.x);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)ceil_div(c.n * s.n_levels, kBlock)), dim3(kBlock), 0, c.strm, fa);
+  st = check_launch("k_features");
+  if (st != NTBC_OK) return st;
+  for (int k = 0; k < s.n_layers; ++k) {
+    GemmArgs g{};
+    g.a = c.act_in(k);
+    g.sam = s.layer_in[k];
+    g.sak = 1;
+    g.b = weights + s.w_off[k];
+    g.sbk = 1;
+    g.sbn = s.layer_in[k];
+    const bool last = k == s.n_layers - 1;
+    g.c = last ? y : c.ws + c.lay.h[k];
+    g.ldc = s.layer_out[k];
+    g.M = (int)c.n;
+    g.N = s.layer_out[k];
+    g.K = s.layer_in[k];
+    g.k_split = g.K;
+    g.bias = weights + s.b_off[k];
+    st = last ? gemm<EPI_BIAS_SIGMOID>(g, 1, c.strm) : gemm<EPI_BIAS_RELU>(g, 1, c.strm);
+    if (st != NTBC_OK) return st;
+  }
+  return NTBC_OK;
+}
+
+// Backward of the batch from dZ_out (in lay.dy): accumulates d_weights and d_grid.
+int backward(Ctx& c, const float* grid, const float* weights, bool qat, const int32_t* ids, float* d_grid, float* d_weights) {
+  const Shape& s = c.s;
+  int st;
+  float* dz = c.ws + c.lay.dy;
+  float* bufs[2] = {c.ws + c.lay.da, c.ws + c.lay.db};
+  int nb = 0;
+  for (int k = s.n_layers - 1; k >= 0; --k) {
+    const int in = s.layer_in[k], out = s.layer_out[k];
+    // dW_k += dZ_k^T H_k (split over the batch)
+    GemmArgs gw{};
+    gw.a = dz;
+    gw.sam = 1;
+    gw.sak = out;
+    gw.b = c.act_in(k);
+    gw.sbk = in;
+    gw.sbn = 1;
+    gw.c = d_weights + s.w_off[k];
+    gw.ldc = in;
+    gw.M = out;
+    gw.N = in;
+    gw.K = (int)c.n;
+    const int tiles = (int)(ceil_div(out, 64) * ceil_div(in, 64));
+    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n, 256), ceil_div(2048, tiles)));
+    gw.k_split = (int)ceil_div(ceil_div(c.n, splits), 16) * 16;
+    splits = (int)ceil_div(c.n, gw.k_split);
+    st = gemm<EPI_ATOMIC>(gw, splits, c.strm);
+    if (st != NTBC_OK) return st;
+    const int rpb = 256;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb)), dim3(kBlock), 0, c.strm, dz, c.n, out, rpb,
+                       d_weights + s.b_off[k]);
+    st = check_launch("k_colsum");
+    if (st != NTBC_OK) return st;
+    // dH_k = dZ_k W_k, masked by the ReLU of the layer input (none for the grid features)
+    GemmArgs gd{};
+    gd.a = dz;
+    gd.sam = out;
+    gd.sak = 1;
+    gd.b = weights + s.w_off[k];
+    gd.sbk = in;
+    gd.sbn = 1;
+    gd.c = bufs[nb];
+    gd.ldc = in;
+    gd.M = (int)c.n;
+    gd.N = in;
+    gd.K = out;
+    gd.k_split = out;
+    if (k > 0) {
+      gd.mask = c.act_in(k);
+      gd.ldm = in;
+      st = gemm<EPI_MASK>(gd, 1, c.strm);
+    } else {
+      st = gemm<EPI_STORE>(gd, 1, c.strm);
+    }
+    if (st != NTBC_OK) return st;
+    dz = bufs[nb];
+    nb ^= 1;
+  }
+  const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * s.n_levels, kBlock)), dim3(kBlock), 0, c.strm, fa, dz,
+                     d_grid);
+  return check_launch("k_scatter");
+}
+
+int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, float temperature,
+              const float* lw, float* losses, float* dheads, hipStream_t strm) {
+  int st = fill(losses, 5, 0.0f, strm);
+  if (st != NTBC_OK) return st;
+  LossArgs a{};
+  a.y = heads;
+  a.dy = dheads;
+  a.ids = ids;
+  a.n = n;
+  a.n_positions = s.n_positions;
+  a.head_dim = s.head_dim;
+  a.E = s.endpoint_dim;
+  a.C = s.channels;
+  a.n_textures = s.n_textures;
+  a.blocks_w = s.blocks_w;
+  for (int i = 0; i < s.n_textures; ++i) {
+    a.formats[i] = s.formats[i];
+    a.ep_off[i] = s.ep_off[i];
+    a.ch_off[i] = s.ch_off[i];
+    a.tex[i] = t->texels[i];
+  }
+  a.ref = t->ref_blocks;
+  a.inv_t = 1.0f / temperature;
+  a.w_e = lw ? lw[0] : 1.0f;
+  a.w_c = lw ? lw[1] : 1.0f;
+  a.w_cde = lw ? lw[2] : 1.0f;
+  a.w_cdc = lw ? lw[3] : 1.0f;
+  a.inv_ne = (float)(1.0 / ((double)n * s.endpoint_dim));
+  a.inv_nc = (float)(1.0 / ((double)n * 16.0 * s.channels));
+  a.losses = losses;
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)ceil_div(n * s.n_textures, kBlock)), dim3(kBlock), 0, strm, a);
+  return check_launch("k_loss_grad");
+}
+
+int check_targets(const Shape& s, const ntbc_targets* t) {
+  NTBC_REQUIRE(t != nullptr && t->ref_blocks != nullptr, "targets or ref_blocks is NULL");
+  for (int i = 0; i < s.n_textures; ++i) NTBC_REQUIRE(t->texels[i] != nullptr, "targets texels[%d] is NULL", i);
+  return NTBC_OK;
+}
+
+}  // namespace
+
+namespace ntbc {
+int64_t train_workspace_bytes(const Shape& s, int64_t batch) { return train_layout(s, batch).total * (int64_t)sizeof(float); }
+}  // namespace ntbc
+
+extern "C" int ntbc_forward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
+                            int32_t precision, const int32_t* ids, int32_t n, float* heads_out, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  Ctx c;
+  int st = check_common(d, precision, ids, n, workspace, workspace_bytes, &c);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(grid && weights, "grid or weights is NULL");
+  if (n == 0) return NTBC_OK;
+  NTBC_REQUIRE(heads_out != nullptr, "heads_out is NULL");
+  c.strm = as_stream(stream);
+  return forward(c, grid, weights, qat != 0, ids, heads_out);
+}
+
+extern "C" int ntbc_backward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
+                             int32_t precision, const int32_t* ids, int32_t n, const float* d_heads, float* d_grid,
+                             float* d_weights, void* workspace, size_t workspace_bytes, void* stream) {
+  Ctx c;
+  int st = check_common(d, precision, ids, n, workspace, workspace_bytes, &c);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(grid && weights && d_grid && d_weights, "grid, weights, d_grid or d_weights is NULL");
+  if (n == 0) return NTBC_OK;
+  NTBC_REQUIRE(d_heads != nullptr, "d_heads is NULL");
+  c.strm = as_stream(stream);
+  float* y = c.ws + c.lay.y;
+  st = forward(c, grid, weights, qat != 0, ids, y);
+  if (st != NTBC_OK) return st;
+  const int64_t ny = c.n * c.s.head_dim;
+  hipLaunchKernelGGL(k_dsigmoid, dim3((unsigned)std::min<int64_t>(ceil_div(ny, 256), 4096)), dim3(256), 0, c.strm, d_heads, y,
+                     c.ws + c.lay.dy, ny);
+  st = check_launch("k_dsigmoid");
+  if (st != NTBC_OK) return st;
+  return backward(c, grid, weights, qat != 0, ids, d_grid, d_weights);
+}
+
+extern "C" int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float* heads, const int32_t* ids,
+                              int32_t n, float temperature, const float* loss_weights, float* losses_out,
+                              float* d_heads_out, void* stream) {
+  Shape s;
+  int st = make_shape(d, &s);
+  if (st != NTBC_OK) return st;
+  st = check_targets(s, t);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(n >= 0, "n %d < 0", n);
+  NTBC_REQUIRE(temperature > 0.0f, "temperature must be positive");
+  NTBC_REQUIRE(losses_out != nullptr, "losses_out is NULL");
+  if (n == 0) return fill(losses_out, 5, 0.0f, as_stream(stream));
+  NTBC_REQUIRE(heads && ids && d_heads_out, "heads, ids or d_heads_out is NULL");
+  return loss_grad(s, t, heads, ids, n, temperature, loss_weights, losses_out, d_heads_out, as_stream(stream));
+}
+
+extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* tsd, const ntbc_targets* t,
+                               const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
+                               float* losses_out, void* workspace, size_t workspace_bytes, void* stream) {
+  NTBC_REQUIRE(h != nullptr && tsd != nullptr, "hparams or state is NULL");
+  Ctx c;
+  int st = check_common(d, h->precision, batch_ids, batch, workspace, workspace_bytes, &c);
+  if (st != NTBC_OK) return st;
+  st = check_targets(c.s, t);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(batch > 0, "batch must be positive");
+  NTBC_REQUIRE(step >= 0, "step must be >= 0");
+  NTBC_REQUIRE(tsd->grid && tsd->weights && tsd->m_grid && tsd->v_grid && tsd->m_weights && tsd->v_weights &&
+                   tsd->d_grid && tsd->d_weights,
+               "a train-state pointer is NULL");
+  NTBC_REQUIRE(losses_out != nullptr, "losses_out is NULL");
+  NTBC_REQUIRE(h->temperature > 0.0f && h->total_steps > 0 && h->warmup >= 0, "bad temperature or schedule");
+  c.strm = as_stream(stream);
+  const Shape& s = c.s;
+  const bool qat = h->qat != 0;
+  float* y = c.ws + c.lay.y;
+  st = forward(c, tsd->grid, tsd->weights, qat, batch_ids, y);
+  if (st != NTBC_OK) return st;
+  st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm);
+  if (st != NTBC_OK) return st;
+  const int64_t ny = c.n * s.head_dim;
+  hipLaunchKernelGGL(k_dsigmoid, dim3((unsigned)std::min<int64_t>(ceil_div(ny, 256), 4096)), dim3(256), 0, c.strm,
+                     c.ws + c.lay.dy, y, c.ws + c.lay.dy, ny);
+  st = check_launch("k_dsigmoid");
+  if (st != NTBC_OK) return st;
+  const int64_t ng = s.grid_vertices * s.n_features;
+  st = fill(tsd->d_grid, ng, 0.0f, c.strm);
+  if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
+  if (st != NTBC_OK) return st;
+  st = backward(c, tsd->grid, tsd->weights, qat, batch_ids, tsd->d_grid, tsd->d_weights);
+  if (st != NTBC_OK) return st;
+  // learning rates of this step: linear warm-up, then cosine annealing to 0
+  auto lr_at = [&](double lr0) {
+    if (step < h->warmup) return lr0 * (double)(step + 1) / h->warmup;
+    const double span = h->total_steps - h->warmup > 0 ? (double)(h->total_steps - h->warmup) : 1.0;
+    return lr0 * 0.5 * (1.0 + std::cos(M_PI * (double)(step - h->warmup) / span));
+  };
+  const double tt = (double)step + 1.0;
+  AdamArgs aa{};
+  aa.b1 = h->beta1;
+  aa.b2 = h->beta2;
+  aa.eps = h->eps;
+  aa.bc1 = (float)(1.0 / (1.0 - std::pow((double)h->beta1, tt)));
+  aa.bc2 = (float)(1.0 / (1.0 - std::pow((double)h->beta2, tt)));
+  aa.flag = losses_out + 4;
+  aa.lr = (float)lr_at(h->lr_grid);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(ng, 256), 8192)), dim3(256), 0, c.strm, tsd->grid,
+                     tsd->d_grid, tsd->m_grid, tsd->v_grid, ng, aa);
+  aa.lr = (float)lr_at(h->lr_mlp);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 8192)), dim3(256), 0, c.strm,
+                     tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, aa);
+  return check_launch("k_adam");
+}
+
+extern "C" int ntbc_quantize_grid(const ntbc_model_desc* d, const float* grid, uint8_t* codes, float* scale,
+                                  int32_t* zero, void* workspace, size_t workspace_bytes, void* stream) {
+  Shape s;
+  int st = make_shape(d, &s);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(grid && codes && scale && zero, "NULL pointer argument");
+  if (workspace == nullptr || workspace_bytes < 4 * NTBC_MAX_LEVELS * sizeof(float))
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %d bytes", (int)(4 * NTBC_MAX_LEVELS * sizeof(float)));
+  hipStream_t strm = as_stream(stream);
+  int* stats = static_cast<int*>(workspace);
+  st = qat_range(s, grid, stats, strm);
+  if (st != NTBC_OK) return st;
+  const LevelArgs la = level_args(s);
+  int64_t mx = 0;
+  for (int l = 0; l < s.n_levels; ++l) mx = la.count[l] > mx ? la.count[l] : mx;
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)std::min<int64_t>(ceil_div(mx, 256), 4096), s.n_levels), dim3(256), 0, strm,
+                     grid, la, stats, codes);
+  hipLaunchKernelGGL(k_export_qparams, dim3(1), dim3(64), 0, strm, stats, s.n_levels, scale, zero);
+  return check_launch("ntbc_quantize_grid");
+}
+
+extern "C" int ntbc_batch_ids(uint64_t seed, int64_t step, int32_t batch, int64_t n_positions, int32_t* ids_out,
+                              void* stream) {
+  NTBC_REQUIRE(ids_out != nullptr || batch == 0, "ids_out is NULL");
+  NTBC_REQUIRE(batch >= 0 && n_positions > 0 && n_positions <= 0x7FFFFFFF, "bad batch or n_positions");
+  if (batch == 0) return NTBC_OK;
+  uint64_t h = 0;
+  const uint64_t parts[3] = {seed, 0xBA7C4ull, (uint64_t)step};
+  for (uint64_t p : parts) h = splitmix_out((h ^ p) + kGamma);
+  hipLaunchKernelGGL(k_batch_ids, dim3((unsigned)ceil_div(batch, 256)), dim3(256), 0, as_stream(stream), h, batch,
+                     (uint64_t)n_positions, ids_out);
+  return check_launch("ntbc_batch_ids");
+}

@@ -45,6 +45,22 @@ class Params(ctypes.Structure):
 REUSE_PACKED = 1
 
 
+class TrainStateC(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("grid", "weights", "m_grid", "v_grid", "m_weights",
+                                                 "v_weights", "d_grid", "d_weights")]
+
+
+class TargetsC(ctypes.Structure):
+    _fields_ = [("ref_blocks", ctypes.c_void_p), ("texels", ctypes.c_void_p * MAX_TEXTURES)]
+
+
+class HParams(ctypes.Structure):
+    _fields_ = [("lr_grid", ctypes.c_float), ("lr_mlp", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("temperature", ctypes.c_float),
+                ("warmup", ctypes.c_int32), ("total_steps", ctypes.c_int32), ("qat", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("loss_weights", ctypes.c_float * 4)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -64,6 +80,15 @@ _SIGNATURES = {
     "ntbc_fallback": ([_P, _P, _P, _P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
     "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
                            _P, _SZ, _P], ctypes.c_int),
+    "ntbc_forward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P], ctypes.c_int),
+    "ntbc_backward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _SZ, _P],
+                      ctypes.c_int),
+    "ntbc_loss_grad": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TargetsC), _P, _P, _I32, _F, _P, _P, _P, _P],
+                       ctypes.c_int),
+    "ntbc_train_step": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TrainStateC), ctypes.POINTER(TargetsC), _P,
+                         _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P], ctypes.c_int),
+    "ntbc_quantize_grid": ([ctypes.POINTER(ModelDesc), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "ntbc_batch_ids": ([ctypes.c_uint64, _I64, _I32, _I64, _P, _P], ctypes.c_int),
 }
 
 
@@ -229,3 +254,105 @@ class Model:
         _check(lib().ntbc_infer_blocks(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
                                        n_blocks, _ptr(out), _ptr(h), _ptr(ws), ws.numel(), _stream()))
         return (out, h) if heads else out
+
+
+# -------------------------------------------------------------------------------------- training
+def _scratch(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def forward(desc: ModelDesc, grid: torch.Tensor, weights: torch.Tensor, ids: torch.Tensor, qat: bool = False,
+            precision: int = FP32) -> torch.Tensor:
+    """Sigmoid heads [n, head_dim] of block positions ids (int32) from the FP32 master parameters."""
+    n = ids.numel()
+    _, head_dim, _ = model_sizes(desc)
+    out = torch.empty((n, head_dim), dtype=torch.float32, device=grid.device)
+    ws = _scratch(workspace_size(desc, precision, max(n, 1)), grid.device)
+    _check(lib().ntbc_forward(ctypes.byref(desc), _ptr(grid), _ptr(weights), int(qat), precision, _ptr(ids), n,
+                              _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def backward(desc: ModelDesc, grid, weights, ids, d_heads, qat: bool = False, precision: int = FP32):
+    """(d_grid, d_weights) of sum(d_heads * heads); the forward activations are recomputed."""
+    n = ids.numel()
+    dg = torch.zeros_like(grid)
+    dw = torch.zeros_like(weights)
+    ws = _scratch(workspace_size(desc, precision, max(n, 1)), grid.device)
+    _check(lib().ntbc_backward(ctypes.byref(desc), _ptr(grid), _ptr(weights), int(qat), precision, _ptr(ids), n,
+                               _ptr(d_heads.contiguous()), _ptr(dg), _ptr(dw), _ptr(ws), ws.numel(), _stream()))
+    return dg, dw
+
+
+class Targets:
+    """Reference blocks [n_textures, n_positions] (int64) and the textures (uint8, device)."""
+
+    def __init__(self, ref_blocks: torch.Tensor, textures: Sequence[torch.Tensor]):
+        self.ref_blocks = ref_blocks.contiguous()
+        self.textures = [t.contiguous() for t in textures]
+        self.c = TargetsC()
+        self.c.ref_blocks = self.ref_blocks.data_ptr()
+        for i, t in enumerate(self.textures):
+            self.c.texels[i] = t.data_ptr()
+
+
+def loss_grad(desc: ModelDesc, targets: Targets, heads: torch.Tensor, ids: torch.Tensor,
+              temperature: float = 0.01, loss_weights=(1.0, 1.0, 1.0, 1.0)):
+    """(losses float32[5] = L_e, L_c, L_cd_e, L_cd_c, nonfinite flag; dL/dheads)."""
+    losses = torch.empty(5, dtype=torch.float32, device=heads.device)
+    dh = torch.empty_like(heads)
+    lw = torch.tensor(loss_weights, dtype=torch.float32, device=heads.device)
+    _check(lib().ntbc_loss_grad(ctypes.byref(desc), ctypes.byref(targets.c), _ptr(heads.contiguous()), _ptr(ids),
+                                ids.numel(), temperature, _ptr(lw), _ptr(losses), _ptr(dh), _stream()))
+    return losses, dh
+
+
+def quantize_grid(desc: ModelDesc, grid: torch.Tensor):
+    """(codes uint8 [V, F], scale float32 [L], zero int32 [L]) of an FP32 grid."""
+    codes = torch.empty(grid.shape, dtype=torch.uint8, device=grid.device)
+    scale = torch.empty(desc.n_levels, dtype=torch.float32, device=grid.device)
+    zero = torch.empty(desc.n_levels, dtype=torch.int32, device=grid.device)
+    ws = _scratch(1024, grid.device)
+    _check(lib().ntbc_quantize_grid(ctypes.byref(desc), _ptr(grid), _ptr(codes), _ptr(scale), _ptr(zero), _ptr(ws),
+                                    ws.numel(), _stream()))
+    return codes, scale, zero
+
+
+class Trainer:
+    """FP32 master parameters, Adam state and scratch of one material on the device."""
+
+    def __init__(self, desc: ModelDesc, grid: torch.Tensor, weights: torch.Tensor, targets: Targets, batch: int,
+                 total_steps: int, lr_grid: float = 0.01, lr_mlp: float = 0.005, temperature: float = 0.01,
+                 warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0)):
+        self.desc = desc
+        self.grid = grid.clone().contiguous()
+        self.weights = weights.clone().contiguous()
+        self.targets = targets
+        self.batch = batch
+        dev = grid.device
+        self.m_grid, self.v_grid = torch.zeros_like(self.grid), torch.zeros_like(self.grid)
+        self.m_w, self.v_w = torch.zeros_like(self.weights), torch.zeros_like(self.weights)
+        self.d_grid, self.d_w = torch.zeros_like(self.grid), torch.zeros_like(self.weights)
+        self.ws = _scratch(workspace_size(desc, FP32, batch), dev)
+        self.losses = torch.zeros(5, dtype=torch.float32, device=dev)
+        self.state = TrainStateC(*[t.data_ptr() for t in (self.grid, self.weights, self.m_grid, self.v_grid,
+                                                          self.m_w, self.v_w, self.d_grid, self.d_w)])
+        self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, FP32,
+                         (ctypes.c_float * 4)(*loss_weights))
+
+    def step(self, ids: torch.Tensor, step: int, qat: bool = False) -> torch.Tensor:
+        """One step on the batch ids (int32, device); returns the device losses[5] (overwritten)."""
+        self.h.qat = int(qat)
+        _check(lib().ntbc_train_step(ctypes.byref(self.desc), ctypes.byref(self.state), ctypes.byref(self.targets.c),
+                                     _ptr(ids), ids.numel(), step, ctypes.byref(self.h), _ptr(self.losses),
+                                     _ptr(self.ws), self.ws.numel(), _stream()))
+        return self.losses
+
+
+def batch_ids(seed: int, step: int, batch: int, n_positions: int, out: Optional[torch.Tensor] = None,
+              device="cuda") -> torch.Tensor:
+    """Device int32 batch of block ids (SplitMix64 stream keyed by seed and step)."""
+    if out is None:
+        out = torch.empty(batch, dtype=torch.int32, device=device)
+    _check(lib().ntbc_batch_ids(seed, step, batch, n_positions, _ptr(out), _stream()))
+    return out

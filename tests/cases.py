@@ -64,3 +64,34 @@ def assert_exact_in_float32(cfg, layers, g, ids):
         assert np.abs(z).max() < 2.0 ** 12
         assert np.array_equal(z, z.astype(np.float32).astype(np.float64))
         h = np.maximum(z, 0.0)
+
+
+class TrainProblem:
+    """A material, its reference blocks on both sides (each side encodes its own), and parameters."""
+
+    def __init__(self, cfg, material, seed, grid_scale=0.5):
+        import torch
+        from oracle import bc as OB
+        from paper_2407_09543_amd import ntbc
+        self.cfg = cfg
+        self.mat = material
+        self.desc = ntbc.desc_from_config(cfg)
+        blocks = [OB.image_to_blocks(t.texels) for t in material.textures]
+        ref_or = [OB.bc1_encode_ref(b) if t.fmt == 1 else OB.bc4_encode_ref(b[..., 0])
+                  for b, t in zip(blocks, material.textures)]
+        self.tg_oracle = ON.Targets(cfg.formats, ref_or, blocks)
+        tex = [torch.from_numpy(t.texels).cuda() for t in material.textures]
+        ref_gpu = torch.stack([ntbc.encode_ref(t, f) for t, f in zip(tex, cfg.formats)])
+        self.tg_gpu = ntbc.Targets(ref_gpu, tex)
+        layers = synth.init_weights(cfg, seed)
+        rng = np.random.default_rng(seed + 7)
+        self.layers = [(w, (0.1 * rng.standard_normal(len(b))).astype(np.float32)) for w, b in layers]
+        self.flat = synth.flatten_weights(self.layers)
+        self.grid = synth.random_grid(cfg, seed, grid_scale)
+        self.grid_d = torch.from_numpy(self.grid).cuda()
+        self.flat_d = torch.from_numpy(self.flat).cuda()
+
+    def ids(self, seed, n):
+        import torch
+        ids = synth.batch_ids(seed, 0, n, self.cfg.n_positions)
+        return ids, torch.from_numpy(ids).cuda()
