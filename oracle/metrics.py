@@ -8,9 +8,13 @@ block is a quantisation-boundary tie when (1) packing the implementation's own h
 oracle's float32 packer reproduces its word bit for bit, and (2) the oracle's smallest decision margin
 for that block (distance of an endpoint value to its rounding boundary, in y units; gap between the two
 nearest squared palette distances) is within what the head difference d = |Y_impl - Y_oracle|_inf of
-the block can move it: d for an endpoint; 2*ch*d for the gap of a texel with ch channels, since
-D_a - D_b changes by 2 * sum_c (p_b,c - p_a,c) delta_c under a colour change delta, and palette values
-lie in [0, 1].
+the block, plus the implementation's float32 rounding of the decision itself, can move it:
+  * endpoint: d + 1.25e-7.  The implementation decides floor(fl(fl(y*m) + 0.5)) in float32; both
+    roundings together move y*m by at most one ulp of values below m+1, i.e. 2^-23 * 2^ceil(log2(m+1)),
+    which is < 1.25e-7 * m for m = 31, 63, 255;
+  * index: 2*ch*d + 2e-6 for a ch-channel texel.  D_a - D_b changes by 2 sum_c (p_b,c - p_a,c) delta_c
+    under a colour change delta (palette values lie in [0, 1]); float32 evaluation of each squared
+    distance (a difference, ch squares, ch-1 sums, each within half an ulp, D <= 3) is off by < 1e-6.
 """
 from __future__ import annotations
 
@@ -50,7 +54,7 @@ def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
             continue
         _, ep_m, idx_m = ntbc.pack_texture(Y_oracle[diff], lay, t, "f64", return_margin=True)
         ch = lay.channels(t)
-        tie = (ep_m <= dy[diff] * (1 + 1e-9)) | (idx_m <= 2.0 * ch * dy[diff] * (1 + 1e-9))
+        tie = (ep_m <= dy[diff] + 1.25e-7) | (idx_m <= 2.0 * ch * dy[diff] + 2e-6)
         out["differ"] += int(diff.sum())
         out["ties"] += int(tie.sum())
         idx = np.nonzero(diff)[0]

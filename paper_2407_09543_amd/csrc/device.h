@@ -90,16 +90,31 @@ struct GridView {
   const float* scale;    // per level (U8)
   const int32_t* zero;   // per level (U8)
   int n_levels, base_res, n_features, blocks_w, blocks_h;
+  // shift_x = log2(2*blocks_w) when that is a power of two and every numerator fits in 31 bits,
+  // else -1 (general path); likewise shift_y
+  int shift_x, shift_y;
   int64_t level_offset[NTBC_MAX_LEVELS + 1];
 };
+
+// corner() when 2*blocks = 2^shift: the same integer decisions with shifts instead of divisions.
+__device__ __forceinline__ Corner corner_pow2(int b, int blocks, int res, int shift) {
+  const int num = (2 * b + 1) * res - blocks;
+  const int hi = (res - 1) << shift;
+  const int i0 = num >> shift;
+  Corner c;
+  c.i0 = num <= 0 ? 0 : (num >= hi ? res - 2 : i0);
+  const int fnum = num <= 0 ? 0 : (num >= hi ? (1 << shift) : num - (i0 << shift));
+  c.f = (float)fnum * __int_as_float((127 - shift) << 23);  // exact: 2^-shift
+  return c;
+}
 
 // Bilinear feature values of features [f0, f0+FE) of `level` at block (bx, by):
 // sum over the four corners of w_c * value_c, value = scale*(q - zero) for U8 grids.
 template <int FE>
 __device__ __forceinline__ void sample(const GridView& g, int level, int f0, int bx, int by, float out[FE]) {
   const int res = g.base_res << level;
-  const Corner cx = corner(bx, g.blocks_w, res);
-  const Corner cy = corner(by, g.blocks_h, res);
+  const Corner cx = g.shift_x >= 0 ? corner_pow2(bx, g.blocks_w, res, g.shift_x) : corner(bx, g.blocks_w, res);
+  const Corner cy = g.shift_y >= 0 ? corner_pow2(by, g.blocks_h, res, g.shift_y) : corner(by, g.blocks_h, res);
   const int64_t v00 = g.level_offset[level] + (int64_t)cy.i0 * res + cx.i0;
   const int64_t F = g.n_features;
   const float w00 = (1.0f - cx.f) * (1.0f - cy.f), w10 = cx.f * (1.0f - cy.f);
@@ -111,10 +126,9 @@ __device__ __forceinline__ void sample(const GridView& g, int level, int f0, int
     load_u8<FE>(g.u8 + (v00 + res) * F + f0, c);
     load_u8<FE>(g.u8 + (v00 + res + 1) * F + f0, d);
     const float s = g.scale[level];
-    const float z = (float)g.zero[level];
+    const float sz = -s * (float)g.zero[level];
 #pragma unroll
-    for (int m = 0; m < FE; ++m)
-      out[m] = s * (fmaf(w00, a[m], fmaf(w10, b[m], fmaf(w01, c[m], w11 * d[m]))) - z);
+    for (int m = 0; m < FE; ++m) out[m] = fmaf(s, fmaf(w00, a[m], fmaf(w10, b[m], fmaf(w01, c[m], w11 * d[m]))), sz);
   } else {
     load_f32<FE>(g.f32 + v00 * F + f0, a);
     load_f32<FE>(g.f32 + (v00 + 1) * F + f0, b);
@@ -188,7 +202,10 @@ struct Bc1Pal {
   float pal[4][3];  // weight order
 };
 
-__device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep) {
+// tab (optional): tab[c] = c / 255 as float32 (correctly rounded), replacing the division.
+__device__ __forceinline__ float unit8(int c, const float* tab) { return tab ? tab[c] : (float)c / 255.0f; }
+
+__device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep, const float* tab = nullptr) {
   const int r0 = quant_bits(ep[0], 31.0f), g0 = quant_bits(ep[1], 63.0f), b0 = quant_bits(ep[2], 31.0f);
   const int r1 = quant_bits(ep[3], 31.0f), g1 = quant_bits(ep[4], 63.0f), b1 = quant_bits(ep[5], 31.0f);
   uint32_t c0 = ((uint32_t)r0 << 11) | ((uint32_t)g0 << 5) | (uint32_t)b0;
@@ -205,10 +222,10 @@ __device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep) {
   const int b[3] = {expand5d((c1 >> 11) & 31), expand6d((c1 >> 5) & 63), expand5d(c1 & 31)};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    p.pal[0][c] = (float)a[c] / 255.0f;
-    p.pal[1][c] = (float)((2 * a[c] + b[c] + 1) / 3) / 255.0f;
-    p.pal[2][c] = (float)((a[c] + 2 * b[c] + 1) / 3) / 255.0f;
-    p.pal[3][c] = (float)b[c] / 255.0f;
+    p.pal[0][c] = unit8(a[c], tab);
+    p.pal[1][c] = unit8((2 * a[c] + b[c] + 1) / 3, tab);
+    p.pal[2][c] = unit8((a[c] + 2 * b[c] + 1) / 3, tab);
+    p.pal[3][c] = unit8(b[c], tab);
   }
   return p;
 }
@@ -236,7 +253,7 @@ struct Bc4Pal {
   float pal[8];  // weight order
 };
 
-__device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep) {
+__device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep, const float* tab = nullptr) {
   Bc4Pal p;
   p.e0 = quant_bits(ep[0], 255.0f);
   p.e1 = quant_bits(ep[1], 255.0f);
@@ -256,7 +273,7 @@ __device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep) {
     for (int j = 1; j <= 4; ++j) v[1 + j] = ((5 - j) * p.e0 + j * p.e1 + 2) / 5;
   }
 #pragma unroll
-  for (int n = 0; n < 8; ++n) p.pal[n] = (float)v[n] / 255.0f;
+  for (int n = 0; n < 8; ++n) p.pal[n] = unit8(v[n], tab);
   return p;
 }
 

@@ -19,6 +19,8 @@
 //
 // Weights (A operands) are read from the packed copy in the workspace, each lane's operand being one
 // contiguous 16-byte (BF16) or 4-byte (FP32) load; the copy is made by k_pack_weights on every call.
+#include <algorithm>
+
 #include "common.h"
 #include "device.h"
 
@@ -29,6 +31,9 @@ using namespace ntbc;
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 mk4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) { return u32x4{a, b, c, d}; }
 
 constexpr int kMaxLayers = 5;
 constexpr int kWaves = 2;  // waves per workgroup
@@ -131,10 +136,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t wg, int64_t nwg) {
 
 __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
 
+// Sigmoid with the hardware exp2 and reciprocal (each within ~1 ulp): |error| < 3e-7 for |z| < 64.
+__device__ __forceinline__ float sigmoid_fast(float z) {
+  const float e = __builtin_amdgcn_exp2f(-z * 1.4426950408889634f);
+  return __builtin_amdgcn_rcpf(1.0f + e);
+}
+
 // Packs the blocks of the wave's P positions from the sigmoid heads in LDS (y: [P][head_stride]).
 // Lane layout: position j = lane % P, texel group q = lane / P handles texels q*TPL .. q*TPL+TPL-1.
 template <int P>
-__device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int lane, int64_t pos0) {
+__device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int lane, int64_t pos0,
+                            const float* tab = nullptr) {
   constexpr int LPP = 64 / P;   // lanes per position
   constexpr int TPL = 16 / LPP; // texels per lane
   const int j = lane % P, q = lane / P;
@@ -146,7 +158,7 @@ __device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int
     const float* col = yj + a.endpoint_dim + a.ch_off[t];
     uint64_t bits;
     if (a.formats[t] == NTBC_BC1) {
-      const dev::Bc1Pal p = dev::bc1_from_heads(ep);
+      const dev::Bc1Pal p = dev::bc1_from_heads(ep, tab);
       uint32_t codes = 0;
 #pragma unroll
       for (int i = 0; i < TPL; ++i) {
@@ -158,7 +170,7 @@ __device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int
       for (int o = P; o < 64; o <<= 1) codes |= __shfl_xor(codes, o);
       bits = (uint64_t)p.c0 | ((uint64_t)p.c1 << 16) | ((uint64_t)codes << 32);
     } else {
-      const dev::Bc4Pal p = dev::bc4_from_heads(ep);
+      const dev::Bc4Pal p = dev::bc4_from_heads(ep, tab);
       uint64_t codes = 0;
 #pragma unroll
       for (int i = 0; i < TPL; ++i) {
@@ -291,6 +303,242 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
   }
   __syncthreads();
   pack_blocks<32>(a, y, lane, pos0);
+}
+
+// ------------------------------------------------------------------------------ BF16 kernel, LDS-staged
+// Eight waves (two per SIMD) of 32 block positions each share every weight chunk: a chunk is two
+// output tiles of one layer over the layer's full K, copied global -> registers -> LDS one chunk ahead
+// of its use (double buffer), so each weight byte crosses L2 once per 256 positions.  The per-value
+// work between the matrix products is kept to a few instructions: biases come from LDS, conversion to
+// bfloat16 is v_cvt_pk_bf16_f32 (round to nearest even) and the ReLU is a packed 16-bit integer max
+// on the bfloat16 pairs (a negative bfloat16 is a negative int16).  The head layer keeps its
+// accumulators in registers; the sigmoid heads are staged in LDS in two halves of 16 positions per
+// wave for the BC epilogue, which reads code/255 from an LDS table.
+constexpr int kHeadTiles = 6;
+constexpr int kMaxChunks = 32;
+constexpr int kLdsWaves = 8;
+constexpr int kMaxBias = 2048;
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef short i16x2_t __attribute__((ext_vector_type(2)));
+
+template <int PR, int NT>
+__device__ __forceinline__ void chunk_load(u32x4 (&pref)[PR], const u32x4* __restrict__ wp, int64_t src, int len, int tid) {
+#pragma unroll
+  for (int r = 0; r < PR; ++r) pref[r] = wp[src + min(tid + NT * r, len - 1)];
+}
+
+template <int PR, int NT>
+__device__ __forceinline__ void chunk_store(const u32x4 (&pref)[PR], u32x4* dst, int len, int tid) {
+#pragma unroll
+  for (int r = 0; r < PR; ++r)
+    if (tid + NT * r < len) dst[tid + NT * r] = pref[r];
+}
+
+// Direct global -> LDS copy of a weight chunk (global_load_lds_dwordx4): element e = tid + NT*r goes
+// to dst[e]; within a wave the 64 lanes write 64 consecutive 16-byte slots from the wave's LDS base.
+// The copy completes at the next s_waitcnt vmcnt(0).
+template <int PR, int NT>
+__device__ __forceinline__ void chunk_dma(const u32x4* __restrict__ wp, int64_t src, int len, u32x4* dst, int tid) {
+  const int wave_base = tid & ~63;
+#pragma unroll
+  for (int r = 0; r < PR; ++r) {
+    const int e = tid + NT * r;
+    if (e < len)
+      __builtin_amdgcn_global_load_lds(wp + src + e, (__attribute__((address_space(3))) void*)(dst + wave_base + NT * r),
+                                       16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+struct ChunkTable {
+  int n;
+  int64_t src[kMaxChunks];  // u32x4 offset in the packed weights
+  int len[kMaxChunks];      // u32x4 count
+  int n_bias;               // padded biases of all layers (floats)
+};
+
+// Two floats -> two bfloat16 (round to nearest even) in one 32-bit word.
+__device__ __forceinline__ uint32_t cvt_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
+
+// ReLU of two bfloat16 in one word: max as signed 16-bit integers against 0.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2_t, x), i16x2_t{0, 0}));
+}
+
+__device__ __forceinline__ u32x4 bf16x8_of(const float* v) {
+  return mk4(cvt_bf16x2(v[0], v[1]), cvt_bf16x2(v[2], v[3]), cvt_bf16x2(v[4], v[5]), cvt_bf16x2(v[6], v[7]));
+}
+
+__device__ __forceinline__ f32x16_t mfma_bf16(const u32x4& a, const u32x4& b, const f32x16_t& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+
+// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, bfloat16: the two
+// B-operand words of K-steps 2t and 2t+1 of the next layer.
+__device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float* bt, int g, u32x4* lo, u32x4* hi) {
+  uint32_t w[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+    w[2 * q] = relu_bf16x2(cvt_bf16x2(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
+    w[2 * q + 1] = relu_bf16x2(cvt_bf16x2(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
+  }
+  *lo = mk4(w[0], w[1], w[2], w[3]);
+  *hi = mk4(w[4], w[5], w[6], w[7]);
+}
+
+template <int HID, int KS0>
+__global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, ChunkTable ct) {
+  constexpr int S = HID / 16;
+  constexpr int T = HID / 32;
+  constexpr int CH = 2 * S * 64;                       // u32x4 per chunk buffer
+  constexpr int NT = 64 * kLdsWaves;                    // threads
+  constexpr int PR = (CH + NT - 1) / NT;                // prefetch registers per thread
+  extern __shared__ u32x4 smem[];
+  float* tab = reinterpret_cast<float*>(smem + 2 * CH);
+  float* bias_s = tab + 256;
+  float* ybase = bias_s + kMaxBias;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int j = lane & 31, g = lane >> 5;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t pos0 = a.first + (tile * kLdsWaves + wave) * 32;
+  const int64_t last = a.first + a.n - 1;
+  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
+  const u32x4* wp = reinterpret_cast<const u32x4*>(a.wpack);
+
+  for (int i = tid; i < 256; i += NT) tab[i] = (float)i / 255.0f;
+  for (int i = tid; i < ct.n_bias; i += NT) bias_s[i] = a.bias[i];
+  chunk_dma<PR, NT>(wp, ct.src[0], ct.len[0], smem, tid);
+
+  // grid features: the first layer's B operands
+  u32x4 x0[KS0];
+#pragma unroll
+  for (int s = 0; s < KS0; ++s) {
+    float v[8];
+    dev::features<8>(a.grid, 16 * s + 8 * g, bx, by, v);
+    x0[s] = bf16x8_of(v);
+  }
+  wait_dma();
+  __syncthreads();
+
+  int c = 0;
+  u32x4 bin[S];
+  {
+    const float* bl = bias_s + a.bias_off[0];
+#pragma unroll
+    for (int tp = 0; tp < T / 2; ++tp) {
+      const bool more = c + 1 < ct.n;
+      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      const u32x4* wb = smem + (c & 1) * CH;
+      f32x16_t acc0 = f32x16_t{}, acc1 = f32x16_t{};
+#pragma unroll
+      for (int s = 0; s < KS0; ++s) {
+        acc0 = mfma_bf16(wb[s * 64 + lane], x0[s], acc0);
+        acc1 = mfma_bf16(wb[(KS0 + s) * 64 + lane], x0[s], acc1);
+      }
+      hidden_epilogue(acc0, bl + 64 * tp, g, &bin[4 * tp], &bin[4 * tp + 1]);
+      hidden_epilogue(acc1, bl + 64 * tp + 32, g, &bin[4 * tp + 2], &bin[4 * tp + 3]);
+      wait_dma();
+      __syncthreads();
+      ++c;
+    }
+  }
+  for (int layer = 1; layer < a.n_layers - 1; ++layer) {
+    const float* bl = bias_s + a.bias_off[layer];
+    u32x4 bout[S];
+#pragma unroll
+    for (int tp = 0; tp < T / 2; ++tp) {
+      const bool more = c + 1 < ct.n;
+      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      const u32x4* wb = smem + (c & 1) * CH;
+      f32x16_t acc0 = f32x16_t{}, acc1 = f32x16_t{};
+      u32x4 n0 = wb[lane], n1 = wb[S * 64 + lane];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const u32x4 w0 = n0, w1 = n1;
+        if (s + 1 < S) {
+          n0 = wb[(s + 1) * 64 + lane];
+          n1 = wb[(S + s + 1) * 64 + lane];
+        }
+        acc0 = mfma_bf16(w0, bin[s], acc0);
+        acc1 = mfma_bf16(w1, bin[s], acc1);
+        asm volatile("" ::: "memory");  // A fragments are read one K-step ahead, no further
+      }
+      hidden_epilogue(acc0, bl + 64 * tp, g, &bout[4 * tp], &bout[4 * tp + 1]);
+      hidden_epilogue(acc1, bl + 64 * tp + 32, g, &bout[4 * tp + 2], &bout[4 * tp + 3]);
+      wait_dma();
+      __syncthreads();
+      ++c;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  // head layer, accumulators kept for the BC epilogue
+  const int layer = a.n_layers - 1;
+  const int ks = S;
+  const int nht = a.otiles[layer];
+  const float* bl = bias_s + a.bias_off[layer];
+  f32x16_t hacc[kHeadTiles];
+#pragma unroll
+  for (int t = 0; t < kHeadTiles; ++t) hacc[t] = f32x16_t{};
+#pragma unroll
+  for (int tp = 0; tp < kHeadTiles / 2; ++tp) {
+    if (2 * tp < nht) {
+      const bool more = c + 1 < ct.n;
+      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      const u32x4* wb = smem + (c & 1) * CH;
+      const bool two = 2 * tp + 1 < nht;
+      u32x4 n0 = wb[lane], n1 = two ? wb[ks * 64 + lane] : n0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s < ks) {
+          const u32x4 w0 = n0, w1 = n1;
+          if (s + 1 < ks) {
+            n0 = wb[(s + 1) * 64 + lane];
+            if (two) n1 = wb[(ks + s + 1) * 64 + lane];
+          }
+          hacc[2 * tp] = mfma_bf16(w0, bin[s], hacc[2 * tp]);
+          if (two) hacc[2 * tp + 1] = mfma_bf16(w1, bin[s], hacc[2 * tp + 1]);
+          asm volatile("" ::: "memory");
+        }
+      }
+      wait_dma();
+      __syncthreads();
+      ++c;
+    }
+  }
+  // sigmoid heads -> LDS, 16 positions at a time, then pack
+  float* y = ybase + wave * 16 * a.head_stride;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if ((j >> 4) == half) {
+#pragma unroll
+      for (int t = 0; t < kHeadTiles; ++t) {
+        if (t < nht) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int n0 = 32 * t + 8 * q + 4 * g;
+            const float4 b = *reinterpret_cast<const float4*>(bl + n0);
+            const float bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (n0 + r < a.head_dim) y[(j & 15) * a.head_stride + n0 + r] = sigmoid_fast(hacc[t][4 * q + r] + bv[r]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    pack_blocks<16>(a, y, lane, pos0 + 16 * half, tab);
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------------------------ FP32 kernel
@@ -508,6 +756,16 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   a.grid.blocks_w = s.blocks_w;
   a.grid.blocks_h = s.blocks_h;
   for (int l = 0; l <= s.n_levels; ++l) a.grid.level_offset[l] = s.level_offset[l];
+  auto pow2_shift = [&](int blocks) {
+    const int64_t den = 2 * (int64_t)blocks;
+    const int64_t top = (int64_t)s.base_res << (s.n_levels - 1);
+    if ((den & (den - 1)) != 0 || (2 * (int64_t)blocks + 1) * top >= (1ll << 31) || top * den >= (1ll << 31)) return -1;
+    int sh = 0;
+    while ((1ll << sh) < den) ++sh;
+    return sh;
+  };
+  a.grid.shift_x = pow2_shift(s.blocks_w);
+  a.grid.shift_y = pow2_shift(s.blocks_h);
   a.wpack = wpack;
   a.bias = bias;
   for (int k = 0; k < s.n_layers; ++k) {
@@ -533,6 +791,43 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   a.heads = heads_out;
 
   const int ppw = p.positions_per_wave;
+  if (precision == NTBC_BF16 && p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2) {
+    ChunkTable ct{};
+    for (int k = 0; k < s.n_layers && ct.n < kMaxChunks; ++k) {
+      for (int t0 = 0; t0 < p.otiles[k]; t0 += 2) {
+        const int nt = std::min(2, p.otiles[k] - t0);
+        ct.src[ct.n] = p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64;
+        ct.len[ct.n] = nt * p.ksteps[k] * 64;
+        ++ct.n;
+      }
+    }
+    const int64_t nwg = ceil_div(n_blocks, (int64_t)32 * kLdsWaves);
+    int64_t nb = 0;
+    for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
+    NTBC_REQUIRE(nb <= kMaxBias, "too many biases (%lld) for the LDS kernel", (long long)nb);
+    ct.n_bias = (int)nb;
+    const size_t chunk = (size_t)2 * (p.hid_inst / 16) * 64 * sizeof(uint4);
+    const size_t lds = 2 * chunk + (256 + kMaxBias) * sizeof(float) + (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
+    NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
+    const void* fn = nullptr;
+    void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
+#define NTBC_LDS_INSTANCE(H, K)                                                                       \
+    if (p.hid_inst == H && p.ksteps[0] == K) {                                                       \
+      fn = (const void*)k_infer_bf16_lds<H, K>;                                                      \
+      launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
+        hipLaunchKernelGGL((k_infer_bf16_lds<H, K>), gr, bl, sh, st, x, y);                          \
+      };                                                                                             \
+    }
+    NTBC_LDS_INSTANCE(64, 1) NTBC_LDS_INSTANCE(64, 2) NTBC_LDS_INSTANCE(64, 3) NTBC_LDS_INSTANCE(64, 4)
+    NTBC_LDS_INSTANCE(128, 1) NTBC_LDS_INSTANCE(128, 2) NTBC_LDS_INSTANCE(128, 3) NTBC_LDS_INSTANCE(128, 4)
+    NTBC_LDS_INSTANCE(256, 1) NTBC_LDS_INSTANCE(256, 2) NTBC_LDS_INSTANCE(256, 3) NTBC_LDS_INSTANCE(256, 4)
+#undef NTBC_LDS_INSTANCE
+    NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
+    NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const dim3 grid((unsigned)nwg), block(64 * kLdsWaves);
+    launch(grid, block, lds, strm, a, ct);
+    return check_launch("ntbc_infer_blocks");
+  }
   const int64_t nwg = ceil_div(n_blocks, (int64_t)ppw * kWaves);
   const size_t lds = (size_t)kWaves * ppw * a.head_stride * sizeof(float);
   const dim3 grid((unsigned)nwg), block(64 * kWaves);

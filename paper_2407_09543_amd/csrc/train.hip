@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       float v = acc[i][j];
       float* out = g.c + (int64_t)m * g.ldc + n;
       if (EPI == EPI_BIAS_RELU) {
-        *out = fmaxf(v + g.bias[n], 0.0f);
+        const float z = v + g.bias[n];
+        *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
       } else if (EPI == EPI_BIAS_SIGMOID) {
         *out = 1.0f / (1.0f + expf(-(v + g.bias[n])));
       } else if (EPI == EPI_MASK) {
@@ -547,6 +548,14 @@ __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
     atomicAdd(&a.losses[3], lcdc * a.inv_nc);
     if (anybad) atomicExch(&a.losses[4], 1.0f);
   }
+}
+
+// Sets flag[0] = 1 if any of x[0..n) is not finite.
+__global__ void k_check_finite(const float* __restrict__ x, int64_t n, float* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicExch(flag, 1.0f);
 }
 
 // ------------------------------------------------------------------------------------------ Adam
@@ -905,6 +914,8 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   if (st != NTBC_OK) return st;
   st = backward(c, tsd->grid, tsd->weights, qat, batch_ids, tsd->d_grid, tsd->d_weights);
   if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 1024)), dim3(256), 0,
+                     c.strm, tsd->d_weights, s.n_weights, losses_out + 4);
   // learning rates of this step: linear warm-up, then cosine annealing to 0
   auto lr_at = [&](double lr0) {
     if (step < h->warmup) return lr0 * (double)(step + 1) / h->warmup;

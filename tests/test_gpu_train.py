@@ -55,9 +55,10 @@ def test_forward_heads(which, qat):
     assert dy <= 1e-5
 
 
-def _near_tie_positions(pb, y, ids, gap=1e-4):
-    """Positions where some texel's two smallest decoded-colour distances (either branch) are within
-    `gap`: there the float32 and float64 argmax may differ."""
+def _near_tie_positions(pb, y, ids, gap=1e-6):
+    """Positions where some texel's two smallest decoded-colour distances (either branch) differ by
+    less than `gap` but are not equal (equal distances to equal palette entries are harmless): there
+    the float32 and float64 argmax may differ."""
     lay, tg = pb.tg_oracle.lay, pb.tg_oracle
     n = len(ids)
     bad = np.zeros(n, dtype=bool)
@@ -72,7 +73,8 @@ def _near_tie_positions(pb, y, ids, gap=1e-4):
         for dist in (np.sqrt(((c[:, :, None, :] - ph[:, None]) ** 2).sum(-1)),
                      np.sqrt(((c_hat[:, :, None, sl] - pr[:, None]) ** 2).sum(-1))):
             s = np.sort(dist, axis=2)
-            bad |= ((s[:, :, 1] - s[:, :, 0]) < gap).any(axis=1)
+            g = s[:, :, 1] - s[:, :, 0]
+            bad |= ((g > 0) & (g < gap)).any(axis=1)
         if f == 4:
             bad |= np.abs(e0[:, 0] - e1[:, 0]) < gap          # BC4 mode switch of the prediction
     return bad
@@ -95,7 +97,7 @@ def test_loss_grad(which):
     err = np.abs(dh - dy_or)[keep]
     scale = np.abs(dy_or).max()
     log(f"  dY: kept {keep.sum()}/{len(keep)} positions, max|d dY| {err.max():.3g} (max|dY| {scale:.3g})")
-    assert keep.mean() > 0.95
+    assert keep.mean() > 0.98
     assert err.max() <= 1e-4 * scale
 
 
