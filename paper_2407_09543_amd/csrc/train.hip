@@ -77,14 +77,28 @@ struct LevelArgs {
   int64_t begin[NTBC_MAX_LEVELS], count[NTBC_MAX_LEVELS];  // in floats
 };
 
-// Per-level min/max of the master grid: blockIdx.y = level, block-reduced, one atomic per block.
-__global__ void __launch_bounds__(kBlock) k_level_minmax(const float* __restrict__ g, LevelArgs la, int* __restrict__ stats) {
-  const int l = blockIdx.y;
-  if (l >= la.n_levels) return;
-  const int64_t n = la.count[l];
-  const float* p = g + la.begin[l];
+// Per-level min/max of the master grid.  Block b handles a contiguous slice of one level (blocks are
+// assigned to levels in proportion to their sizes by the host); the block reduces in LDS and issues
+// one atomic pair.
+struct MinMaxArgs {
+  const float* g;
+  int n_levels;
+  int64_t begin[NTBC_MAX_LEVELS], count[NTBC_MAX_LEVELS];
+  int first_block[NTBC_MAX_LEVELS + 1];  // blocks [first_block[l], first_block[l+1]) cover level l
+};
+
+__global__ void __launch_bounds__(kBlock) k_level_minmax(MinMaxArgs a, int* __restrict__ stats) {
+  __shared__ int smin[kBlock / 64], smax[kBlock / 64];
+  int l = 0;
+  while (l + 1 < a.n_levels && (int)blockIdx.x >= a.first_block[l + 1]) ++l;
+  const int nb = a.first_block[l + 1] - a.first_block[l];
+  const int b = blockIdx.x - a.first_block[l];
+  const int64_t n = a.count[l];
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t i0 = (int64_t)b * per, i1 = min(n, i0 + per);
+  const float* p = a.g + a.begin[l];
   int mn = 0x7FFFFFFF, mx = (int)0x80000000;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
     const int o = ordered(p[i]);
     mn = min(mn, o);
     mx = max(mx, o);
@@ -95,6 +109,15 @@ __global__ void __launch_bounds__(kBlock) k_level_minmax(const float* __restrict
     mx = max(mx, __shfl_xor(mx, off));
   }
   if ((threadIdx.x & 63) == 0) {
+    smin[threadIdx.x >> 6] = mn;
+    smax[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      mn = min(mn, smin[w]);
+      mx = max(mx, smax[w]);
+    }
     atomicMin(&stats[l], mn);
     atomicMax(&stats[NTBC_MAX_LEVELS + l], mx);
   }
@@ -167,11 +190,10 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a) {
 }
 
 // d_grid[corner] += w_corner * dX (times the pass-through mask of the corner value with QAT).
-__global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= a.n * a.n_levels) return;
-  const int64_t p = gid / a.n_levels;
-  const int l = (int)(gid % a.n_levels);
+// One position and level per thread.  Levels below `first_level` are skipped (k_scatter_coarse
+// handles them).
+__device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l,
+                                            float* __restrict__ dst, int64_t dst_base) {
   const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int res = a.base_res << l;
@@ -188,15 +210,38 @@ __global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __r
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       if (w[c] == 0.0f) continue;
-      float m = 1.0f;
       if (a.stats) {
         bool inside;
         fake_quant(a.grid[vtx[c] * a.F + f], s, z, &inside);
-        m = inside ? 1.0f : 0.0f;
+        if (!inside) continue;
       }
-      if (m != 0.0f) atomicAdd(&dgrid[vtx[c] * a.F + f], w[c] * df);
+      atomicAdd(&dst[(vtx[c] - dst_base) * a.F + f], w[c] * df);
     }
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid,
+                                                    int first_level) {
+  const int nl = a.n_levels - first_level;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= a.n * nl) return;
+  scatter_one(a, dx, gid / nl, first_level + (int)(gid % nl), dgrid, 0);
+}
+
+// Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a strided share of the
+// batch in LDS, then adds its non-zero sums to the grid gradient -- one global atomic per touched
+// value per block instead of one per position.
+__global__ void __launch_bounds__(kBlock) k_scatter_coarse(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid,
+                                                           int n_coarse) {
+  extern __shared__ float acc[];
+  const int64_t nv = a.level_offset[n_coarse] * a.F;
+  for (int64_t i = threadIdx.x; i < nv; i += kBlock) acc[i] = 0.0f;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.n * n_coarse; e += (int64_t)gridDim.x * kBlock)
+    scatter_one(a, dx, e / n_coarse, (int)(e % n_coarse), acc, 0);
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < nv; i += kBlock)
+    if (acc[i] != 0.0f) atomicAdd(&dgrid[i], acc[i]);
 }
 
 // ------------------------------------------------------------------------------------------ GEMM
@@ -215,22 +260,28 @@ struct GemmArgs {
   int64_t ldm;
 };
 
-// C = A * B with a fused epilogue; 64x64 tiles, 16-deep K slices, 4x4 outputs per thread.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// C = A * B with a fused epilogue on the FP32 matrix cores: 64x64 workgroup tile, 16-deep K slices
+// staged in LDS; wave w computes the 32x32 quadrant (w/2, w%2) as 2x2 v_mfma_f32_16x16x4f32 tiles
+// (operand lane l: row/column l%16, k = l/16; accumulator v of lane l: row 4(l/16)+v, column l%16).
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   constexpr int TM = 64, TN = 64, TK = 16;
   __shared__ __align__(16) float As[TK][TM + 4];
   __shared__ __align__(16) float Bs[TK][TN + 4];
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int kbeg = blockIdx.z * g.k_split;
   const int kend = min(g.K, kbeg + g.k_split);
-  float acc[4][4];
+  f32x4_t acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{};
+  const int li = lane & 15, lk = lane >> 4;
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -258,39 +309,40 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      const float4 av = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
-      const float4 bv = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4]);
-      const float a4[4] = {av.x, av.y, av.z, av.w};
-      const float b4[4] = {bv.x, bv.y, bv.z, bv.w};
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a4[i], b4[j], acc[i][j]);
+    for (int kk = 0; kk < TK; kk += 4) {
+      const float a0 = As[kk + lk][wm * 32 + li], a1 = As[kk + lk][wm * 32 + 16 + li];
+      const float b0 = Bs[kk + lk][wn * 32 + li], b1 = Bs[kk + lk][wn * 32 + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + ty * 4 + i;
-    if (m >= g.M) continue;
+  for (int tm = 0; tm < 2; ++tm) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx * 4 + j;
-      if (n >= g.N) continue;
-      float v = acc[i][j];
-      float* out = g.c + (int64_t)m * g.ldc + n;
-      if (EPI == EPI_BIAS_RELU) {
-        const float z = v + g.bias[n];
-        *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
-      } else if (EPI == EPI_BIAS_SIGMOID) {
-        *out = 1.0f / (1.0f + expf(-(v + g.bias[n])));
-      } else if (EPI == EPI_MASK) {
-        *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
-      } else if (EPI == EPI_ATOMIC) {
-        atomicAdd(out, v);
-      } else {
-        *out = v;
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm * 32 + tm * 16 + 4 * lk + v;
+      if (m >= g.M) continue;
+#pragma unroll
+      for (int tn = 0; tn < 2; ++tn) {
+        const int n = n0 + wn * 32 + tn * 16 + li;
+        if (n >= g.N) continue;
+        const float val = acc[tm][tn][v];
+        float* out = g.c + (int64_t)m * g.ldc + n;
+        if (EPI == EPI_BIAS_RELU) {
+          const float z = val + g.bias[n];
+          *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
+        } else if (EPI == EPI_BIAS_SIGMOID) {
+          *out = 1.0f / (1.0f + expf(-(val + g.bias[n])));
+        } else if (EPI == EPI_MASK) {
+          *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? val : 0.0f;
+        } else if (EPI == EPI_ATOMIC) {
+          atomicAdd(out, val);
+        } else {
+          *out = val;
+        }
       }
     }
   }
@@ -303,16 +355,21 @@ int gemm(const GemmArgs& g, int splits, hipStream_t s) {
   return check_launch("k_gemm");
 }
 
-// db[n] += sum over rows of dz[m][n]
+// db[n] += sum over rows of dz[m][n]: a block covers 64 columns of a slice of rows; its four waves
+// take every fourth row (coalesced 64-float row segments), then combine in LDS.
 __global__ void __launch_bounds__(kBlock) k_colsum(const float* __restrict__ dz, int64_t rows, int cols, int rows_per_block,
                                              float* __restrict__ db) {
+  __shared__ float part[4][64];
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(rows, r0 + rows_per_block);
-  for (int c = threadIdx.x; c < cols; c += kBlock) {
-    float acc = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) acc += dz[r * cols + c];
-    atomicAdd(&db[c], acc);
-  }
+  float acc = 0.0f;
+  if (c < cols)
+    for (int64_t r = r0 + rg; r < r1; r += 4) acc += dz[r * cols + c];
+  part[rg][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (rg == 0 && c < cols) atomicAdd(&db[c], part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x]);
 }
 
 __global__ void k_dsigmoid(const float* __restrict__ dy, const float* __restrict__ y, float* __restrict__ dz, int64_t n) {
@@ -335,21 +392,26 @@ struct LossArgs {
   float* losses;         // [5]
 };
 
-// Palette coefficients of logical index n (Eq. palette, Eq. weightBC4): c_n = a e0 + b e1 + k.
+// Palette coefficients of logical index n (Eq. palette, Eq. weightBC4): c_n = a e0 + b e1 + k, with
+// the weights w_n = n/3 (BC1), n/7 (BC4, e0 > e1) or (n-1)/5 plus the constants 0 and 1 (BC4, e0 <= e1).
+__constant__ float kW1[4] = {0.0f, 1.0f / 3.0f, 2.0f / 3.0f, 1.0f};
+__constant__ float kW8[8] = {0.0f, 1.0f / 7.0f, 2.0f / 7.0f, 3.0f / 7.0f, 4.0f / 7.0f, 5.0f / 7.0f, 6.0f / 7.0f, 1.0f};
+__constant__ float kW6[8] = {0.0f, 0.0f, 0.2f, 0.4f, 0.6f, 0.8f, 1.0f, 0.0f};
+
 __device__ __forceinline__ void palette_coef(bool bc1, bool eight, int n, float* a, float* b, float* k) {
   *k = 0.0f;
   if (bc1) {
-    *b = (float)n / 3.0f;
+    *b = kW1[n];
     *a = 1.0f - *b;
   } else if (eight) {
-    *b = (float)n / 7.0f;
+    *b = kW8[n];
     *a = 1.0f - *b;
   } else if (n == 0 || n == 7) {
     *a = 0.0f;
     *b = 0.0f;
     *k = n == 7 ? 1.0f : 0.0f;
   } else {
-    *b = (float)(n - 1) / 5.0f;
+    *b = kW6[n];
     *a = 1.0f - *b;
   }
 }
@@ -376,14 +438,15 @@ __device__ __forceinline__ void cd_term(const float* dist, int N, const float (*
   }
   float s[8], tot = 0.0f;
   for (int n = 0; n < N; ++n) {
-    s[n] = expf(-(dist[n] - dmin) * inv_t);
+    s[n] = __expf(-(dist[n] - dmin) * inv_t);
     tot += s[n];
   }
+  const float inv_tot = 1.0f / tot;
   float xs[CH];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) xs[ch] = 0.0f;
   for (int n = 0; n < N; ++n) {
-    s[n] /= tot;
+    s[n] *= inv_tot;
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) xs[ch] += s[n] * pr[n][ch];
   }
@@ -395,9 +458,12 @@ __device__ __forceinline__ void cd_term(const float* dist, int N, const float (*
   }
 }
 
+// Losses and head gradients of one texture of one position, for texels 4*sub .. 4*sub+3 (four lanes
+// share a position/texture).  Returns the partial endpoint gradients in de0/de1; lane sub == 0 also
+// carries the L_e term.  The caller combines the four lanes and writes the endpoint gradients.
 template <int CH>
-__device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float* le, float* lc, float* lcde,
-                             float* lcdc, bool* bad) {
+__device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int sub, float* le, float* lc, float* lcde,
+                             float* lcdc, bool* bad, float de0[3], float de1[3]) {
   const bool bc1 = CH == 3;
   const int N = bc1 ? 4 : 8;
   const float* yp = a.y + p * a.head_dim;
@@ -441,26 +507,28 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float*
       ph[n][ch] = ah * eh0[ch] + bh * eh1[ch] + kh;
     }
   }
-  // L_e
-  float de0[CH], de1[CH];
 #pragma unroll
-  for (int ch = 0; ch < CH; ++ch) {
-    const float d0 = eh0[ch] - er0[ch], d1 = eh1[ch] - er1[ch];
-    *le += d0 * d0 + d1 * d1;
-    de0[ch] = a.w_e * 2.0f * d0 * a.inv_ne;
-    de1[ch] = a.w_e * 2.0f * d1 * a.inv_ne;
-    *bad |= !isfinite(eh0[ch]) || !isfinite(eh1[ch]);
+  for (int ch = 0; ch < 3; ++ch) de0[ch] = de1[ch] = 0.0f;
+  if (sub == 0) {
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      const float d0 = eh0[ch] - er0[ch], d1 = eh1[ch] - er1[ch];
+      *le += d0 * d0 + d1 * d1;
+      de0[ch] = a.w_e * 2.0f * d0 * a.inv_ne;
+      de1[ch] = a.w_e * 2.0f * d1 * a.inv_ne;
+      *bad |= !isfinite(eh0[ch]) || !isfinite(eh1[ch]);
+    }
   }
   const uint8_t* tex = a.tex[t];
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 4 * sub; i < 4 * sub + 4; ++i) {
     const uint8_t* tp = tex + (int64_t)(4 * by + i / 4) * pitch + (int64_t)(4 * bx + i % 4) * CH;
     float c[CH], chat[CH], dchat[CH];
     const int ci = a.E + i * a.C + a.ch_off[t];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-      c[ch] = (float)tp[ch] / 255.0f;
+      c[ch] = (float)tp[ch] * (1.0f / 255.0f);
       chat[ch] = yp[ci + ch];
       const float d = chat[ch] - c[ch];
       *lc += d * d;
@@ -481,7 +549,7 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float*
     cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcde, dd);
     for (int n = 0; n < N; ++n) {
       if (dist[n] <= 0.0f) continue;
-      const float g = a.w_cde * dd[n] / dist[n];
+      const float g = a.w_cde * dd[n] * __frcp_rn(dist[n]);
 #pragma unroll
       for (int ch = 0; ch < CH; ++ch) {
         const float u = g * (c[ch] - ph[n][ch]);
@@ -502,7 +570,7 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float*
     cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcdc, dd);
     for (int n = 0; n < N; ++n) {
       if (dist[n] <= 0.0f) continue;
-      const float g = a.w_cdc * dd[n] / dist[n];
+      const float g = a.w_cdc * dd[n] * __frcp_rn(dist[n]);
 #pragma unroll
       for (int ch = 0; ch < CH; ++ch) dchat[ch] -= g * (chat[ch] - pr[n][ch]);
     }
@@ -512,26 +580,45 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, float*
       *bad |= !isfinite(dchat[ch]);
     }
   }
-#pragma unroll
-  for (int ch = 0; ch < CH; ++ch) {
-    dyp[e + ch] = de0[ch];
-    dyp[e + CH + ch] = de1[ch];
-    *bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
-  }
 }
 
+// Four lanes per (position, texture).
 __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int sub = (int)(gid & 3);
+  const int64_t pt = gid >> 2;
   float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
+  float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
   bool bad = false;
-  if (gid < a.n * a.n_textures) {
-    const int64_t p = gid / a.n_textures;
-    const int t = (int)(gid % a.n_textures);
+  const bool active = pt < a.n * a.n_textures;
+  int64_t p = 0;
+  int t = 0;
+  if (active) {
+    p = pt / a.n_textures;
+    t = (int)(pt % a.n_textures);
     const int id = clamp_id(a.ids[p], a.n_positions);
     if (a.formats[t] == NTBC_BC1)
-      texture_loss<3>(a, p, t, id, &le, &lc, &lcde, &lcdc, &bad);
+      texture_loss<3>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
     else
-      texture_loss<1>(a, p, t, id, &le, &lc, &lcde, &lcdc, &bad);
+      texture_loss<1>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
+  }
+  // combine the endpoint gradients of the four lanes (uniform shuffles)
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+      de0[ch] += __shfl_xor(de0[ch], off);
+      de1[ch] += __shfl_xor(de1[ch], off);
+    }
+  }
+  if (active && sub == 0) {
+    const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
+    float* dyp = a.dy + p * a.head_dim + a.ep_off[t];
+    for (int ch = 0; ch < ch_n; ++ch) {
+      dyp[ch] = de0[ch];
+      dyp[ch_n + ch] = de1[ch];
+      bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -633,11 +720,18 @@ LevelArgs level_args(const Shape& s) {
 
 int qat_range(const Shape& s, const float* grid, int* stats, hipStream_t strm) {
   hipLaunchKernelGGL(k_init_stats, dim3(1), dim3(64), 0, strm, stats);
-  const LevelArgs la = level_args(s);
-  int64_t mx = 0;
-  for (int l = 0; l < s.n_levels; ++l) mx = la.count[l] > mx ? la.count[l] : mx;
-  const unsigned bx = (unsigned)std::min<int64_t>(ceil_div(mx, 256 * 8), 1024);
-  hipLaunchKernelGGL(k_level_minmax, dim3(bx, s.n_levels), dim3(kBlock), 0, strm, grid, la, stats);
+  MinMaxArgs ma{};
+  ma.g = grid;
+  ma.n_levels = s.n_levels;
+  int blocks = 0;
+  for (int l = 0; l < s.n_levels; ++l) {
+    ma.begin[l] = s.level_offset[l] * s.n_features;
+    ma.count[l] = (s.level_offset[l + 1] - s.level_offset[l]) * s.n_features;
+    ma.first_block[l] = blocks;
+    blocks += (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ma.count[l], 8 * kBlock), 2048));
+  }
+  ma.first_block[s.n_levels] = blocks;
+  hipLaunchKernelGGL(k_level_minmax, dim3(blocks), dim3(kBlock), 0, strm, ma, stats);
   hipLaunchKernelGGL(k_qat_params, dim3(1), dim3(64), 0, strm, stats, s.n_levels);
   return check_launch("qat range");
 }
@@ -747,9 +841,9 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     splits = (int)ceil_div(c.n, gw.k_split);
     st = gemm<EPI_ATOMIC>(gw, splits, c.strm);
     if (st != NTBC_OK) return st;
-    const int rpb = 256;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb)), dim3(kBlock), 0, c.strm, dz, c.n, out, rpb,
-                       d_weights + s.b_off[k]);
+    const int rpb = 128;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb), (unsigned)ceil_div(out, 64)), dim3(kBlock), 0, c.strm,
+                       dz, c.n, out, rpb, d_weights + s.b_off[k]);
     st = check_launch("k_colsum");
     if (st != NTBC_OK) return st;
     // dH_k = dZ_k W_k, masked by the ReLU of the layer input (none for the grid features)
@@ -778,8 +872,17 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     nb ^= 1;
   }
   const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * s.n_levels, kBlock)), dim3(kBlock), 0, c.strm, fa, dz,
-                     d_grid);
+  // coarse levels whose gradient fits in 48 KB of LDS are pre-aggregated per block
+  int n_coarse = 0;
+  while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * 4 <= 48 * 1024) ++n_coarse;
+  if (n_coarse > 0) {
+    const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * sizeof(float);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse, 4 * kBlock), 128));
+    hipLaunchKernelGGL(k_scatter_coarse, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dz, d_grid, n_coarse);
+  }
+  if (n_coarse < s.n_levels)
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * (s.n_levels - n_coarse), kBlock)), dim3(kBlock), 0,
+                       c.strm, fa, dz, d_grid, n_coarse);
   return check_launch("k_scatter");
 }
 
@@ -813,7 +916,7 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   a.inv_ne = (float)(1.0 / ((double)n * s.endpoint_dim));
   a.inv_nc = (float)(1.0 / ((double)n * 16.0 * s.channels));
   a.losses = losses;
-  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)ceil_div(n * s.n_textures, kBlock)), dim3(kBlock), 0, strm, a);
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)ceil_div(4 * n * s.n_textures, kBlock)), dim3(kBlock), 0, strm, a);
   return check_launch("k_loss_grad");
 }
 
