@@ -80,14 +80,50 @@ def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
                       f"({blocks} BC blocks), FP64 heads + packing, {t_used:.1f} s"}
 
 
+def traffic_from_profile(path, kernel_src):
+    """HBM bytes per launch of the inference kernel from a committed counter summary, or None if the
+    summary is missing or was taken on a different kernel source (its sha256 is recorded in it)."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(kernel_src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest or "hbm_bytes_per_launch" not in fields:
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
+def copy_probe(torch, mib=1024, reps=5):
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE/WRITE_SIZE counters."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": mib << 20, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--encode-steps", type=int, default=20000,
+                    help="base training steps of the encode (plus 10%% with grid QAT)")
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--kappa", type=float, default=4.0, help="judge: fall back when SSE > kappa * SSE_ref")
+    ap.add_argument("--no-encode", action="store_true",
+                    help="skip the encode; time inference on random parameters of the same shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -96,9 +132,12 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2407_09543_amd import ntbc, synth
+    from paper_2407_09543_amd import encode, ntbc, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     dev = torch.device("cuda:0")
     cfg = synth.config_paper_scale(args.size)
     log(f"generating {args.size}^2 five-texture material")
@@ -113,16 +152,41 @@ def main():
     ref_psnr = [psnr(ntbc.decode(r, args.size, args.size, f).cpu().numpy(), t.texels)
                 for r, f, t in zip(ref, cfg.formats, mat.textures)]
 
-    # model (random parameters of the paper-scale shape; values do not change the work)
-    layers = synth.init_weights(cfg, 3)
-    rng = np.random.default_rng(3)
-    layers = [(w, (0.3 * rng.standard_normal(len(b))).astype(np.float32)) for w, b in layers]
-    codes, _, _ = synth.random_u8_grid(cfg, 3)
-    scale = (np.full(cfg.n_levels, 0.7 / 128.0)).astype(np.float32)
-    zero = np.full(cfg.n_levels, 128, dtype=np.int32)
-    model = ntbc.Model(ntbc.desc_from_config(cfg), torch.from_numpy(synth.flatten_weights(layers)).to(dev),
-                       torch.from_numpy(codes).to(dev), torch.from_numpy(scale).to(dev),
-                       torch.from_numpy(zero).to(dev))
+    encode_info = None
+    if args.no_encode:
+        # random parameters of the paper-scale shape (inference cost does not depend on values)
+        layers = synth.init_weights(cfg, 3)
+        rng = np.random.default_rng(3)
+        layers = [(w, (0.3 * rng.standard_normal(len(b))).astype(np.float32)) for w, b in layers]
+        codes, _, _ = synth.random_u8_grid(cfg, 3)
+        scale = (np.full(cfg.n_levels, 0.7 / 128.0)).astype(np.float32)
+        zero = np.full(cfg.n_levels, 128, dtype=np.int32)
+        model = ntbc.Model(ntbc.desc_from_config(cfg), torch.from_numpy(synth.flatten_weights(layers)).to(dev),
+                           torch.from_numpy(codes).to(dev), torch.from_numpy(scale).to(dev),
+                           torch.from_numpy(zero).to(dev))
+        model_note = "random parameters of the paper-scale shape (inference cost does not depend on values)"
+    else:
+        log(f"encoding the material: {args.encode_steps} steps + 10% QAT at batch {args.batch}")
+        res = encode.encode_material(tex, cfg, steps=args.encode_steps, batch=args.batch, seed=3,
+                                     precision=ntbc.BF16, kappa=args.kappa, delta=0.0)
+        model = res.model
+        layers = synth.unflatten_weights(cfg, res.weights.cpu().numpy())
+        codes = model.grid.cpu().numpy()
+        scale = model.grid_scale.cpu().numpy()
+        zero = model.grid_zero.cpu().numpy()
+        ntbc_psnr = encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, args.size)
+        judged_psnr = encode.psnr_of_words(res.words, tex, cfg.formats, args.size)
+        bc_bytes = 8 * cfg.n_positions * len(cfg.formats)
+        encode_info = {
+            "seconds": res.seconds, "train_seconds": res.train_seconds, "steps": res.steps, "batch": args.batch,
+            "ms_per_train_step": res.train_seconds * 1e3 / res.steps,
+            "includes": "reference encode of the targets, all training steps, grid quantisation, BF16 "
+                        "inference, per-block judge; textures already in HBM",
+            "psnr_db_ntbc": ntbc_psnr, "psnr_db_after_judge": judged_psnr, "psnr_db_ref_encoder": ref_psnr,
+            "judge": {"kappa": args.kappa, "delta": 0.0, "fallback_blocks": res.fallback_blocks},
+            "model_bytes_bf16_weights": encode.model_bytes(cfg, 2), "bc_bytes": bc_bytes,
+        }
+        model_note = "parameters trained by the encode above"
     n_blocks = cfg.n_positions * len(cfg.formats)
     out_bf = torch.empty((len(cfg.formats), cfg.n_positions), dtype=torch.int64, device=dev)
     out_fp = torch.empty_like(out_bf)
@@ -131,7 +195,6 @@ def main():
     torch.cuda.synchronize()
 
     log(f"timing BF16 inference: {args.steps} steps after {args.warmup} warm-up")
-    torch.cuda.synchronize()
     ms_bf = time_call(lambda: model.infer(ntbc.BF16, out=out_bf, reuse_packed=True), args.steps, args.warmup, torch)
     steps_fp = max(2, args.steps // 4)
     ms_fp = time_call(lambda: model.infer(ntbc.FP32, out=out_fp, reuse_packed=True), steps_fp, 1, torch)
@@ -139,14 +202,18 @@ def main():
     # quality: BF16 vs FP32 blocks, decoded PSNR of each against the texture
     wb, wf = out_bf.cpu().numpy(), out_fp.cpu().numpy()
     identity = float((wb == wf).mean())
-    dpsnr = []
+    dpsnr, psnr_bf, psnr_fp = [], [], []
     for t, (f, m) in enumerate(zip(cfg.formats, mat.textures)):
         pb = psnr(ntbc.decode(out_bf[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
         pf = psnr(ntbc.decode(out_fp[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
+        psnr_bf.append(pb)
+        psnr_fp.append(pf)
         dpsnr.append(abs(pb - pf))
 
     flop = flops_per_position(cfg) * cfg.n_positions
     achieved = flop / (ms_bf * 1e-3) / 1e12
+    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "k_infer_bf16_lds_4096_five_texture_traffic.txt"),
+                                   os.path.join(ROOT, "paper_2407_09543_amd", "csrc", "infer.hip"))
     result = {
         "metric": METRIC,
         "value": n_blocks / (ms_bf * 1e-3),
@@ -165,17 +232,19 @@ def main():
                    "blocks_per_step": n_blocks, "mlp": "64-256x3-162 relu/sigmoid",
                    "grid": "8 levels 8..1024 x 8 uint8", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                     "kernel": "k_infer_bf16<256>", "flop_per_launch": flop},
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
+                     "kernel": "k_infer_bf16_lds<256,4>", "flop_per_launch": flop},
         "fp32": {"blocks_per_s": n_blocks / (ms_fp * 1e-3), "ms_per_step": ms_fp,
                  "tflops": flop / (ms_fp * 1e-3) / 1e12, "frac_fp32_peak": flop / (ms_fp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
         "speedup_bf16_vs_fp32": ms_fp / ms_bf,
         "identity_bf16_vs_fp32": identity,
         "dpsnr_db_bf16_vs_fp32": {"per_texture": dpsnr, "max": max(dpsnr)},
+        "psnr_db_bf16": psnr_bf, "psnr_db_fp32": psnr_fp,
         "ref_encoder": {"ms_per_material": enc_ms, "blocks_per_s": n_blocks / (enc_ms * 1e-3), "psnr_db": ref_psnr},
         "decoder": {"ms_per_material": dec_ms, "blocks_per_s": n_blocks / (dec_ms * 1e-3)},
-        "encode_s_per_material": None,
-        "model_note": "random parameters of the paper-scale shape (inference cost does not depend on values)",
+        "encode_s_per_material": encode_info["seconds"] if encode_info else None,
+        "encode": encode_info,
+        "model_note": model_note,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

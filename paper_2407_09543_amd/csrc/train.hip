@@ -161,71 +161,83 @@ struct FeatArgs {
   float* x;          // [n][L*F]
 };
 
-// One thread per (position, level): four corners, F features each.
+// Grid corners and bilinear weights of position p at level l (Eq. grid lookup, cell-centred).
+struct Tap {
+  int64_t vtx[4];
+  float w[4];
+};
+
+__device__ __forceinline__ Tap grid_tap(const FeatArgs& a, int64_t p, int l) {
+  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int res = a.base_res << l;
+  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+  const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
+  Tap t;
+  t.vtx[0] = v00;
+  t.vtx[1] = v00 + 1;
+  t.vtx[2] = v00 + res;
+  t.vtx[3] = v00 + res + 1;
+  t.w[0] = (1.0f - cx.f) * (1.0f - cy.f);
+  t.w[1] = cx.f * (1.0f - cy.f);
+  t.w[2] = (1.0f - cx.f) * cy.f;
+  t.w[3] = cx.f * cy.f;
+  return t;
+}
+
+// One thread per (position, level, feature); the F lanes of a (position, level) read the F
+// consecutive features of each corner together.
 __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= a.n * a.n_levels) return;
-  const int64_t p = gid / a.n_levels;
-  const int l = (int)(gid % a.n_levels);
-  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
-  const int bx = id % a.blocks_w, by = id / a.blocks_w;
-  const int res = a.base_res << l;
-  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
-  const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
-  const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
-  const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
+  if (gid >= a.n * a.n_levels * a.F) return;
+  const int f = (int)(gid % a.F);
+  const int64_t pl = gid / a.F;
+  const int64_t p = pl / a.n_levels;
+  const int l = (int)(pl % a.n_levels);
+  const Tap t = grid_tap(a, p, l);
   const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
   const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
-  float* xo = a.x + p * (int64_t)(a.n_levels * a.F) + l * a.F;
-  for (int f = 0; f < a.F; ++f) {
-    float v[4];
+  float v[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float g = a.grid[vtx[c] * a.F + f];
+  for (int c = 0; c < 4; ++c) {
+    const float g = a.grid[t.vtx[c] * a.F + f];
+    bool inside;
+    v[c] = a.stats ? fake_quant(g, s, z, &inside) : g;
+  }
+  a.x[pl * a.F + f] = fmaf(t.w[0], v[0], fmaf(t.w[1], v[1], fmaf(t.w[2], v[2], t.w[3] * v[3])));
+}
+
+// d_grid[corner] += w_corner * dX (times the pass-through mask of the corner value with QAT), for one
+// (position, level, feature).
+__device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l, int f,
+                                            float* __restrict__ dst) {
+  const float df = dx[(p * a.n_levels + l) * a.F + f];
+  if (df == 0.0f) return;
+  const Tap t = grid_tap(a, p, l);
+  const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
+  const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (t.w[c] == 0.0f) continue;
+    if (a.stats) {
       bool inside;
-      v[c] = a.stats ? fake_quant(g, s, z, &inside) : g;
+      fake_quant(a.grid[t.vtx[c] * a.F + f], s, z, &inside);
+      if (!inside) continue;
     }
-    xo[f] = fmaf(w[0], v[0], fmaf(w[1], v[1], fmaf(w[2], v[2], w[3] * v[3])));
+    atomicAdd(&dst[t.vtx[c] * a.F + f], t.w[c] * df);
   }
 }
 
-// d_grid[corner] += w_corner * dX (times the pass-through mask of the corner value with QAT).
-// One position and level per thread.  Levels below `first_level` are skipped (k_scatter_coarse
-// handles them).
-__device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l,
-                                            float* __restrict__ dst, int64_t dst_base) {
-  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
-  const int bx = id % a.blocks_w, by = id / a.blocks_w;
-  const int res = a.base_res << l;
-  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
-  const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
-  const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
-  const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
-  const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
-  const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
-  const float* d = dx + p * (int64_t)(a.n_levels * a.F) + l * a.F;
-  for (int f = 0; f < a.F; ++f) {
-    const float df = d[f];
-    if (df == 0.0f) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (w[c] == 0.0f) continue;
-      if (a.stats) {
-        bool inside;
-        fake_quant(a.grid[vtx[c] * a.F + f], s, z, &inside);
-        if (!inside) continue;
-      }
-      atomicAdd(&dst[(vtx[c] - dst_base) * a.F + f], w[c] * df);
-    }
-  }
-}
-
+// Levels [first_level, n_levels): one thread per (position, level, feature), feature fastest so that
+// the atomics of a corner land in one cache line.
 __global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid,
                                                     int first_level) {
   const int nl = a.n_levels - first_level;
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (gid >= a.n * nl) return;
-  scatter_one(a, dx, gid / nl, first_level + (int)(gid % nl), dgrid, 0);
+  if (gid >= a.n * nl * a.F) return;
+  const int f = (int)(gid % a.F);
+  const int64_t pl = gid / a.F;
+  scatter_one(a, dx, pl / nl, first_level + (int)(pl % nl), f, dgrid);
 }
 
 // Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a strided share of the
@@ -237,8 +249,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter_coarse(FeatArgs a, const flo
   const int64_t nv = a.level_offset[n_coarse] * a.F;
   for (int64_t i = threadIdx.x; i < nv; i += kBlock) acc[i] = 0.0f;
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.n * n_coarse; e += (int64_t)gridDim.x * kBlock)
-    scatter_one(a, dx, e / n_coarse, (int)(e % n_coarse), acc, 0);
+  const int64_t per_pos = (int64_t)n_coarse * a.F;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.n * per_pos; e += (int64_t)gridDim.x * kBlock) {
+    const int64_t p = e / per_pos;
+    const int r = (int)(e - p * per_pos);
+    scatter_one(a, dx, p, r / a.F, r % a.F, acc);
+  }
   __syncthreads();
   for (int64_t i = threadIdx.x; i < nv; i += kBlock)
     if (acc[i] != 0.0f) atomicAdd(&dgrid[i], acc[i]);
@@ -394,62 +410,69 @@ struct LossArgs {
 
 // Palette coefficients of logical index n (Eq. palette, Eq. weightBC4): c_n = a e0 + b e1 + k, with
 // the weights w_n = n/3 (BC1), n/7 (BC4, e0 > e1) or (n-1)/5 plus the constants 0 and 1 (BC4, e0 <= e1).
-__constant__ float kW1[4] = {0.0f, 1.0f / 3.0f, 2.0f / 3.0f, 1.0f};
-__constant__ float kW8[8] = {0.0f, 1.0f / 7.0f, 2.0f / 7.0f, 3.0f / 7.0f, 4.0f / 7.0f, 5.0f / 7.0f, 6.0f / 7.0f, 1.0f};
-__constant__ float kW6[8] = {0.0f, 0.0f, 0.2f, 0.4f, 0.6f, 0.8f, 1.0f, 0.0f};
-
-__device__ __forceinline__ void palette_coef(bool bc1, bool eight, int n, float* a, float* b, float* k) {
-  *k = 0.0f;
-  if (bc1) {
-    *b = kW1[n];
+// n is a compile-time constant after unrolling, so the mode choice becomes two selects.
+template <bool BC1>
+__device__ __forceinline__ void palette_coef(bool eight, int n, float* a, float* b, float* k) {
+  if (BC1) {
+    *b = (float)n * (1.0f / 3.0f);
     *a = 1.0f - *b;
-  } else if (eight) {
-    *b = kW8[n];
-    *a = 1.0f - *b;
-  } else if (n == 0 || n == 7) {
-    *a = 0.0f;
-    *b = 0.0f;
-    *k = n == 7 ? 1.0f : 0.0f;
-  } else {
-    *b = kW6[n];
-    *a = 1.0f - *b;
+    *k = 0.0f;
+    return;
   }
+  const float b8 = (float)n * (1.0f / 7.0f);
+  const float b6 = (n == 0 || n == 7) ? 0.0f : (float)(n - 1) * 0.2f;
+  const float a6 = (n == 0 || n == 7) ? 0.0f : 1.0f - b6;
+  *b = eight ? b8 : b6;
+  *a = eight ? 1.0f - b8 : a6;
+  *k = (!eight && n == 7) ? 1.0f : 0.0f;
 }
 
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Straight-through decoded-colour term for one texel: distances dist[0..N) (d_n = -dist_n), the
-// reference palette pr and the texel colour c.  Adds (x - c)^2 to *loss for the hard choice x and
+// reference palette pr (built from er0, er1 and the mode) and the texel colour c.  Adds (x - c)^2 to *loss for the hard choice x and
 // returns dL/d(d_n) = (1/T) s_n sum_c g_c (pr_n,c - xs_c), g = 2 (x - c) / N_cd, xs = sum_n s_n pr_n.
-template <int CH>
-__device__ __forceinline__ void cd_term(const float* dist, int N, const float (*pr)[3], const float* c, float inv_ncd,
-                                        float inv_t, float* loss, float* dd) {
+template <int CH, int N>
+__device__ __forceinline__ void cd_term(const float* dist, const float (*pr)[3], const float* er0, const float* er1,
+                                        bool eight_ref, const float* c, float inv_ncd, float inv_t, float* loss,
+                                        float* dd) {
+  // hard choice: the first nearest entry k.  Its colour is rebuilt from k with the same operations
+  // that built pr (an indexed read of pr would force the palette out of registers).
   int k = 0;
   float dmin = dist[0];
-  for (int n = 1; n < N; ++n)
-    if (dist[n] < dmin) {
-      dmin = dist[n];
-      k = n;
-    }
+#pragma unroll
+  for (int n = 1; n < N; ++n) {
+    const bool nearer = dist[n] < dmin;
+    dmin = nearer ? dist[n] : dmin;
+    k = nearer ? n : k;
+  }
+  float ak, bk, kk;
+  palette_coef<CH == 3>(eight_ref, k, &ak, &bk, &kk);
   float gx[CH];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) {
-    const float d = pr[k][ch] - c[ch];
+    const float d = (ak * er0[ch] + bk * er1[ch] + kk) - c[ch];
     *loss += d * d;
     gx[ch] = 2.0f * d * inv_ncd;
   }
-  float s[8], tot = 0.0f;
+  float s[N], tot = 0.0f;
+#pragma unroll
   for (int n = 0; n < N; ++n) {
     s[n] = __expf(-(dist[n] - dmin) * inv_t);
     tot += s[n];
   }
-  const float inv_tot = 1.0f / tot;
+  const float inv_tot = fast_rcp(tot);
   float xs[CH];
 #pragma unroll
   for (int ch = 0; ch < CH; ++ch) xs[ch] = 0.0f;
+#pragma unroll
   for (int n = 0; n < N; ++n) {
     s[n] *= inv_tot;
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) xs[ch] += s[n] * pr[n][ch];
   }
+#pragma unroll
   for (int n = 0; n < N; ++n) {
     float acc = 0.0f;
 #pragma unroll
@@ -458,34 +481,36 @@ __device__ __forceinline__ void cd_term(const float* dist, int N, const float (*
   }
 }
 
-// Losses and head gradients of one texture of one position, for texels 4*sub .. 4*sub+3 (four lanes
-// share a position/texture).  Returns the partial endpoint gradients in de0/de1; lane sub == 0 also
-// carries the L_e term.  The caller combines the four lanes and writes the endpoint gradients.
+// Losses and head gradients of one texture of one position, for the texel row `sub` (texels
+// 4*sub .. 4*sub+3; four lanes share a position/texture).  Returns the partial endpoint gradients in
+// de0/de1; lane sub == 0 also carries the L_e term.  The caller combines the four lanes and writes the
+// endpoint gradients.  Non-finite heads show up as non-finite gradients, which the caller checks.
 template <int CH>
-__device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int sub, float* le, float* lc, float* lcde,
+__device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int sub, float* le, float* lc, float* lcde,
                              float* lcdc, bool* bad, float de0[3], float de1[3]) {
-  const bool bc1 = CH == 3;
-  const int N = bc1 ? 4 : 8;
+  constexpr bool bc1 = CH == 3;
+  constexpr int N = bc1 ? 4 : 8;
   const float* yp = a.y + p * a.head_dim;
   float* dyp = a.dy + p * a.head_dim;
   const uint64_t w = a.ref[(int64_t)t * a.n_positions + id];
   float er0[3] = {0, 0, 0}, er1[3] = {0, 0, 0};
   bool eight_ref = true;
+  constexpr float k255 = 1.0f / 255.0f;
   if (bc1) {
     const uint32_t c0 = (uint32_t)(w & 0xFFFF), c1 = (uint32_t)((w >> 16) & 0xFFFF);
-    er0[0] = (float)dev::expand5d((c0 >> 11) & 31) / 255.0f;
-    er0[1] = (float)dev::expand6d((c0 >> 5) & 63) / 255.0f;
-    er0[2] = (float)dev::expand5d(c0 & 31) / 255.0f;
-    er1[0] = (float)dev::expand5d((c1 >> 11) & 31) / 255.0f;
-    er1[1] = (float)dev::expand6d((c1 >> 5) & 63) / 255.0f;
-    er1[2] = (float)dev::expand5d(c1 & 31) / 255.0f;
+    er0[0] = (float)dev::expand5d((c0 >> 11) & 31) * k255;
+    er0[1] = (float)dev::expand6d((c0 >> 5) & 63) * k255;
+    er0[2] = (float)dev::expand5d(c0 & 31) * k255;
+    er1[0] = (float)dev::expand5d((c1 >> 11) & 31) * k255;
+    er1[1] = (float)dev::expand6d((c1 >> 5) & 63) * k255;
+    er1[2] = (float)dev::expand5d(c1 & 31) * k255;
   } else {
     const int b0 = (int)(w & 0xFF), b1 = (int)((w >> 8) & 0xFF);
-    er0[0] = (float)b0 / 255.0f;
-    er1[0] = (float)b1 / 255.0f;
+    er0[0] = (float)b0 * k255;
+    er1[0] = (float)b1 * k255;
     eight_ref = b0 > b1;
   }
-  float pr[8][3], ph[8][3], ca[8], cb[8];
+  float pr[N][3], ph[N][3], ca[N], cb[N];
   const int e = a.ep_off[t];
   float eh0[3], eh1[3];
 #pragma unroll
@@ -494,11 +519,12 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
     eh1[ch] = yp[e + CH + ch];
   }
   const bool eight_hat = bc1 ? true : eh0[0] > eh1[0];
+#pragma unroll
   for (int n = 0; n < N; ++n) {
     float ar, br, kr;
-    palette_coef(bc1, eight_ref, n, &ar, &br, &kr);
+    palette_coef<bc1>(eight_ref, n, &ar, &br, &kr);
     float ah, bh, kh;
-    palette_coef(bc1, eight_hat, n, &ah, &bh, &kh);
+    palette_coef<bc1>(eight_hat, n, &ah, &bh, &kh);
     ca[n] = ah;
     cb[n] = bh;
 #pragma unroll
@@ -516,27 +542,27 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
       *le += d0 * d0 + d1 * d1;
       de0[ch] = a.w_e * 2.0f * d0 * a.inv_ne;
       de1[ch] = a.w_e * 2.0f * d1 * a.inv_ne;
-      *bad |= !isfinite(eh0[ch]) || !isfinite(eh1[ch]);
     }
   }
-  const uint8_t* tex = a.tex[t];
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
-  for (int i = 4 * sub; i < 4 * sub + 4; ++i) {
-    const uint8_t* tp = tex + (int64_t)(4 * by + i / 4) * pitch + (int64_t)(4 * bx + i % 4) * CH;
+  const uint8_t* row = a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+#pragma unroll 1
+  for (int x = 0; x < 4; ++x) {
+    const int i = 4 * sub + x;
     float c[CH], chat[CH], dchat[CH];
     const int ci = a.E + i * a.C + a.ch_off[t];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-      c[ch] = (float)tp[ch] * (1.0f / 255.0f);
+      c[ch] = (float)row[x * CH + ch] * k255;
       chat[ch] = yp[ci + ch];
       const float d = chat[ch] - c[ch];
       *lc += d * d;
       dchat[ch] = a.w_c * 2.0f * d * a.inv_nc;
-      *bad |= !isfinite(chat[ch]);
     }
     // endpoint branch: d_n = -||c - c^_n|| over the palette of the predicted endpoints
-    float dist[8], dd[8];
+    float dist[N], dd[N];
+#pragma unroll
     for (int n = 0; n < N; ++n) {
       float acc = 0.0f;
 #pragma unroll
@@ -544,12 +570,12 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
         const float d = c[ch] - ph[n][ch];
         acc += d * d;
       }
-      dist[n] = sqrtf(acc);
+      dist[n] = fast_sqrt(acc);
     }
-    cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcde, dd);
+    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, lcde, dd);
+#pragma unroll
     for (int n = 0; n < N; ++n) {
-      if (dist[n] <= 0.0f) continue;
-      const float g = a.w_cde * dd[n] * __frcp_rn(dist[n]);
+      const float g = dist[n] > 0.0f ? a.w_cde * dd[n] * fast_rcp(dist[n]) : 0.0f;
 #pragma unroll
       for (int ch = 0; ch < CH; ++ch) {
         const float u = g * (c[ch] - ph[n][ch]);
@@ -558,6 +584,7 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
       }
     }
     // colour branch: d_n = -||c^ - c_n|| over the reference palette
+#pragma unroll
     for (int n = 0; n < N; ++n) {
       float acc = 0.0f;
 #pragma unroll
@@ -565,12 +592,12 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
         const float d = chat[ch] - pr[n][ch];
         acc += d * d;
       }
-      dist[n] = sqrtf(acc);
+      dist[n] = fast_sqrt(acc);
     }
-    cd_term<CH>(dist, N, pr, c, a.inv_nc, a.inv_t, lcdc, dd);
+    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, lcdc, dd);
+#pragma unroll
     for (int n = 0; n < N; ++n) {
-      if (dist[n] <= 0.0f) continue;
-      const float g = a.w_cdc * dd[n] * __frcp_rn(dist[n]);
+      const float g = dist[n] > 0.0f ? a.w_cdc * dd[n] * fast_rcp(dist[n]) : 0.0f;
 #pragma unroll
       for (int ch = 0; ch < CH; ++ch) dchat[ch] -= g * (chat[ch] - pr[n][ch]);
     }
@@ -582,42 +609,56 @@ __device__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int su
   }
 }
 
-// Four lanes per (position, texture).
+// Four lanes per (texture, position), texture-major so that a wave works on one format.  A grid-
+// stride loop over whole waves keeps the shuffles uniform; the loss sums are reduced per block and
+// added with one atomic per block and loss (same-address atomics from every wave serialise in L2).
+constexpr int kLossBlocks = 768;  // about one resident round at three waves per SIMD
+
 __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int sub = (int)(gid & 3);
-  const int64_t pt = gid >> 2;
+  __shared__ float part[kBlock / 64][4];
+  __shared__ int part_bad[kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t per_tex = 4 * a.n;
+  const int64_t total = per_tex * a.n_textures;
   float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
-  float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
   bool bad = false;
-  const bool active = pt < a.n * a.n_textures;
-  int64_t p = 0;
-  int t = 0;
-  if (active) {
-    p = pt / a.n_textures;
-    t = (int)(pt % a.n_textures);
-    const int id = clamp_id(a.ids[p], a.n_positions);
-    if (a.formats[t] == NTBC_BC1)
-      texture_loss<3>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
-    else
-      texture_loss<1>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
-  }
-  // combine the endpoint gradients of the four lanes (uniform shuffles)
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-#pragma unroll
-    for (int off = 1; off < 4; off <<= 1) {
-      de0[ch] += __shfl_xor(de0[ch], off);
-      de1[ch] += __shfl_xor(de1[ch], off);
+  for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < total;
+       base += (int64_t)gridDim.x * kBlock) {
+    const int64_t gid = base + lane;
+    float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
+    const bool active = gid < total;
+    const int t = active ? (int)(gid / per_tex) : 0;
+    const int64_t r = gid - (int64_t)t * per_tex;
+    const int64_t p = r >> 2;
+    const int sub = (int)(r & 3);
+    if (active) {
+      const int id = clamp_id(a.ids[p], a.n_positions);
+      if (a.formats[t] == NTBC_BC1)
+        texture_loss<3>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
+      else
+        texture_loss<1>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
     }
-  }
-  if (active && sub == 0) {
-    const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
-    float* dyp = a.dy + p * a.head_dim + a.ep_off[t];
-    for (int ch = 0; ch < ch_n; ++ch) {
-      dyp[ch] = de0[ch];
-      dyp[ch_n + ch] = de1[ch];
-      bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
+    // combine the endpoint gradients of the four lanes (per_tex is a multiple of 4, so the four
+    // lanes of a (texture, position) sit in one aligned group of the wave)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+      for (int off = 1; off < 4; off <<= 1) {
+        de0[ch] += __shfl_xor(de0[ch], off);
+        de1[ch] += __shfl_xor(de1[ch], off);
+      }
+    }
+    if (active && sub == 0) {
+      const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
+      float* dyp = a.dy + p * a.head_dim + a.ep_off[t];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        if (ch < ch_n) {
+          dyp[ch] = de0[ch];
+          dyp[ch_n + ch] = de1[ch];
+          bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
+        }
+      }
     }
   }
 #pragma unroll
@@ -628,12 +669,23 @@ __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
     lcdc += __shfl_xor(lcdc, off);
   }
   const unsigned long long anybad = __ballot(bad);
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&a.losses[0], le * a.inv_ne);
-    atomicAdd(&a.losses[1], lc * a.inv_nc);
-    atomicAdd(&a.losses[2], lcde * a.inv_nc);
-    atomicAdd(&a.losses[3], lcdc * a.inv_nc);
-    if (anybad) atomicExch(&a.losses[4], 1.0f);
+  if (lane == 0) {
+    part[wave][0] = le;
+    part[wave][1] = lc;
+    part[wave][2] = lcde;
+    part[wave][3] = lcdc;
+    part_bad[wave] = anybad != 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    float s = 0.0f;
+    for (int w = 0; w < kBlock / 64; ++w) s += part[w][threadIdx.x];
+    const float scale = threadIdx.x == 0 ? a.inv_ne : a.inv_nc;
+    atomicAdd(&a.losses[threadIdx.x], s * scale);
+  } else if (threadIdx.x == 4) {
+    int any = 0;
+    for (int w = 0; w < kBlock / 64; ++w) any |= part_bad[w];
+    if (any) atomicExch(&a.losses[4], 1.0f);
   }
 }
 
@@ -788,7 +840,7 @@ int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int
     if (st != NTBC_OK) return st;
   }
   const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, c.ws + c.lay.x);
-  hipLaunchKernelGGL(k_features, dim3((unsigned)ceil_div(c.n * s.n_levels, kBlock)), dim3(kBlock), 0, c.strm, fa);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)ceil_div(c.n * s.n_levels * s.n_features, kBlock)), dim3(kBlock), 0, c.strm, fa);
   st = check_launch("k_features");
   if (st != NTBC_OK) return st;
   for (int k = 0; k < s.n_layers; ++k) {
@@ -877,11 +929,11 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
   while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * 4 <= 48 * 1024) ++n_coarse;
   if (n_coarse > 0) {
     const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * sizeof(float);
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse, 4 * kBlock), 128));
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 128));
     hipLaunchKernelGGL(k_scatter_coarse, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dz, d_grid, n_coarse);
   }
   if (n_coarse < s.n_levels)
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * (s.n_levels - n_coarse), kBlock)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * (s.n_levels - n_coarse) * s.n_features, kBlock)), dim3(kBlock), 0,
                        c.strm, fa, dz, d_grid, n_coarse);
   return check_launch("k_scatter");
 }
@@ -916,7 +968,8 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   a.inv_ne = (float)(1.0 / ((double)n * s.endpoint_dim));
   a.inv_nc = (float)(1.0 / ((double)n * 16.0 * s.channels));
   a.losses = losses;
-  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)ceil_div(4 * n * s.n_textures, kBlock)), dim3(kBlock), 0, strm, a);
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)std::min<int64_t>(ceil_div(4 * n * s.n_textures, kBlock), kLossBlocks)),
+                     dim3(kBlock), 0, strm, a);
   return check_launch("k_loss_grad");
 }
 

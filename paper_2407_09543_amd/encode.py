@@ -29,6 +29,7 @@ class EncodeResult:
     losses: List[np.ndarray]       # sampled training losses (step, L_e, L_c, L_cd_e, L_cd_c)
     seconds: float                 # device-resident textures -> device-resident blocks
     steps: int
+    train_seconds: float           # the training steps alone (HIP events)
 
 
 def encode_material(textures: Sequence[torch.Tensor], cfg, steps: int, batch: int, seed: int = 0,
@@ -52,11 +53,15 @@ def encode_material(textures: Sequence[torch.Tensor], cfg, steps: int, batch: in
     tr = ntbc.Trainer(desc_train, grid0, w0, targets, batch, total)
     ids = torch.empty(batch, dtype=torch.int32, device=dev)
     losses = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
     for s in range(total):
         ntbc.batch_ids(seed, s, batch, cfg.n_positions, out=ids)
         l = tr.step(ids, s, qat=s >= steps)
         if log_every and (s % log_every == 0 or s == total - 1):
             losses.append(np.concatenate([[s], l.cpu().numpy()[:4]]))
+    t_end.record()
     if cfg.grid_u8:
         codes, scale, zero = ntbc.quantize_grid(desc_train, tr.grid)
         model = ntbc.Model(ntbc.desc_from_config(cfg), tr.weights, codes, scale, zero)
@@ -76,7 +81,7 @@ def encode_material(textures: Sequence[torch.Tensor], cfg, steps: int, batch: in
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     return EncodeResult(out, words, ref, [int(c.item()) for c in fb], model, tr.grid, tr.weights, losses, seconds,
-                        total)
+                        total, t_start.elapsed_time(t_end) * 1e-3)
 
 
 def psnr_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats, size: int) -> List[float]:

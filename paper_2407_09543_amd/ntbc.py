@@ -284,6 +284,24 @@ def backward(desc: ModelDesc, grid, weights, ids, d_heads, qat: bool = False, pr
     return dg, dw
 
 
+class NTBCFunction(torch.autograd.Function):
+    """Heads [n, head_dim] as a differentiable function of the FP32 grid and MLP weights.  The
+    backward calls ntbc_backward, which recomputes the forward activations instead of keeping them
+    (Sec. 3.2; the grid gradient is a scatter-add through the bilinear weights, Sec. 3.3 with QAT)."""
+
+    @staticmethod
+    def forward(ctx, grid, weights, ids, desc, qat=False):
+        ctx.desc, ctx.qat = desc, bool(qat)
+        ctx.save_for_backward(grid, weights, ids)
+        return forward(desc, grid, weights, ids, qat)
+
+    @staticmethod
+    def backward(ctx, d_heads):
+        grid, weights, ids = ctx.saved_tensors
+        dg, dw = backward(ctx.desc, grid, weights, ids, d_heads, ctx.qat)
+        return dg, dw, None, None, None
+
+
 class Targets:
     """Reference blocks [n_textures, n_positions] (int64) and the textures (uint8, device)."""
 

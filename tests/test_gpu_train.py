@@ -123,6 +123,24 @@ def test_backward(which, qat):
     assert rg <= 1e-5 and rw <= 1e-5
 
 
+def test_autograd_function_matches_backward():
+    # NTBCFunction wires ntbc_forward/ntbc_backward into autograd: the gradient of sum(heads * G)
+    # equals ntbc_backward with d_heads = G (FP32 atomics: equal up to summation order)
+    pb = _problem("mid", 3)
+    ids, ids_d = pb.ids(9, 2048)
+    rng = np.random.default_rng(9)
+    g_heads = torch.from_numpy((rng.standard_normal((len(ids), pb.cfg.head_dim)) * 1e-3).astype(np.float32)).cuda()
+    grid = pb.grid_d.clone().requires_grad_(True)
+    w = pb.flat_d.clone().requires_grad_(True)
+    y = ntbc.NTBCFunction.apply(grid, w, ids_d, pb.desc, False)
+    y_direct = ntbc.forward(pb.desc, pb.grid_d, pb.flat_d, ids_d)
+    assert torch.equal(y.detach(), y_direct)
+    (y * g_heads).sum().backward()
+    dg, dw = ntbc.backward(pb.desc, pb.grid_d, pb.flat_d, ids_d, g_heads)
+    assert _rel(grid.grad.cpu().numpy(), dg.cpu().numpy().astype(np.float64)) <= 1e-6
+    assert _rel(w.grad.cpu().numpy(), dw.cpu().numpy().astype(np.float64)) <= 1e-6
+
+
 @pytest.mark.parametrize("which", ["small", "mid"])
 def test_end_to_end_gradients(which):
     pb = _problem(which, 4)
