@@ -1,9 +1,11 @@
-"""Rounding to bfloat16 and to FP8 E4M3 (oracle; test infrastructure only).
+"""Rounding to bfloat16, IEEE half precision and FP8 E4M3 (oracle; test infrastructure only).
 
 Used to emulate the reduced-precision MLP paths: values are rounded to the target format with
 round-to-nearest-even directly from their float64 value, then all arithmetic continues in float64.
 
 bfloat16: 8 significant bits, 8 exponent bits (float32's range).
+half (IEEE binary16, the precision the paper runs its networks in): 11 significant bits, smallest
+normal 2^-14, subnormal step 2^-24, largest finite 65504; values that round beyond it become +-inf.
 FP8 E4M3 (OCP "E4M3FN"): 4 significant bits, exponent bias 7, smallest normal 2^-6, subnormal step
 2^-9, largest finite 448, no infinities; conversion saturates to +-448.
 """
@@ -22,6 +24,16 @@ def round_bf16(x):
     e = np.maximum(e, -125)                    # bf16 subnormals share the 2^-133 step
     q = np.ldexp(1.0, e - 8)
     out = _round_to_quantum(x, q)
+    return np.where(x == 0, x, out)
+
+
+def round_fp16(x):
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                         # |x| in [2^(e-1), 2^e)
+    e = np.maximum(e, -13)                     # subnormals share the 2^-24 step
+    q = np.ldexp(1.0, e - 11)
+    out = _round_to_quantum(x, q)
+    out = np.where(np.abs(out) > 65504.0, np.copysign(np.inf, x), out)
     return np.where(x == 0, x, out)
 
 

@@ -10,6 +10,7 @@ Weights are [out][in] float32 arrays, biases [out].  Arithmetic is float64 (``pr
 emulates a reduced-precision matrix path with float64 accumulation:
 
   * ``"bf16"``: every layer input and every weight rounded to bfloat16 (round-to-nearest-even);
+  * ``"fp16"``: the same with IEEE half precision (the paper's network precision);
   * ``"fp8"``: per-layer scales (s_x, s_w); the layer input is rounded to E4M3 as x / s_x, the weight
     as W * (1/s_w) evaluated in float32 (the GPU path's precision for this integer decision), and the
     product is rescaled by s_x * s_w before the bias is added.
@@ -45,6 +46,8 @@ def forward(layers, x, precision: str = "f64", scales=None):
             z = h @ w.T + b
         elif precision == "bf16":
             z = lowp.round_bf16(h) @ lowp.round_bf16(w).T + b
+        elif precision == "fp16":
+            z = lowp.round_fp16(h) @ lowp.round_fp16(w).T + b
         elif precision == "fp8":
             s_x, s_w = float(scales[k][0]), float(scales[k][1])
             xq = lowp.round_e4m3(h / s_x)
