@@ -127,7 +127,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(inference shards by block range with no communication; see the design notes)",
+              "(inference shards by block range with no communication between GPUs)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -188,31 +188,49 @@ def main():
         }
         model_note = "parameters trained by the encode above"
     n_blocks = cfg.n_positions * len(cfg.formats)
-    out_bf = torch.empty((len(cfg.formats), cfg.n_positions), dtype=torch.int64, device=dev)
-    out_fp = torch.empty_like(out_bf)
-    model.infer(ntbc.BF16, out=out_bf)
-    model.infer(ntbc.FP32, out=out_fp)
+    outs = {}
+    for prec in (ntbc.BF16, ntbc.FP16, ntbc.FP32):
+        outs[prec] = torch.empty((len(cfg.formats), cfg.n_positions), dtype=torch.int64, device=dev)
+        model.infer(prec, out=outs[prec])
     torch.cuda.synchronize()
+    out_bf, out_fp = outs[ntbc.BF16], outs[ntbc.FP32]
 
     log(f"timing BF16 inference: {args.steps} steps after {args.warmup} warm-up")
     ms_bf = time_call(lambda: model.infer(ntbc.BF16, out=out_bf, reuse_packed=True), args.steps, args.warmup, torch)
+    model.infer(ntbc.FP16, out=outs[ntbc.FP16])
+    ms_h = time_call(lambda: model.infer(ntbc.FP16, out=outs[ntbc.FP16], reuse_packed=True), args.steps,
+                     args.warmup, torch)
+    model.infer(ntbc.FP32, out=out_fp)
     steps_fp = max(2, args.steps // 4)
     ms_fp = time_call(lambda: model.infer(ntbc.FP32, out=out_fp, reuse_packed=True), steps_fp, 1, torch)
 
-    # quality: BF16 vs FP32 blocks, decoded PSNR of each against the texture
-    wb, wf = out_bf.cpu().numpy(), out_fp.cpu().numpy()
-    identity = float((wb == wf).mean())
-    dpsnr, psnr_bf, psnr_fp = [], [], []
-    for t, (f, m) in enumerate(zip(cfg.formats, mat.textures)):
-        pb = psnr(ntbc.decode(out_bf[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
-        pf = psnr(ntbc.decode(out_fp[t].contiguous(), args.size, args.size, f).cpu().numpy(), m.texels)
-        psnr_bf.append(pb)
-        psnr_fp.append(pf)
-        dpsnr.append(abs(pb - pf))
+    # quality: decoded PSNR of every precision's blocks against the texture, and deltas to FP32
+    sq_err = {}
+    psnrs = {}
+    for prec, words in outs.items():
+        psnrs[prec], sq_err[prec] = [], 0.0
+        for t, (f, m) in enumerate(zip(cfg.formats, mat.textures)):
+            dec = ntbc.decode(words[t].contiguous(), args.size, args.size, f).cpu().numpy()
+            psnrs[prec].append(psnr(dec, m.texels))
+            sq_err[prec] += float(((dec.astype(np.float64) - m.texels.astype(np.float64)) ** 2).sum())
+    n_values = sum(m.texels.size for m in mat.textures)
+
+    def material_psnr(prec):
+        mse = sq_err[prec] / n_values
+        return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+
+    def versus_fp32(prec):
+        d = [abs(a - b) for a, b in zip(psnrs[prec], psnrs[ntbc.FP32])]
+        return {"identity_vs_fp32": float((outs[prec] == out_fp).float().mean().item()),
+                "dpsnr_db_vs_fp32": {"per_texture": d, "max": max(d),
+                                     "material": abs(material_psnr(prec) - material_psnr(ntbc.FP32))}}
+
+    identity = versus_fp32(ntbc.BF16)["identity_vs_fp32"]
+    psnr_bf, psnr_fp = psnrs[ntbc.BF16], psnrs[ntbc.FP32]
 
     flop = flops_per_position(cfg) * cfg.n_positions
     achieved = flop / (ms_bf * 1e-3) / 1e12
-    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "k_infer_bf16_lds_4096_five_texture_traffic.txt"),
+    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "k_infer_lds_bf16_4096_five_texture_traffic.txt"),
                                    os.path.join(ROOT, "paper_2407_09543_amd", "csrc", "infer.hip"))
     result = {
         "metric": METRIC,
@@ -233,13 +251,21 @@ def main():
                    "grid": "8 levels 8..1024 x 8 uint8", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                     "kernel": "k_infer_bf16_lds<256,4>", "flop_per_launch": flop},
+                     "kernel": "k_infer_lds<BF16,256,4>", "flop_per_launch": flop},
         "fp32": {"blocks_per_s": n_blocks / (ms_fp * 1e-3), "ms_per_step": ms_fp,
                  "tflops": flop / (ms_fp * 1e-3) / 1e12, "frac_fp32_peak": flop / (ms_fp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
         "speedup_bf16_vs_fp32": ms_fp / ms_bf,
         "identity_bf16_vs_fp32": identity,
-        "dpsnr_db_bf16_vs_fp32": {"per_texture": dpsnr, "max": max(dpsnr)},
+        "dpsnr_db_bf16_vs_fp32": versus_fp32(ntbc.BF16)["dpsnr_db_vs_fp32"],
         "psnr_db_bf16": psnr_bf, "psnr_db_fp32": psnr_fp,
+        "fp16": dict({"blocks_per_s": n_blocks / (ms_h * 1e-3), "ms_per_step": ms_h,
+                      "frac_fp16_peak": flop / (ms_h * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+                      "psnr_db": psnrs[ntbc.FP16]}, **versus_fp32(ntbc.FP16)),
+        "psnr_db_material": {"bf16": material_psnr(ntbc.BF16), "fp16": material_psnr(ntbc.FP16),
+                             "fp32": material_psnr(ntbc.FP32)},
+        "gate_dpsnr_0p1db": {p: {"per_texture": versus_fp32(v)["dpsnr_db_vs_fp32"]["max"] <= 0.1,
+                                 "material": versus_fp32(v)["dpsnr_db_vs_fp32"]["material"] <= 0.1}
+                             for p, v in (("bf16", ntbc.BF16), ("fp16", ntbc.FP16))},
         "ref_encoder": {"ms_per_material": enc_ms, "blocks_per_s": n_blocks / (enc_ms * 1e-3), "psnr_db": ref_psnr},
         "decoder": {"ms_per_material": dec_ms, "blocks_per_s": n_blocks / (dec_ms * 1e-3)},
         "encode_s_per_material": encode_info["seconds"] if encode_info else None,

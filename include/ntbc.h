@@ -56,6 +56,7 @@ extern "C" {
 #define NTBC_FP32 0               /* MLP in FP32 (FP32 matrix cores), FP32 accumulation             */
 #define NTBC_BF16 1               /* MLP weights and layer inputs in BF16, FP32 accumulation         */
 #define NTBC_FP8_E4M3 2           /* MLP weights and layer inputs in FP8 E4M3 with per-layer scales  */
+#define NTBC_FP16 3               /* MLP weights and layer inputs in IEEE half, FP32 accumulation    */
 
 #define NTBC_GRID_F32 0
 #define NTBC_GRID_U8 1

@@ -8,7 +8,8 @@
 // layout of one layer's output tile is reused directly as the B operand of the next layer, and the
 // next layer's weight columns are permuted on the host side of the kernel (k_pack_weights) to match.
 //
-//   BF16 (v_mfma_f32_32x32x16_bf16, P = 32): lane l holds position j = l%32 and row group g = l/32;
+//   BF16 / FP16 (v_mfma_f32_32x32x16_{bf16,f16}, P = 32): lane l holds position j = l%32 and row
+//     group g = l/32;
 //     accumulator v of output tile t is neuron 32t + 8(v/4) + 4g + v%4.  Values v = 8h..8h+7 of tile
 //     t become the eight B-operand values of K-step s = 2t+h; so K-step s, lane group g, element m
 //     of a hidden layer's input is neuron 32(s/2) + 16(s%2) + 8(m/4) + 4g + m%4.  The first layer's
@@ -18,7 +19,8 @@
 //     of a hidden layer's input is neuron 16(s/4) + 4g + s%4; first layer c = 4s + g.
 //
 // Weights (A operands) are read from the packed copy in the workspace, each lane's operand being one
-// contiguous 16-byte (BF16) or 4-byte (FP32) load; the copy is made by k_pack_weights on every call.
+// contiguous 16-byte (16-bit formats) or 4-byte (FP32) load; the copy is made by k_pack_lp / k_pack_f32
+// unless the caller says it is current.
 #include <algorithm>
 
 #include "common.h"
@@ -29,11 +31,51 @@ namespace {
 using namespace ntbc;
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef short i16x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32x4 mk4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) { return u32x4{a, b, c, d}; }
+
+// The 16-bit matrix formats: bfloat16 (8 significant bits, float32's range) and IEEE half (11
+// significant bits, the precision the paper evaluates its networks in).  Both use the same
+// 32x32x16 matrix-core shape with float32 accumulation and the same operand layouts.
+enum class Lp { BF16, FP16 };
+
+// Two floats -> two 16-bit values (round to nearest even) in one 32-bit word (v_cvt_pk_*_f32).
+template <Lp L>
+__device__ __forceinline__ uint32_t cvt2(float lo, float hi) {
+  if constexpr (L == Lp::BF16)
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+  else
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, f16x2_t));
+}
+
+template <Lp L>
+__device__ __forceinline__ u32x4 x8_of(const float* v) {
+  return mk4(cvt2<L>(v[0], v[1]), cvt2<L>(v[2], v[3]), cvt2<L>(v[4], v[5]), cvt2<L>(v[6], v[7]));
+}
+
+template <Lp L>
+__device__ __forceinline__ f32x16_t mfma16(const u32x4& a, const u32x4& b, const f32x16_t& c) {
+  if constexpr (L == Lp::BF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b), c,
+                                                  0, 0, 0);
+}
+
+// ReLU of two 16-bit floats in one word: max as signed 16-bit integers against 0 (a negative
+// bfloat16 or half has its sign bit set, so it is a negative int16).
+__device__ __forceinline__ uint32_t relu16x2(uint32_t x) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2_t, x), i16x2_t{0, 0}));
+}
 
 constexpr int kMaxLayers = 5;
 constexpr int kWaves = 2;  // waves per workgroup
@@ -44,7 +86,7 @@ struct PackArgs {
   int in_dim[kMaxLayers], out_dim[kMaxLayers];
   int64_t w_off[kMaxLayers], b_off[kMaxLayers];
   int ksteps[kMaxLayers], otiles[kMaxLayers];
-  int64_t pack_off[kMaxLayers];  // in operand units (uint4 for BF16, float for FP32)
+  int64_t pack_off[kMaxLayers];  // in operand units (16 bytes for 16-bit formats, float for FP32)
   int64_t bias_off[kMaxLayers];  // floats
   int pos_hidden;                // hidden layers use the chained input permutation
 };
@@ -66,7 +108,7 @@ struct InferArgs {
 };
 
 // ------------------------------------------------------------------------------ weight packing
-// BF16: element (tile t, step s, lane l, m) = W[32t + l%32][col(s, l/32, m)] as bfloat16.
+// 16-bit formats: element (tile t, step s, lane l, m) = W[32t + l%32][col(s, l/32, m)].
 __device__ __forceinline__ int bf16_col(int layer, int s, int g, int m) {
   if (layer == 0) return 16 * s + 8 * g + m;
   return 32 * (s / 2) + 16 * (s % 2) + 8 * (m / 4) + 4 * g + (m % 4);
@@ -77,7 +119,8 @@ __device__ __forceinline__ int f32_col(int layer, int s, int g) {
   return 16 * (s / 4) + 4 * g + (s % 4);
 }
 
-__global__ void k_pack_bf16(PackArgs a, uint4* __restrict__ pack, float* __restrict__ bias) {
+template <Lp L>
+__global__ void k_pack_lp(PackArgs a, u32x4* __restrict__ pack, float* __restrict__ bias) {
   const int layer = blockIdx.y;
   if (layer >= a.n_layers) return;
   const int64_t total = (int64_t)a.otiles[layer] * a.ksteps[layer] * 64;
@@ -94,12 +137,7 @@ __global__ void k_pack_bf16(PackArgs a, uint4* __restrict__ pack, float* __restr
                  ? a.w[a.w_off[layer] + (int64_t)row * a.in_dim[layer] + col]
                  : 0.0f;
     }
-    uint4 q;
-    q.x = dev::pack_bf16x2(v[0], v[1]);
-    q.y = dev::pack_bf16x2(v[2], v[3]);
-    q.z = dev::pack_bf16x2(v[4], v[5]);
-    q.w = dev::pack_bf16x2(v[6], v[7]);
-    pack[a.pack_off[layer] + e] = q;
+    pack[a.pack_off[layer] + e] = x8_of<L>(v);
   }
   const int nb = a.otiles[layer] * 32;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
@@ -196,9 +234,9 @@ __device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int
   }
 }
 
-// ------------------------------------------------------------------------------ BF16 kernel
-template <int HID>
-__global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
+// ------------------------------------------------------------------------------ 16-bit kernel
+template <Lp L, int HID>
+__global__ void __launch_bounds__(64 * kWaves) k_infer_lp(InferArgs a) {
   constexpr int S = HID / 16;  // K-steps of a hidden input
   constexpr int T = HID / 32;  // output tiles of a hidden layer
   constexpr int TC = T < 4 ? T : 4;  // output tiles per pass
@@ -211,7 +249,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
   const int64_t id = pos0 + j <= last ? pos0 + j : last;
   const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
 
-  uint4 bin[S];
+  u32x4 bin[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     float v[8];
@@ -221,17 +259,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) v[m] = 0.0f;
     }
-    bin[s] = make_uint4(dev::pack_bf16x2(v[0], v[1]), dev::pack_bf16x2(v[2], v[3]),
-                        dev::pack_bf16x2(v[4], v[5]), dev::pack_bf16x2(v[6], v[7]));
+    bin[s] = x8_of<L>(v);
   }
 
-  const uint4* wp = reinterpret_cast<const uint4*>(a.wpack);
+  const u32x4* wp = reinterpret_cast<const u32x4*>(a.wpack);
   // hidden layers
   for (int layer = 0; layer < a.n_layers - 1; ++layer) {
     const int ks = a.ksteps[layer];
-    const uint4* wl = wp + a.pack_off[layer];
+    const u32x4* wl = wp + a.pack_off[layer];
     const float* bl = a.bias + a.bias_off[layer];
-    uint4 bout[S];
+    u32x4 bout[S];
 #pragma unroll
     for (int t0 = 0; t0 < T; t0 += TC) {
       f32x16_t acc[TC];
@@ -242,9 +279,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
         if (s < ks) {
 #pragma unroll
           for (int u = 0; u < TC; ++u) {
-            const uint4 w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
-            acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w),
-                                                             __builtin_bit_cast(bf16x8_t, bin[s]), acc[u], 0, 0, 0);
+            acc[u] = mfma16<L>(wl[((int64_t)(t0 + u) * ks + s) * 64 + lane], bin[s], acc[u]);
           }
         }
       }
@@ -257,10 +292,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
           const int neuron = 32 * t + 8 * (v / 4) + 4 * g + (v % 4);
           r[v] = fmaxf(acc[u][v] + bl[neuron], 0.0f);
         }
-        bout[2 * t] = make_uint4(dev::pack_bf16x2(r[0], r[1]), dev::pack_bf16x2(r[2], r[3]),
-                                 dev::pack_bf16x2(r[4], r[5]), dev::pack_bf16x2(r[6], r[7]));
-        bout[2 * t + 1] = make_uint4(dev::pack_bf16x2(r[8], r[9]), dev::pack_bf16x2(r[10], r[11]),
-                                     dev::pack_bf16x2(r[12], r[13]), dev::pack_bf16x2(r[14], r[15]));
+        bout[2 * t] = x8_of<L>(r);
+        bout[2 * t + 1] = x8_of<L>(r + 8);
       }
     }
 #pragma unroll
@@ -271,7 +304,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
   {
     const int layer = a.n_layers - 1;
     const int ks = a.ksteps[layer];
-    const uint4* wl = wp + a.pack_off[layer];
+    const u32x4* wl = wp + a.pack_off[layer];
     const float* bl = a.bias + a.bias_off[layer];
     for (int t0 = 0; t0 < a.otiles[layer]; t0 += 2) {
       f32x16_t acc[2] = {f32x16_t{}, f32x16_t{}};
@@ -282,9 +315,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             if (u < nt) {
-              const uint4 w = wl[((int64_t)(t0 + u) * ks + s) * 64 + lane];
-              acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w),
-                                                               __builtin_bit_cast(bf16x8_t, bin[s]), acc[u], 0, 0, 0);
+              acc[u] = mfma16<L>(wl[((int64_t)(t0 + u) * ks + s) * 64 + lane], bin[s], acc[u]);
             }
           }
         }
@@ -305,23 +336,19 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_bf16(InferArgs a) {
   pack_blocks<32>(a, y, lane, pos0);
 }
 
-// ------------------------------------------------------------------------------ BF16 kernel, LDS-staged
+// ------------------------------------------------------------------------------ 16-bit kernel, LDS-staged
 // Eight waves (two per SIMD) of 32 block positions each share every weight chunk: a chunk is two
 // output tiles of one layer over the layer's full K, copied global -> registers -> LDS one chunk ahead
 // of its use (double buffer), so each weight byte crosses L2 once per 256 positions.  The per-value
 // work between the matrix products is kept to a few instructions: biases come from LDS, conversion to
-// bfloat16 is v_cvt_pk_bf16_f32 (round to nearest even) and the ReLU is a packed 16-bit integer max
-// on the bfloat16 pairs (a negative bfloat16 is a negative int16).  The head layer keeps its
+// the 16-bit format is one packed convert (round to nearest even) and the ReLU is a packed 16-bit
+// integer max on the pairs.  The head layer keeps its
 // accumulators in registers; the sigmoid heads are staged in LDS in two halves of 16 positions per
 // wave for the BC epilogue, which reads code/255 from an LDS table.
 constexpr int kHeadTiles = 6;
 constexpr int kMaxChunks = 32;
 constexpr int kLdsWaves = 8;
 constexpr int kMaxBias = 2048;
-
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-typedef short i16x2_t __attribute__((ext_vector_type(2)));
 
 template <int PR, int NT>
 __device__ __forceinline__ void chunk_load(u32x4 (&pref)[PR], const u32x4* __restrict__ wp, int64_t src, int len, int tid) {
@@ -360,41 +387,23 @@ struct ChunkTable {
   int n_bias;               // padded biases of all layers (floats)
 };
 
-// Two floats -> two bfloat16 (round to nearest even) in one 32-bit word.
-__device__ __forceinline__ uint32_t cvt_bf16x2(float lo, float hi) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
-}
-
-// ReLU of two bfloat16 in one word: max as signed 16-bit integers against 0.
-__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t x) {
-  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2_t, x), i16x2_t{0, 0}));
-}
-
-__device__ __forceinline__ u32x4 bf16x8_of(const float* v) {
-  return mk4(cvt_bf16x2(v[0], v[1]), cvt_bf16x2(v[2], v[3]), cvt_bf16x2(v[4], v[5]), cvt_bf16x2(v[6], v[7]));
-}
-
-__device__ __forceinline__ f32x16_t mfma_bf16(const u32x4& a, const u32x4& b, const f32x16_t& c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
-                                                 0, 0, 0);
-}
-
-// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, bfloat16: the two
+// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, 16-bit: the two
 // B-operand words of K-steps 2t and 2t+1 of the next layer.
+template <Lp L>
 __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float* bt, int g, u32x4* lo, u32x4* hi) {
   uint32_t w[8];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
-    w[2 * q] = relu_bf16x2(cvt_bf16x2(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
-    w[2 * q + 1] = relu_bf16x2(cvt_bf16x2(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
+    w[2 * q] = relu16x2(cvt2<L>(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
+    w[2 * q + 1] = relu16x2(cvt2<L>(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
   }
   *lo = mk4(w[0], w[1], w[2], w[3]);
   *hi = mk4(w[4], w[5], w[6], w[7]);
 }
 
-template <int HID, int KS0>
-__global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, ChunkTable ct) {
+template <Lp L, int HID, int KS0>
+__global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, ChunkTable ct) {
   constexpr int S = HID / 16;
   constexpr int T = HID / 32;
   constexpr int CH = 2 * S * 64;                       // u32x4 per chunk buffer
@@ -424,7 +433,7 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, 
   for (int s = 0; s < KS0; ++s) {
     float v[8];
     dev::features<8>(a.grid, 16 * s + 8 * g, bx, by, v);
-    x0[s] = bf16x8_of(v);
+    x0[s] = x8_of<L>(v);
   }
   wait_dma();
   __syncthreads();
@@ -441,11 +450,11 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, 
       f32x16_t acc0 = f32x16_t{}, acc1 = f32x16_t{};
 #pragma unroll
       for (int s = 0; s < KS0; ++s) {
-        acc0 = mfma_bf16(wb[s * 64 + lane], x0[s], acc0);
-        acc1 = mfma_bf16(wb[(KS0 + s) * 64 + lane], x0[s], acc1);
+        acc0 = mfma16<L>(wb[s * 64 + lane], x0[s], acc0);
+        acc1 = mfma16<L>(wb[(KS0 + s) * 64 + lane], x0[s], acc1);
       }
-      hidden_epilogue(acc0, bl + 64 * tp, g, &bin[4 * tp], &bin[4 * tp + 1]);
-      hidden_epilogue(acc1, bl + 64 * tp + 32, g, &bin[4 * tp + 2], &bin[4 * tp + 3]);
+      hidden_epilogue<L>(acc0, bl + 64 * tp, g, &bin[4 * tp], &bin[4 * tp + 1]);
+      hidden_epilogue<L>(acc1, bl + 64 * tp + 32, g, &bin[4 * tp + 2], &bin[4 * tp + 3]);
       wait_dma();
       __syncthreads();
       ++c;
@@ -468,12 +477,12 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, 
           n0 = wb[(s + 1) * 64 + lane];
           n1 = wb[(S + s + 1) * 64 + lane];
         }
-        acc0 = mfma_bf16(w0, bin[s], acc0);
-        acc1 = mfma_bf16(w1, bin[s], acc1);
+        acc0 = mfma16<L>(w0, bin[s], acc0);
+        acc1 = mfma16<L>(w1, bin[s], acc1);
         asm volatile("" ::: "memory");  // A fragments are read one K-step ahead, no further
       }
-      hidden_epilogue(acc0, bl + 64 * tp, g, &bout[4 * tp], &bout[4 * tp + 1]);
-      hidden_epilogue(acc1, bl + 64 * tp + 32, g, &bout[4 * tp + 2], &bout[4 * tp + 3]);
+      hidden_epilogue<L>(acc0, bl + 64 * tp, g, &bout[4 * tp], &bout[4 * tp + 1]);
+      hidden_epilogue<L>(acc1, bl + 64 * tp + 32, g, &bout[4 * tp + 2], &bout[4 * tp + 3]);
       wait_dma();
       __syncthreads();
       ++c;
@@ -505,8 +514,8 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_bf16_lds(InferArgs a, 
             n0 = wb[(s + 1) * 64 + lane];
             if (two) n1 = wb[(ks + s + 1) * 64 + lane];
           }
-          hacc[2 * tp] = mfma_bf16(w0, bin[s], hacc[2 * tp]);
-          if (two) hacc[2 * tp + 1] = mfma_bf16(w1, bin[s], hacc[2 * tp + 1]);
+          hacc[2 * tp] = mfma16<L>(w0, bin[s], hacc[2 * tp]);
+          if (two) hacc[2 * tp + 1] = mfma16<L>(w1, bin[s], hacc[2 * tp + 1]);
           asm volatile("" ::: "memory");
         }
       }
@@ -636,8 +645,8 @@ struct Plan {
   Shape s;
   int precision;
   int hid_inst;       // kernel instance hidden width (>= shape hidden)
-  int rows;           // output-tile rows (32 BF16, 16 FP32)
-  int kstep;          // K per step (16 BF16, 4 FP32)
+  int rows;           // output-tile rows (32 for 16-bit formats, 16 FP32)
+  int kstep;          // K per step (16 for 16-bit formats, 4 FP32)
   int ksteps[kMaxLayers], otiles[kMaxLayers];
   int64_t pack_off[kMaxLayers], bias_off[kMaxLayers];
   int64_t pack_bytes, bias_bytes, total_bytes;
@@ -647,7 +656,7 @@ struct Plan {
 int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
   int st = make_shape(d, &p->s);
   if (st != NTBC_OK) return st;
-  if (precision != NTBC_FP32 && precision != NTBC_BF16)
+  if (precision != NTBC_FP32 && precision != NTBC_BF16 && precision != NTBC_FP16)
     return fail(precision == NTBC_FP8_E4M3 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
                 "precision %d not available for inference", precision);
   if (p->s.n_layers > kMaxLayers) return fail(NTBC_EUNSUPPORTED, "at most %d layers", kMaxLayers);
@@ -655,7 +664,7 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
   const int h = p->s.hidden;
   p->hid_inst = h <= 64 ? 64 : (h <= 128 ? 128 : 256);
   if (p->s.in_dim > p->hid_inst) return fail(NTBC_EUNSUPPORTED, "in_dim %d > kernel width %d", p->s.in_dim, p->hid_inst);
-  const bool bf = precision == NTBC_BF16;
+  const bool bf = precision == NTBC_BF16 || precision == NTBC_FP16;  // 16-bit operands
   p->rows = bf ? 32 : 16;
   p->kstep = bf ? 16 : 4;
   p->positions_per_wave = bf ? 32 : 16;
@@ -738,7 +747,9 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   if (!(prm->flags & NTBC_REUSE_PACKED)) {
     const dim3 pgrid(64, s.n_layers);
     if (precision == NTBC_BF16)
-      hipLaunchKernelGGL(k_pack_bf16, pgrid, dim3(256), 0, strm, pa, static_cast<uint4*>(wpack), bias);
+      hipLaunchKernelGGL(k_pack_lp<Lp::BF16>, pgrid, dim3(256), 0, strm, pa, static_cast<u32x4*>(wpack), bias);
+    else if (precision == NTBC_FP16)
+      hipLaunchKernelGGL(k_pack_lp<Lp::FP16>, pgrid, dim3(256), 0, strm, pa, static_cast<u32x4*>(wpack), bias);
     else
       hipLaunchKernelGGL(k_pack_f32, pgrid, dim3(256), 0, strm, pa, static_cast<float*>(wpack), bias);
     st = check_launch("ntbc_infer_blocks: weight packing");
@@ -791,7 +802,8 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   a.heads = heads_out;
 
   const int ppw = p.positions_per_wave;
-  if (precision == NTBC_BF16 && p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2) {
+  const bool lp16 = precision == NTBC_BF16 || precision == NTBC_FP16;
+  if (lp16 && p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2) {
     ChunkTable ct{};
     for (int k = 0; k < s.n_layers && ct.n < kMaxChunks; ++k) {
       for (int t0 = 0; t0 < p.otiles[k]; t0 += 2) {
@@ -806,22 +818,24 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
     NTBC_REQUIRE(nb <= kMaxBias, "too many biases (%lld) for the LDS kernel", (long long)nb);
     ct.n_bias = (int)nb;
-    const size_t chunk = (size_t)2 * (p.hid_inst / 16) * 64 * sizeof(uint4);
+    const size_t chunk = (size_t)2 * (p.hid_inst / 16) * 64 * sizeof(u32x4);
     const size_t lds = 2 * chunk + (256 + kMaxBias) * sizeof(float) + (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
     NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
     const void* fn = nullptr;
     void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
-#define NTBC_LDS_INSTANCE(H, K)                                                                       \
-    if (p.hid_inst == H && p.ksteps[0] == K) {                                                       \
-      fn = (const void*)k_infer_bf16_lds<H, K>;                                                      \
+#define NTBC_LDS_INSTANCE_L(LP, H, K)                                                                 \
+    if (p.hid_inst == H && p.ksteps[0] == K && (precision == NTBC_FP16) == (LP == Lp::FP16)) {      \
+      fn = (const void*)k_infer_lds<LP, H, K>;                                                       \
       launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
-        hipLaunchKernelGGL((k_infer_bf16_lds<H, K>), gr, bl, sh, st, x, y);                          \
+        hipLaunchKernelGGL((k_infer_lds<LP, H, K>), gr, bl, sh, st, x, y);                           \
       };                                                                                             \
     }
+#define NTBC_LDS_INSTANCE(H, K) NTBC_LDS_INSTANCE_L(Lp::BF16, H, K) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K)
     NTBC_LDS_INSTANCE(64, 1) NTBC_LDS_INSTANCE(64, 2) NTBC_LDS_INSTANCE(64, 3) NTBC_LDS_INSTANCE(64, 4)
     NTBC_LDS_INSTANCE(128, 1) NTBC_LDS_INSTANCE(128, 2) NTBC_LDS_INSTANCE(128, 3) NTBC_LDS_INSTANCE(128, 4)
     NTBC_LDS_INSTANCE(256, 1) NTBC_LDS_INSTANCE(256, 2) NTBC_LDS_INSTANCE(256, 3) NTBC_LDS_INSTANCE(256, 4)
 #undef NTBC_LDS_INSTANCE
+#undef NTBC_LDS_INSTANCE_L
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const dim3 grid((unsigned)nwg), block(64 * kLdsWaves);
@@ -834,16 +848,25 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
   if (lds > 64 * 1024) {
     const void* fn = precision == NTBC_BF16
-                         ? (p.hid_inst == 64 ? (const void*)k_infer_bf16<64>
-                                             : (p.hid_inst == 128 ? (const void*)k_infer_bf16<128> : (const void*)k_infer_bf16<256>))
+                         ? (p.hid_inst == 64 ? (const void*)k_infer_lp<Lp::BF16, 64>
+                                             : (p.hid_inst == 128 ? (const void*)k_infer_lp<Lp::BF16, 128>
+                                                                  : (const void*)k_infer_lp<Lp::BF16, 256>))
+                     : precision == NTBC_FP16
+                         ? (p.hid_inst == 64 ? (const void*)k_infer_lp<Lp::FP16, 64>
+                                             : (p.hid_inst == 128 ? (const void*)k_infer_lp<Lp::FP16, 128>
+                                                                  : (const void*)k_infer_lp<Lp::FP16, 256>))
                          : (p.hid_inst == 64 ? (const void*)k_infer_f32<64>
                                              : (p.hid_inst == 128 ? (const void*)k_infer_f32<128> : (const void*)k_infer_f32<256>));
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
   if (precision == NTBC_BF16) {
-    if (p.hid_inst == 64) hipLaunchKernelGGL(k_infer_bf16<64>, grid, block, lds, strm, a);
-    else if (p.hid_inst == 128) hipLaunchKernelGGL(k_infer_bf16<128>, grid, block, lds, strm, a);
-    else hipLaunchKernelGGL(k_infer_bf16<256>, grid, block, lds, strm, a);
+    if (p.hid_inst == 64) hipLaunchKernelGGL((k_infer_lp<Lp::BF16, 64>), grid, block, lds, strm, a);
+    else if (p.hid_inst == 128) hipLaunchKernelGGL((k_infer_lp<Lp::BF16, 128>), grid, block, lds, strm, a);
+    else hipLaunchKernelGGL((k_infer_lp<Lp::BF16, 256>), grid, block, lds, strm, a);
+  } else if (precision == NTBC_FP16) {
+    if (p.hid_inst == 64) hipLaunchKernelGGL((k_infer_lp<Lp::FP16, 64>), grid, block, lds, strm, a);
+    else if (p.hid_inst == 128) hipLaunchKernelGGL((k_infer_lp<Lp::FP16, 128>), grid, block, lds, strm, a);
+    else hipLaunchKernelGGL((k_infer_lp<Lp::FP16, 256>), grid, block, lds, strm, a);
   } else {
     if (p.hid_inst == 64) hipLaunchKernelGGL(k_infer_f32<64>, grid, block, lds, strm, a);
     else if (p.hid_inst == 128) hipLaunchKernelGGL(k_infer_f32<128>, grid, block, lds, strm, a);

@@ -17,10 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libntbc.so")
 
 OK, EINVAL, EUNSUPPORTED, EHIP, ENOWORKSPACE = 0, -1, -2, -3, -5
 BC1, BC4 = 1, 4
-FP32, BF16, FP8_E4M3 = 0, 1, 2
+FP32, BF16, FP8_E4M3, FP16 = 0, 1, 2, 3
 GRID_F32, GRID_U8 = 0, 1
 MAX_TEXTURES = 8
-PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3}
 
 
 class NtbcError(RuntimeError):

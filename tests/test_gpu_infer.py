@@ -2,9 +2,9 @@
 
 FP32: sigmoid heads within 1e-5 of the FP64 oracle; packing bit-exact (the oracle's float32 packer on
 the GPU's own heads reproduces every word); >= 99.9% of blocks identical to the FP64 oracle's and
-every differing block a quantisation-boundary tie.  BF16: the same against the oracle's BF16
-emulation (weights and layer inputs rounded to bfloat16, float64 accumulation), with the tolerance
-derived in the design notes."""
+every differing block a quantisation-boundary tie.  BF16 and FP16: the same against the oracle's
+emulation of the format (weights and layer inputs rounded to bfloat16 or IEEE half, float64
+accumulation), with tolerances derived from the format's rounding step."""
 import dataclasses
 
 import numpy as np
@@ -22,10 +22,16 @@ pytestmark = pytest.mark.gpu
 TOL_F32 = 1e-5
 # BF16 against its emulation: float32 accumulation noise (~1e-6 relative) occasionally moves an
 # intermediate activation across a bfloat16 rounding boundary; each such flip changes that activation
-# by one bf16 ulp (2^-8 relative) and the heads by up to a few 1e-3 (design notes).
+# by one bf16 ulp (2^-8 relative) and the heads by up to a few 1e-3.
 TOL_BF16 = 1e-2
 TOL_BF16_P99 = 2e-3
 TOL_BF16_MEDIAN = 1e-6
+# FP16 (IEEE half) against its emulation: the same mechanism with a half ulp of 2^-11 relative, eight
+# times finer than bfloat16's.
+TOL_FP16 = 2e-3
+TOL_FP16_P99 = 4e-4
+TOL_FP16_MEDIAN = 1e-6
+EMULATION = {ntbc.FP32: "f64", ntbc.BF16: "bf16", ntbc.FP16: "fp16"}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -46,8 +52,7 @@ def _device_model(cfg, flat, g):
 def _check(cfg, layers, g, words, heads, ids, precision):
     """Compares GPU (words [T,n], heads [n,H]) at positions ids against the oracle."""
     lv = oracle_levels(cfg, g)
-    emu = "f64" if precision == ntbc.FP32 else "bf16"
-    y_or = ON.heads(cfg, lv, layers, ids, emu)
+    y_or = ON.heads(cfg, lv, layers, ids, EMULATION[precision])
     w_or = ON.pack(y_or, cfg.formats)
     dy = np.abs(heads.astype(np.float64) - y_or)
     res = OM.classify_differences(heads, words, y_or, w_or, cfg.formats)
@@ -69,14 +74,16 @@ def _check(cfg, layers, g, words, heads, ids, precision):
         assert dy.max() <= TOL_F32
         assert ident >= 0.999
     else:
-        assert dy.max() <= TOL_BF16
-        assert np.percentile(dy, 99) <= TOL_BF16_P99
-        assert np.median(dy) <= TOL_BF16_MEDIAN
+        tol = (TOL_BF16, TOL_BF16_P99, TOL_BF16_MEDIAN) if precision == ntbc.BF16 else \
+            (TOL_FP16, TOL_FP16_P99, TOL_FP16_MEDIAN)
+        assert dy.max() <= tol[0]
+        assert np.percentile(dy, 99) <= tol[1]
+        assert np.median(dy) <= tol[2]
     assert res["ties"] == res["differ"], "a differing block is not a boundary tie"
     return ident
 
 
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 def test_small_config_all_blocks(precision):
     cfg = synth.config_small(256)
     flat, layers, g = model_inputs(cfg, 1)
@@ -86,7 +93,7 @@ def test_small_config_all_blocks(precision):
     _check(cfg, layers, g, u64(words), heads.cpu().numpy(), ids, precision)
 
 
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 def test_mid_config_u8(precision):
     cfg = synth.config_mid(1024)
     flat, layers, g = model_inputs(cfg, 2)
@@ -96,7 +103,7 @@ def test_mid_config_u8(precision):
     _check(cfg, layers, g, u64(words), heads.cpu().numpy(), ids, precision)
 
 
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 def test_paper_scale_sampled(precision):
     # the full 4096^2 launch (1,048,576 positions) compared on a sample the oracle computes one by one
     cfg = synth.config_paper_scale(4096)
@@ -111,7 +118,7 @@ def test_paper_scale_sampled(precision):
     _check(cfg, layers, g, u64(words[:, idt]), heads[idt].cpu().numpy(), ids, precision)
 
 
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 def test_ranges_and_ragged_tail(precision):
     cfg = synth.config_small(256)
     flat, layers, g = model_inputs(cfg, 4)
@@ -135,7 +142,7 @@ VARIANTS = [
 
 
 @pytest.mark.parametrize("name,over", VARIANTS)
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 def test_shape_variants(name, over, precision):
     cfg = dataclasses.replace(synth.config_small(128), **over)
     for u8 in (False, True):
@@ -146,7 +153,7 @@ def test_shape_variants(name, over, precision):
         _check(cfg, layers, g, u64(words), heads.cpu().numpy(), np.arange(cfg.n_positions), precision)
 
 
-@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
 @pytest.mark.parametrize("which", ["small", "mid", "paper"])
 def test_exact_arithmetic_network(which, precision):
     # every float32 partial sum is exact, so every bf16 rounding decision matches the emulation: the
@@ -162,7 +169,7 @@ def test_exact_arithmetic_network(which, precision):
     idt = torch.from_numpy(ids).cuda()
     w, h = u64(words[:, idt]), heads[idt].cpu().numpy()
     lv = oracle_levels(cfg, g)
-    y_or = ON.heads(cfg, lv, layers, ids, "f64" if precision == ntbc.FP32 else "bf16")
+    y_or = ON.heads(cfg, lv, layers, ids, EMULATION[precision])
     dy = np.abs(h.astype(np.float64) - y_or)
     res = OM.classify_differences(h, w, y_or, ON.pack(y_or, cfg.formats), cfg.formats)
     log(f"exact {which} precision {precision}: max|dY| {dy.max():.3g} differ {res['differ']} ties {res['ties']}")
