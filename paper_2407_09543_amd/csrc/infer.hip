@@ -337,31 +337,19 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_lp(InferArgs a) {
 }
 
 // ------------------------------------------------------------------------------ 16-bit kernel, LDS-staged
-// Eight waves (two per SIMD) of 32 block positions each share every weight chunk: a chunk is two
-// output tiles of one layer over the layer's full K, copied global -> registers -> LDS one chunk ahead
-// of its use (double buffer), so each weight byte crosses L2 once per 256 positions.  The per-value
-// work between the matrix products is kept to a few instructions: biases come from LDS, conversion to
-// the 16-bit format is one packed convert (round to nearest even) and the ReLU is a packed 16-bit
-// integer max on the pairs.  The head layer keeps its
-// accumulators in registers; the sigmoid heads are staged in LDS in two halves of 16 positions per
-// wave for the BC epilogue, which reads code/255 from an LDS table.
+// kLdsWaves waves of 32 block positions each share every weight chunk: a chunk is kChunkTiles output
+// tiles of one layer over the layer's full K, copied global -> LDS (direct DMA) one chunk ahead of
+// its use (double buffer).  The block is sized so that two blocks fit in a CU's LDS (two waves per
+// SIMD, 256 registers each; the staged heads reuse the chunk buffers): while one block is in its
+// VALU-heavy phases (grid gather, sigmoid, BC packing), the other keeps the matrix cores busy.  The per-value work between the matrix products is
+// a few instructions: biases come from LDS, conversion to the 16-bit format is one packed convert
+// (round to nearest even) and the ReLU is a packed 16-bit integer max on the pairs.  The head layer
+// keeps its accumulators in registers and applies the sigmoid there; the heads are staged in LDS in
+// two halves of 16 positions per wave for the BC epilogue, which reads code/255 from an LDS table.
 constexpr int kHeadTiles = 6;
-constexpr int kMaxChunks = 32;
-constexpr int kLdsWaves = 8;
-constexpr int kMaxBias = 2048;
-
-template <int PR, int NT>
-__device__ __forceinline__ void chunk_load(u32x4 (&pref)[PR], const u32x4* __restrict__ wp, int64_t src, int len, int tid) {
-#pragma unroll
-  for (int r = 0; r < PR; ++r) pref[r] = wp[src + min(tid + NT * r, len - 1)];
-}
-
-template <int PR, int NT>
-__device__ __forceinline__ void chunk_store(const u32x4 (&pref)[PR], u32x4* dst, int len, int tid) {
-#pragma unroll
-  for (int r = 0; r < PR; ++r)
-    if (tid + NT * r < len) dst[tid + NT * r] = pref[r];
-}
+constexpr int kMaxChunks = 48;
+constexpr int kLdsWaves = 4;
+constexpr int kChunkTiles = 2;
 
 // Direct global -> LDS copy of a weight chunk (global_load_lds_dwordx4): element e = tid + NT*r goes
 // to dst[e]; within a wave the 64 lanes write 64 consecutive 16-byte slots from the wave's LDS base.
@@ -384,7 +372,8 @@ struct ChunkTable {
   int n;
   int64_t src[kMaxChunks];  // u32x4 offset in the packed weights
   int len[kMaxChunks];      // u32x4 count
-  int n_bias;               // padded biases of all layers (floats)
+  int n_bias;               // padded biases of all layers (floats, a multiple of 4)
+  int stage;                // u32x4 slots of the staging area: the two chunk buffers, later the heads
 };
 
 // acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, 16-bit: the two
@@ -402,17 +391,45 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
   *hi = mk4(w[4], w[5], w[6], w[7]);
 }
 
+// One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `ntiles`) over KS K-steps, the
+// A fragments read from LDS one K-step ahead of their product.
+template <Lp L, int KS, int CT, int S>
+__device__ __forceinline__ void chunk_mfma(const u32x4* wb, int ks_stride, const u32x4 (&b)[S], int lane, int valid,
+                                           f32x16_t (&acc)[CT]) {
+  u32x4 nxt[CT];
+#pragma unroll
+  for (int u = 0; u < CT; ++u) nxt[u] = u < valid ? wb[u * ks_stride * 64 + lane] : u32x4{};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    u32x4 cur[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) cur[u] = nxt[u];
+    if (s + 1 < KS) {
+#pragma unroll
+      for (int u = 0; u < CT; ++u)
+        if (u < valid) nxt[u] = wb[(u * ks_stride + s + 1) * 64 + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+      if (u < valid) acc[u] = mfma16<L>(cur[u], b[s], acc[u]);
+    asm volatile("" ::: "memory");  // A fragments are read one K-step ahead, no further
+  }
+}
+
 template <Lp L, int HID, int KS0>
-__global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, ChunkTable ct) {
+__global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
+k_infer_lds(InferArgs a, ChunkTable ct) {
   constexpr int S = HID / 16;
   constexpr int T = HID / 32;
-  constexpr int CH = 2 * S * 64;                       // u32x4 per chunk buffer
+  constexpr int CT = kChunkTiles;
+  constexpr int CH = CT * S * 64;                       // u32x4 per chunk buffer
   constexpr int NT = 64 * kLdsWaves;                    // threads
-  constexpr int PR = (CH + NT - 1) / NT;                // prefetch registers per thread
+  constexpr int PR = (CH + NT - 1) / NT;                // DMA slots per thread
+  static_assert(T % CT == 0 && kHeadTiles % CT == 0, "chunk tiles must divide the tile counts");
   extern __shared__ u32x4 smem[];
-  float* tab = reinterpret_cast<float*>(smem + 2 * CH);
+  float* tab = reinterpret_cast<float*>(smem + ct.stage);
   float* bias_s = tab + 256;
-  float* ybase = bias_s + kMaxBias;
+  float* ybase = reinterpret_cast<float*>(smem);  // the heads reuse the chunk buffers after the last chunk
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int j = lane & 31, g = lane >> 5;
@@ -423,9 +440,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, Chunk
   const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
   const u32x4* wp = reinterpret_cast<const u32x4*>(a.wpack);
 
+  chunk_dma<PR, NT>(wp, ct.src[0], ct.len[0], smem, tid);
   for (int i = tid; i < 256; i += NT) tab[i] = (float)i / 255.0f;
   for (int i = tid; i < ct.n_bias; i += NT) bias_s[i] = a.bias[i];
-  chunk_dma<PR, NT>(wp, ct.src[0], ct.len[0], smem, tid);
 
   // grid features: the first layer's B operands
   u32x4 x0[KS0];
@@ -443,18 +460,17 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, Chunk
   {
     const float* bl = bias_s + a.bias_off[0];
 #pragma unroll
-    for (int tp = 0; tp < T / 2; ++tp) {
-      const bool more = c + 1 < ct.n;
-      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
-      const u32x4* wb = smem + (c & 1) * CH;
-      f32x16_t acc0 = f32x16_t{}, acc1 = f32x16_t{};
+    for (int tc = 0; tc < T / CT; ++tc) {
+      if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      f32x16_t acc[CT];
 #pragma unroll
-      for (int s = 0; s < KS0; ++s) {
-        acc0 = mfma16<L>(wb[s * 64 + lane], x0[s], acc0);
-        acc1 = mfma16<L>(wb[(KS0 + s) * 64 + lane], x0[s], acc1);
+      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+      chunk_mfma<L, KS0, CT, KS0>(smem + (c & 1) * CH, KS0, x0, lane, CT, acc);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const int t = CT * tc + u;
+        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bin[2 * t], &bin[2 * t + 1]);
       }
-      hidden_epilogue<L>(acc0, bl + 64 * tp, g, &bin[4 * tp], &bin[4 * tp + 1]);
-      hidden_epilogue<L>(acc1, bl + 64 * tp + 32, g, &bin[4 * tp + 2], &bin[4 * tp + 3]);
       wait_dma();
       __syncthreads();
       ++c;
@@ -464,25 +480,17 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, Chunk
     const float* bl = bias_s + a.bias_off[layer];
     u32x4 bout[S];
 #pragma unroll
-    for (int tp = 0; tp < T / 2; ++tp) {
-      const bool more = c + 1 < ct.n;
-      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
-      const u32x4* wb = smem + (c & 1) * CH;
-      f32x16_t acc0 = f32x16_t{}, acc1 = f32x16_t{};
-      u32x4 n0 = wb[lane], n1 = wb[S * 64 + lane];
+    for (int tc = 0; tc < T / CT; ++tc) {
+      if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      f32x16_t acc[CT];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const u32x4 w0 = n0, w1 = n1;
-        if (s + 1 < S) {
-          n0 = wb[(s + 1) * 64 + lane];
-          n1 = wb[(S + s + 1) * 64 + lane];
-        }
-        acc0 = mfma16<L>(w0, bin[s], acc0);
-        acc1 = mfma16<L>(w1, bin[s], acc1);
-        asm volatile("" ::: "memory");  // A fragments are read one K-step ahead, no further
+      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+      chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, bin, lane, CT, acc);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const int t = CT * tc + u;
+        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bout[2 * t], &bout[2 * t + 1]);
       }
-      hidden_epilogue<L>(acc0, bl + 64 * tp, g, &bout[4 * tp], &bout[4 * tp + 1]);
-      hidden_epilogue<L>(acc1, bl + 64 * tp + 32, g, &bout[4 * tp + 2], &bout[4 * tp + 3]);
       wait_dma();
       __syncthreads();
       ++c;
@@ -492,39 +500,39 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, Chunk
   }
   // head layer, accumulators kept for the BC epilogue
   const int layer = a.n_layers - 1;
-  const int ks = S;
   const int nht = a.otiles[layer];
   const float* bl = bias_s + a.bias_off[layer];
   f32x16_t hacc[kHeadTiles];
 #pragma unroll
   for (int t = 0; t < kHeadTiles; ++t) hacc[t] = f32x16_t{};
 #pragma unroll
-  for (int tp = 0; tp < kHeadTiles / 2; ++tp) {
-    if (2 * tp < nht) {
-      const bool more = c + 1 < ct.n;
-      if (more) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
-      const u32x4* wb = smem + (c & 1) * CH;
-      const bool two = 2 * tp + 1 < nht;
-      u32x4 n0 = wb[lane], n1 = two ? wb[ks * 64 + lane] : n0;
+  for (int tc = 0; tc < kHeadTiles / CT; ++tc) {
+    if (CT * tc < nht) {
+      if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      f32x16_t acc[CT];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (s < ks) {
-          const u32x4 w0 = n0, w1 = n1;
-          if (s + 1 < ks) {
-            n0 = wb[(s + 1) * 64 + lane];
-            if (two) n1 = wb[(ks + s + 1) * 64 + lane];
-          }
-          hacc[2 * tp] = mfma16<L>(w0, bin[s], hacc[2 * tp]);
-          if (two) hacc[2 * tp + 1] = mfma16<L>(w1, bin[s], hacc[2 * tp + 1]);
-          asm volatile("" ::: "memory");
-        }
-      }
+      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+      chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, bin, lane, nht - CT * tc, acc);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) hacc[CT * tc + u] = acc[u];
       wait_dma();
       __syncthreads();
       ++c;
     }
   }
-  // sigmoid heads -> LDS, 16 positions at a time, then pack
+  // sigmoid heads in registers (all lanes), then staged in LDS 16 positions at a time for the pack
+#pragma unroll
+  for (int t = 0; t < kHeadTiles; ++t) {
+    if (t < nht) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
+        const float bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hacc[t][4 * q + r] = sigmoid_fast(hacc[t][4 * q + r] + bv[r]);
+      }
+    }
+  }
   float* y = ybase + wave * 16 * a.head_stride;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
@@ -535,11 +543,9 @@ __global__ void __launch_bounds__(64 * kLdsWaves) k_infer_lds(InferArgs a, Chunk
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int n0 = 32 * t + 8 * q + 4 * g;
-            const float4 b = *reinterpret_cast<const float4*>(bl + n0);
-            const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (n0 + r < a.head_dim) y[(j & 15) * a.head_stride + n0 + r] = sigmoid_fast(hacc[t][4 * q + r] + bv[r]);
+              if (n0 + r < a.head_dim) y[(j & 15) * a.head_stride + n0 + r] = hacc[t][4 * q + r];
           }
         }
       }
@@ -805,9 +811,10 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   const bool lp16 = precision == NTBC_BF16 || precision == NTBC_FP16;
   if (lp16 && p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2) {
     ChunkTable ct{};
-    for (int k = 0; k < s.n_layers && ct.n < kMaxChunks; ++k) {
-      for (int t0 = 0; t0 < p.otiles[k]; t0 += 2) {
-        const int nt = std::min(2, p.otiles[k] - t0);
+    for (int k = 0; k < s.n_layers; ++k) {
+      for (int t0 = 0; t0 < p.otiles[k]; t0 += kChunkTiles) {
+        NTBC_REQUIRE(ct.n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
+        const int nt = std::min(kChunkTiles, p.otiles[k] - t0);
         ct.src[ct.n] = p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64;
         ct.len[ct.n] = nt * p.ksteps[k] * 64;
         ++ct.n;
@@ -816,10 +823,12 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     const int64_t nwg = ceil_div(n_blocks, (int64_t)32 * kLdsWaves);
     int64_t nb = 0;
     for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
-    NTBC_REQUIRE(nb <= kMaxBias, "too many biases (%lld) for the LDS kernel", (long long)nb);
-    ct.n_bias = (int)nb;
-    const size_t chunk = (size_t)2 * (p.hid_inst / 16) * 64 * sizeof(u32x4);
-    const size_t lds = 2 * chunk + (256 + kMaxBias) * sizeof(float) + (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
+    ct.n_bias = (int)((nb + 3) / 4 * 4);
+    const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * sizeof(u32x4);
+    const size_t ybytes = (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
+    const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
+    ct.stage = (int)(stage / sizeof(u32x4));
+    const size_t lds = stage + (256 + (size_t)ct.n_bias) * sizeof(float);
     NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
     const void* fn = nullptr;
     void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
