@@ -109,6 +109,24 @@ def copy_probe(torch, mib=1024, reps=5):
     print(json.dumps({"copy_probe_bytes_read_per_launch": mib << 20, "launches": reps}), flush=True)
 
 
+def _finite(x):
+    """Replaces infinite or NaN floats (PSNR of an exact texture) by None: strict JSON has neither."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    if isinstance(x, (float, np.floating)) and not np.isfinite(x):
+        return None
+    return x
+
+
+def _plain(x):
+    """JSON fallback for NumPy scalars."""
+    if isinstance(x, np.generic):
+        return x.item()
+    raise TypeError(f"not JSON serializable: {type(x).__name__}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,8 +281,8 @@ def main():
                       "psnr_db": psnrs[ntbc.FP16]}, **versus_fp32(ntbc.FP16)),
         "psnr_db_material": {"bf16": material_psnr(ntbc.BF16), "fp16": material_psnr(ntbc.FP16),
                              "fp32": material_psnr(ntbc.FP32)},
-        "gate_dpsnr_0p1db": {p: {"per_texture": versus_fp32(v)["dpsnr_db_vs_fp32"]["max"] <= 0.1,
-                                 "material": versus_fp32(v)["dpsnr_db_vs_fp32"]["material"] <= 0.1}
+        "gate_dpsnr_0p1db": {p: {"per_texture": bool(versus_fp32(v)["dpsnr_db_vs_fp32"]["max"] <= 0.1),
+                                 "material": bool(versus_fp32(v)["dpsnr_db_vs_fp32"]["material"] <= 0.1)}
                              for p, v in (("bf16", ntbc.BF16), ("fp16", ntbc.FP16))},
         "ref_encoder": {"ms_per_material": enc_ms, "blocks_per_s": n_blocks / (enc_ms * 1e-3), "psnr_db": ref_psnr},
         "decoder": {"ms_per_material": dec_ms, "blocks_per_s": n_blocks / (dec_ms * 1e-3)},
@@ -275,7 +293,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(cfg, layers, codes, scale, zero, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
+    result["note"] = "a PSNR of null means zero error (lossless)"
+    print(json.dumps(_finite(result), default=_plain, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

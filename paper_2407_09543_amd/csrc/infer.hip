@@ -416,7 +416,31 @@ __device__ __forceinline__ void chunk_mfma(const u32x4* wb, int ks_stride, const
   }
 }
 
-template <Lp L, int HID, int KS0>
+// One middle hidden layer: every chunk (CT output tiles over the full K) through the matrix cores,
+// bias + ReLU + 16-bit conversion into `out`; the next chunk's DMA runs under the products.
+template <Lp L, int S, int T, int CT, int PR, int NT, int CH>
+__device__ __forceinline__ void hidden_layer(const u32x4 (&in)[S], u32x4 (&out)[S], const float* bl,
+                                             const u32x4* __restrict__ wp, const ChunkTable& ct, u32x4* smem, int& c,
+                                             int tid, int lane, int g) {
+#pragma unroll
+  for (int tc = 0; tc < T / CT; ++tc) {
+    if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+    f32x16_t acc[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+    chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, in, lane, CT, acc);
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int t = CT * tc + u;
+      hidden_epilogue<L>(acc[u], bl + 32 * t, g, &out[2 * t], &out[2 * t + 1]);
+    }
+    wait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+template <Lp L, int HID, int KS0, int NH>
 __global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_infer_lds(InferArgs a, ChunkTable ct) {
   constexpr int S = HID / 16;
@@ -456,7 +480,7 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   __syncthreads();
 
   int c = 0;
-  u32x4 bin[S];
+  u32x4 bin[S], bout[S];
   {
     const float* bl = bias_s + a.bias_off[0];
 #pragma unroll
@@ -476,32 +500,29 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
       ++c;
     }
   }
-  for (int layer = 1; layer < a.n_layers - 1; ++layer) {
-    const float* bl = bias_s + a.bias_off[layer];
-    u32x4 bout[S];
+  // middle hidden layers: NH of them unrolled at compile time (the two register arrays alternate, so
+  // nothing is copied), or NH < 0: a run-time count
+  if constexpr (NH >= 0) {
+    static_assert(NH <= 2, "at most two unrolled middle layers");
+    if constexpr (NH >= 1)
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[1], wp, ct, smem, c, tid, lane, g);
+    if constexpr (NH >= 2)
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bout, bin, bias_s + a.bias_off[2], wp, ct, smem, c, tid, lane, g);
+    if constexpr (NH == 1) {
 #pragma unroll
-    for (int tc = 0; tc < T / CT; ++tc) {
-      if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
-      f32x16_t acc[CT];
-#pragma unroll
-      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
-      chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, bin, lane, CT, acc);
-#pragma unroll
-      for (int u = 0; u < CT; ++u) {
-        const int t = CT * tc + u;
-        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bout[2 * t], &bout[2 * t + 1]);
-      }
-      wait_dma();
-      __syncthreads();
-      ++c;
+      for (int s = 0; s < S; ++s) bin[s] = bout[s];
     }
+  } else {
+    for (int layer = 1; layer < a.n_layers - 1; ++layer) {
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], wp, ct, smem, c, tid, lane, g);
 #pragma unroll
-    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+      for (int s = 0; s < S; ++s) bin[s] = bout[s];
+    }
   }
   // head layer, accumulators kept for the BC epilogue
-  const int layer = a.n_layers - 1;
-  const int nht = a.otiles[layer];
-  const float* bl = bias_s + a.bias_off[layer];
+  const int head = a.n_layers - 1;
+  const int nht = a.otiles[head];
+  const float* bl = bias_s + a.bias_off[head];
   f32x16_t hacc[kHeadTiles];
 #pragma unroll
   for (int t = 0; t < kHeadTiles; ++t) hacc[t] = f32x16_t{};
@@ -832,17 +853,22 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
     const void* fn = nullptr;
     void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
-#define NTBC_LDS_INSTANCE_L(LP, H, K)                                                                 \
-    if (p.hid_inst == H && p.ksteps[0] == K && (precision == NTBC_FP16) == (LP == Lp::FP16)) {      \
-      fn = (const void*)k_infer_lds<LP, H, K>;                                                       \
+    // generic instances (run-time middle-layer count), then the unrolled ones for the shapes of the
+    // paper-scale (width 256, 64 inputs) and mid (width 128, 48 inputs) models with two middle layers
+    const int mid = s.n_layers - 2;
+#define NTBC_LDS_INSTANCE_L(LP, H, K, NH)                                                             \
+    if (p.hid_inst == H && p.ksteps[0] == K && (NH < 0 || NH == mid) &&                              \
+        (precision == NTBC_FP16) == (LP == Lp::FP16)) {                                              \
+      fn = (const void*)k_infer_lds<LP, H, K, NH>;                                                   \
       launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
-        hipLaunchKernelGGL((k_infer_lds<LP, H, K>), gr, bl, sh, st, x, y);                           \
+        hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH>), gr, bl, sh, st, x, y);                       \
       };                                                                                             \
     }
-#define NTBC_LDS_INSTANCE(H, K) NTBC_LDS_INSTANCE_L(Lp::BF16, H, K) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K)
-    NTBC_LDS_INSTANCE(64, 1) NTBC_LDS_INSTANCE(64, 2) NTBC_LDS_INSTANCE(64, 3) NTBC_LDS_INSTANCE(64, 4)
-    NTBC_LDS_INSTANCE(128, 1) NTBC_LDS_INSTANCE(128, 2) NTBC_LDS_INSTANCE(128, 3) NTBC_LDS_INSTANCE(128, 4)
-    NTBC_LDS_INSTANCE(256, 1) NTBC_LDS_INSTANCE(256, 2) NTBC_LDS_INSTANCE(256, 3) NTBC_LDS_INSTANCE(256, 4)
+#define NTBC_LDS_INSTANCE(H, K, NH) NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH)
+    NTBC_LDS_INSTANCE(64, 1, -1) NTBC_LDS_INSTANCE(64, 2, -1) NTBC_LDS_INSTANCE(64, 3, -1) NTBC_LDS_INSTANCE(64, 4, -1)
+    NTBC_LDS_INSTANCE(128, 1, -1) NTBC_LDS_INSTANCE(128, 2, -1) NTBC_LDS_INSTANCE(128, 3, -1) NTBC_LDS_INSTANCE(128, 4, -1)
+    NTBC_LDS_INSTANCE(256, 1, -1) NTBC_LDS_INSTANCE(256, 2, -1) NTBC_LDS_INSTANCE(256, 3, -1) NTBC_LDS_INSTANCE(256, 4, -1)
+    NTBC_LDS_INSTANCE(128, 3, 2) NTBC_LDS_INSTANCE(256, 4, 2)
 #undef NTBC_LDS_INSTANCE
 #undef NTBC_LDS_INSTANCE_L
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
