@@ -391,28 +391,33 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
   *hi = mk4(w[4], w[5], w[6], w[7]);
 }
 
-// One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `ntiles`) over KS K-steps, the
-// A fragments read from LDS one K-step ahead of their product.
+// One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `valid`) over KS K-steps, the
+// A fragments read from LDS kPrefetch K-steps ahead of their product.
+constexpr int kPrefetch = 2;
+
 template <Lp L, int KS, int CT, int S>
 __device__ __forceinline__ void chunk_mfma(const u32x4* wb, int ks_stride, const u32x4 (&b)[S], int lane, int valid,
                                            f32x16_t (&acc)[CT]) {
-  u32x4 nxt[CT];
+  constexpr int PD = kPrefetch < KS ? kPrefetch : KS;
+  u32x4 ring[PD][CT];
 #pragma unroll
-  for (int u = 0; u < CT; ++u) nxt[u] = u < valid ? wb[u * ks_stride * 64 + lane] : u32x4{};
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) ring[d][u] = u < valid ? wb[(u * ks_stride + d) * 64 + lane] : u32x4{};
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
     u32x4 cur[CT];
 #pragma unroll
-    for (int u = 0; u < CT; ++u) cur[u] = nxt[u];
-    if (s + 1 < KS) {
+    for (int u = 0; u < CT; ++u) cur[u] = ring[s % PD][u];
+    if (s + PD < KS) {
 #pragma unroll
       for (int u = 0; u < CT; ++u)
-        if (u < valid) nxt[u] = wb[(u * ks_stride + s + 1) * 64 + lane];
+        if (u < valid) ring[s % PD][u] = wb[(u * ks_stride + s + PD) * 64 + lane];
     }
 #pragma unroll
     for (int u = 0; u < CT; ++u)
       if (u < valid) acc[u] = mfma16<L>(cur[u], b[s], acc[u]);
-    asm volatile("" ::: "memory");  // A fragments are read one K-step ahead, no further
+    asm volatile("" ::: "memory");  // A fragments are read PD K-steps ahead, no further
   }
 }
 
