@@ -14,8 +14,15 @@ emulates a reduced-precision matrix path with float64 accumulation:
   * ``"fp8"``: per-layer scales (s_x, s_w); the layer input is rounded to E4M3 as x / s_x, the weight
     as W * (1/s_w) evaluated in float32 (the GPU path's precision for this integer decision), and the
     product is rescaled by s_x * s_w before the bias is added.
+
+FP8 scales (the paper has no FP8 path; this is the reading used here): per layer and per tensor, the
+smallest power of two s with max|v| / s <= 448 (the largest finite E4M3 value), so that v / s is exact
+and never saturates; s_x from the layer inputs of a float64 forward over calibration rows, s_w from
+the layer's weight matrix (biases stay float32).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -81,3 +88,26 @@ def activation_absmax(layers, x):
     """max |input| of every layer over the rows of x (float64 forward); for FP8 scale calibration."""
     _, (hs, _) = forward(layers, x, "f64")
     return [float(np.abs(h).max()) for h in hs]
+
+
+E4M3_MAX = 448.0
+
+
+def pow2_scale(m):
+    """The smallest power of two s (down to 2^-126) with m / s <= 448; 1 when m is 0 or not finite."""
+    m = float(m)
+    if not (m > 0.0 and math.isfinite(m)):
+        return 1.0
+    e = math.frexp(m)[1] - 9
+    while m > math.ldexp(E4M3_MAX, e):
+        e += 1
+    while e > -126 and m <= math.ldexp(E4M3_MAX, e - 1):
+        e -= 1
+    return math.ldexp(1.0, e)
+
+
+def fp8_scales(layers, x):
+    """[(s_x, s_w)] per layer for the calibration rows x [n, in]."""
+    ax = activation_absmax(layers, x)
+    return [(pow2_scale(a), pow2_scale(float(np.abs(np.asarray(w, dtype=np.float32)).max())))
+            for a, (w, _) in zip(ax, layers)]

@@ -162,6 +162,21 @@ def heads(cfg, levels, layers, ids, precision: str = "f64", scales=None):
     return y
 
 
+def calibration_ids(n_positions: int, n_sample: int):
+    """Block positions of an FP8 calibration sample: every stride-th block, stride = n_positions //
+    n_sample (at least 1), the first min(n_sample, n_positions) of them."""
+    n = min(int(n_sample), int(n_positions))
+    stride = max(1, int(n_positions) // max(1, int(n_sample)))
+    return np.arange(n, dtype=np.int64) * stride
+
+
+def fp8_calibration(cfg, levels, layers, n_sample: int):
+    """Per-layer (s_x, s_w) FP8 scales from the calibration sample's float64 forward."""
+    ids = calibration_ids(cfg.n_positions, n_sample)
+    x = G.features(levels, ids % cfg.blocks_w, ids // cfg.blocks_w, cfg.blocks_w, cfg.blocks_h)
+    return mlp.fp8_scales(layers, x)
+
+
 def infer_blocks(cfg, levels, layers, ids, precision: str = "f64", scales=None):
     """(words [T, n], Y [n, H]) for block positions ids."""
     y = heads(cfg, levels, layers, ids, precision, scales)
