@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "NTBC inference blocks/s at 4096² BF16 vs FP32 @ ΔPSNR≤0.1dB; encode s/material"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP8_TFLOPS = 5000.0
 
 
 def log(msg):
@@ -206,8 +207,14 @@ def main():
         }
         model_note = "parameters trained by the encode above"
     n_blocks = cfg.n_positions * len(cfg.formats)
+    # FP8 E4M3 scales from a 65,536-block calibration sample (not part of the timed inference)
+    torch.cuda.synchronize()
+    t_cal = time.perf_counter()
+    model.fp8_calibrate(65536)
+    torch.cuda.synchronize()
+    calib_ms = (time.perf_counter() - t_cal) * 1e3
     outs = {}
-    for prec in (ntbc.BF16, ntbc.FP16, ntbc.FP32):
+    for prec in (ntbc.BF16, ntbc.FP16, ntbc.FP8_E4M3, ntbc.FP32):
         outs[prec] = torch.empty((len(cfg.formats), cfg.n_positions), dtype=torch.int64, device=dev)
         model.infer(prec, out=outs[prec])
     torch.cuda.synchronize()
@@ -218,6 +225,9 @@ def main():
     model.infer(ntbc.FP16, out=outs[ntbc.FP16])
     ms_h = time_call(lambda: model.infer(ntbc.FP16, out=outs[ntbc.FP16], reuse_packed=True), args.steps,
                      args.warmup, torch)
+    model.infer(ntbc.FP8_E4M3, out=outs[ntbc.FP8_E4M3])
+    ms_f8 = time_call(lambda: model.infer(ntbc.FP8_E4M3, out=outs[ntbc.FP8_E4M3], reuse_packed=True), args.steps,
+                      args.warmup, torch)
     model.infer(ntbc.FP32, out=out_fp)
     steps_fp = max(2, args.steps // 4)
     ms_fp = time_call(lambda: model.infer(ntbc.FP32, out=out_fp, reuse_packed=True), steps_fp, 1, torch)
@@ -279,11 +289,15 @@ def main():
         "fp16": dict({"blocks_per_s": n_blocks / (ms_h * 1e-3), "ms_per_step": ms_h,
                       "frac_fp16_peak": flop / (ms_h * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
                       "psnr_db": psnrs[ntbc.FP16]}, **versus_fp32(ntbc.FP16)),
+        "fp8_e4m3": dict({"blocks_per_s": n_blocks / (ms_f8 * 1e-3), "ms_per_step": ms_f8,
+                          "frac_fp8_peak": flop / (ms_f8 * 1e-3) / 1e12 / PEAK_FP8_TFLOPS,
+                          "calibration_ms": calib_ms, "scales": model.fp8_scales.cpu().numpy().tolist(),
+                          "psnr_db": psnrs[ntbc.FP8_E4M3]}, **versus_fp32(ntbc.FP8_E4M3)),
         "psnr_db_material": {"bf16": material_psnr(ntbc.BF16), "fp16": material_psnr(ntbc.FP16),
-                             "fp32": material_psnr(ntbc.FP32)},
+                             "fp8_e4m3": material_psnr(ntbc.FP8_E4M3), "fp32": material_psnr(ntbc.FP32)},
         "gate_dpsnr_0p1db": {p: {"per_texture": bool(versus_fp32(v)["dpsnr_db_vs_fp32"]["max"] <= 0.1),
                                  "material": bool(versus_fp32(v)["dpsnr_db_vs_fp32"]["material"] <= 0.1)}
-                             for p, v in (("bf16", ntbc.BF16), ("fp16", ntbc.FP16))},
+                             for p, v in (("bf16", ntbc.BF16), ("fp16", ntbc.FP16), ("fp8_e4m3", ntbc.FP8_E4M3))},
         "ref_encoder": {"ms_per_material": enc_ms, "blocks_per_s": n_blocks / (enc_ms * 1e-3), "psnr_db": ref_psnr},
         "decoder": {"ms_per_material": dec_ms, "blocks_per_s": n_blocks / (dec_ms * 1e-3)},
         "encode_s_per_material": encode_info["seconds"] if encode_info else None,

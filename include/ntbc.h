@@ -55,7 +55,8 @@ extern "C" {
 
 #define NTBC_FP32 0               /* MLP in FP32 (FP32 matrix cores), FP32 accumulation             */
 #define NTBC_BF16 1               /* MLP weights and layer inputs in BF16, FP32 accumulation         */
-#define NTBC_FP8_E4M3 2           /* MLP weights and layer inputs in FP8 E4M3 with per-layer scales  */
+#define NTBC_FP8_E4M3 2           /* MLP weights and layer inputs in FP8 E4M3 (OCP) with per-layer
+                                     power-of-two scales, FP32 accumulation (ntbc_fp8_calibrate)     */
 #define NTBC_FP16 3               /* MLP weights and layer inputs in IEEE half, FP32 accumulation    */
 
 #define NTBC_GRID_F32 0
@@ -146,10 +147,24 @@ int ntbc_fallback(const uint64_t* ntbc, const uint64_t* ref, const int32_t* sse_
  * (ties: smallest weight index) -> packed words.  BC1 endpoints are swapped when c0 < c1; equal
  * endpoints give all-zero codes.  BC4's mode follows the stored endpoint order.
  * blocks_out: uint64[n_textures][n_blocks].  heads_out (optional, may be NULL): float
- * [n_blocks][head_dim] sigmoid outputs.  workspace: >= ntbc_workspace_size(d, precision, 0). */
+ * [n_blocks][head_dim] sigmoid outputs.  workspace: >= ntbc_workspace_size(d, precision, 0).
+ * Precisions: NTBC_FP32, NTBC_BF16, NTBC_FP16, and NTBC_FP8_E4M3 with p->fp8_scales set (from
+ * ntbc_fp8_calibrate; FP8 needs head_dim <= 192, in_dim <= 64 and a hidden layer, else
+ * NTBC_EUNSUPPORTED). */
 int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t precision,
                       int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* FP8 E4M3 scales for ntbc_infer_blocks at NTBC_FP8_E4M3 (the paper has no FP8 path; per-layer,
+ * per-tensor scaling as this library defines it): for every layer, s_w = the smallest power of two
+ * with max|W| / s_w <= 448 (the largest finite E4M3 value; biases stay FP32) and s_x = the same for
+ * the largest |input| of the layer over a calibration sample — blocks i * stride, i < min(n_sample,
+ * n_positions), stride = max(1, n_positions / n_sample) — evaluated by the FP32 inference path.
+ * Powers of two make the scaling exact and keep every scaled value inside the E4M3 range.
+ * scales_out: device float[n_layers][2] = (s_x, s_w).  workspace: >= ntbc_workspace_size(d,
+ * NTBC_FP8_E4M3, 0).  Errors: NTBC_EINVAL (NULL pointers, n_sample < 1), NTBC_ENOWORKSPACE. */
+int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* p, int64_t n_sample, float* scales_out,
+                       void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- training ----------------------------------------------------------------------------------- */
 

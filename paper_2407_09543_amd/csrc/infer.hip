@@ -39,13 +39,19 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef short i16x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u32x4 mk4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) { return u32x4{a, b, c, d}; }
 
-// The 16-bit matrix formats: bfloat16 (8 significant bits, float32's range) and IEEE half (11
-// significant bits, the precision the paper evaluates its networks in).  Both use the same
-// 32x32x16 matrix-core shape with float32 accumulation and the same operand layouts.
-enum class Lp { BF16, FP16 };
+// The reduced-precision matrix formats: bfloat16 (8 significant bits, float32's range), IEEE half (11
+// significant bits, the precision the paper evaluates its networks in) and FP8 E4M3 (OCP, 4
+// significant bits, largest finite 448) with per-layer power-of-two scales.  All use a 32x32x16
+// matrix-core shape with float32 accumulation and the same operand layouts (lane l: row/column l%32,
+// K elements 8(l/32) .. 8(l/32)+7); an operand is eight values: 16 bytes, or 8 bytes for FP8.
+enum class Lp { BF16, FP16, FP8 };
+
+template <Lp L> struct LpOp { typedef u32x4 type; };
+template <> struct LpOp<Lp::FP8> { typedef u32x2 type; };
 
 // Two floats -> two 16-bit values (round to nearest even) in one 32-bit word (v_cvt_pk_*_f32).
 template <Lp L>
@@ -56,19 +62,35 @@ __device__ __forceinline__ uint32_t cvt2(float lo, float hi) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, f16x2_t));
 }
 
+// Four floats -> four E4M3 bytes (round to nearest even), saturating at +-448 like the E4M3FN
+// conversion of the oracle (the hardware conversion would give NaN beyond the range).
+__device__ __forceinline__ float sat448(float x) { return fminf(fmaxf(x, -448.0f), 448.0f); }
+__device__ __forceinline__ uint32_t cvt4_fp8(float a, float b, float c, float d) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(sat448(a), sat448(b), 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(sat448(c), sat448(d), lo, true);
+}
+
+// Eight floats (already divided by the FP8 scale) -> one operand.
 template <Lp L>
-__device__ __forceinline__ u32x4 x8_of(const float* v) {
-  return mk4(cvt2<L>(v[0], v[1]), cvt2<L>(v[2], v[3]), cvt2<L>(v[4], v[5]), cvt2<L>(v[6], v[7]));
+__device__ __forceinline__ typename LpOp<L>::type x8_of(const float* v) {
+  if constexpr (L == Lp::FP8)
+    return u32x2{cvt4_fp8(v[0], v[1], v[2], v[3]), cvt4_fp8(v[4], v[5], v[6], v[7])};
+  else
+    return mk4(cvt2<L>(v[0], v[1]), cvt2<L>(v[2], v[3]), cvt2<L>(v[4], v[5]), cvt2<L>(v[6], v[7]));
 }
 
 template <Lp L>
-__device__ __forceinline__ f32x16_t mfma16(const u32x4& a, const u32x4& b, const f32x16_t& c) {
+__device__ __forceinline__ f32x16_t mfma16(const typename LpOp<L>::type& a, const typename LpOp<L>::type& b,
+                                           const f32x16_t& c) {
   if constexpr (L == Lp::BF16)
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
                                                    0, 0, 0);
-  else
+  else if constexpr (L == Lp::FP16)
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b), c,
                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0,
+                                                      0);
 }
 
 // ReLU of two 16-bit floats in one word: max as signed 16-bit integers against 0 (a negative
@@ -89,6 +111,7 @@ struct PackArgs {
   int64_t pack_off[kMaxLayers];  // in operand units (16 bytes for 16-bit formats, float for FP32)
   int64_t bias_off[kMaxLayers];  // floats
   int pos_hidden;                // hidden layers use the chained input permutation
+  const float* fp8_scales;       // FP8: [n_layers][2] = (s_x, s_w)
 };
 
 struct InferArgs {
@@ -105,6 +128,9 @@ struct InferArgs {
   int64_t first, n;
   uint64_t* out;                // [n_textures][n]
   float* heads;                 // optional [n][head_dim]
+  const float* fp8_scales;      // FP8: [n_layers][2] = (s_x, s_w)
+  int64_t stride;               // calibration: block id of sample i is i * stride
+  unsigned* amax;               // calibration: per layer, max |layer input| as float bits
 };
 
 // ------------------------------------------------------------------------------ weight packing
@@ -120,9 +146,11 @@ __device__ __forceinline__ int f32_col(int layer, int s, int g) {
 }
 
 template <Lp L>
-__global__ void k_pack_lp(PackArgs a, u32x4* __restrict__ pack, float* __restrict__ bias) {
+__global__ void k_pack_lp(PackArgs a, typename LpOp<L>::type* __restrict__ pack, float* __restrict__ bias) {
   const int layer = blockIdx.y;
   if (layer >= a.n_layers) return;
+  // FP8: W * (1/s_w) in float32 (exact for the power-of-two scales), then E4M3
+  const float inv_w = L == Lp::FP8 ? 1.0f / a.fp8_scales[2 * layer + 1] : 1.0f;
   const int64_t total = (int64_t)a.otiles[layer] * a.ksteps[layer] * 64;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int l = (int)(e % 64);
@@ -136,6 +164,10 @@ __global__ void k_pack_lp(PackArgs a, u32x4* __restrict__ pack, float* __restric
       v[m] = (row < a.out_dim[layer] && col < a.in_dim[layer])
                  ? a.w[a.w_off[layer] + (int64_t)row * a.in_dim[layer] + col]
                  : 0.0f;
+    }
+    if constexpr (L == Lp::FP8) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] *= inv_w;
     }
     pack[a.pack_off[layer] + e] = x8_of<L>(v);
   }
@@ -376,19 +408,37 @@ struct ChunkTable {
   int stage;                // u32x4 slots of the staging area: the two chunk buffers, later the heads
 };
 
-// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, 16-bit: the two
-// B-operand words of K-steps 2t and 2t+1 of the next layer.
+// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, conversion: the two
+// B-operand words of K-steps 2t and 2t+1 of the next layer.  FP8: z = acc * (s_x s_w) + b, then the
+// ReLU output is divided by the next layer's s_x (`mul`, `inv_next`: exact powers of two).
 template <Lp L>
-__device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float* bt, int g, u32x4* lo, u32x4* hi) {
-  uint32_t w[8];
+__device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float* bt, int g, typename LpOp<L>::type* lo,
+                                                typename LpOp<L>::type* hi, float mul, float inv_next) {
+  if constexpr (L == Lp::FP8) {
+    float r[16];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
-    w[2 * q] = relu16x2(cvt2<L>(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
-    w[2 * q + 1] = relu16x2(cvt2<L>(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+      const float bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float z = acc[4 * q + k] * mul + bv[k];
+        r[4 * q + k] = (z < 0.0f ? 0.0f : z) * inv_next;
+      }
+    }
+    *lo = x8_of<L>(r);
+    *hi = x8_of<L>(r + 8);
+  } else {
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+      w[2 * q] = relu16x2(cvt2<L>(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
+      w[2 * q + 1] = relu16x2(cvt2<L>(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
+    }
+    *lo = mk4(w[0], w[1], w[2], w[3]);
+    *hi = mk4(w[4], w[5], w[6], w[7]);
   }
-  *lo = mk4(w[0], w[1], w[2], w[3]);
-  *hi = mk4(w[4], w[5], w[6], w[7]);
 }
 
 // One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `valid`) over KS K-steps, the
@@ -396,17 +446,19 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
 constexpr int kPrefetch = 2;
 
 template <Lp L, int KS, int CT, int S>
-__device__ __forceinline__ void chunk_mfma(const u32x4* wb, int ks_stride, const u32x4 (&b)[S], int lane, int valid,
+__device__ __forceinline__ void chunk_mfma(const typename LpOp<L>::type* wb, int ks_stride,
+                                           const typename LpOp<L>::type (&b)[S], int lane, int valid,
                                            f32x16_t (&acc)[CT]) {
+  typedef typename LpOp<L>::type Op;
   constexpr int PD = kPrefetch < KS ? kPrefetch : KS;
-  u32x4 ring[PD][CT];
+  Op ring[PD][CT];
 #pragma unroll
   for (int d = 0; d < PD; ++d)
 #pragma unroll
-    for (int u = 0; u < CT; ++u) ring[d][u] = u < valid ? wb[(u * ks_stride + d) * 64 + lane] : u32x4{};
+    for (int u = 0; u < CT; ++u) ring[d][u] = u < valid ? wb[(u * ks_stride + d) * 64 + lane] : Op{};
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
-    u32x4 cur[CT];
+    Op cur[CT];
 #pragma unroll
     for (int u = 0; u < CT; ++u) cur[u] = ring[s % PD][u];
     if (s + PD < KS) {
@@ -421,23 +473,43 @@ __device__ __forceinline__ void chunk_mfma(const u32x4* wb, int ks_stride, const
   }
 }
 
+// Per-layer FP8 factors: mul[k] = s_x s_w rescales layer k's products, inv[k] = 1 / s_x divides its
+// input (both exact: the scales are powers of two).  Unused (1) for the 16-bit formats.
+struct Fp8Factors {
+  float mul[kMaxLayers], inv[kMaxLayers + 1];
+};
+
+template <Lp L>
+__device__ __forceinline__ Fp8Factors fp8_factors(const InferArgs& a) {
+  Fp8Factors f;
+#pragma unroll
+  for (int k = 0; k < kMaxLayers; ++k) {
+    const bool on = L == Lp::FP8 && k < a.n_layers;
+    f.mul[k] = on ? a.fp8_scales[2 * k] * a.fp8_scales[2 * k + 1] : 1.0f;
+    f.inv[k] = on ? 1.0f / a.fp8_scales[2 * k] : 1.0f;
+  }
+  f.inv[kMaxLayers] = 1.0f;
+  return f;
+}
+
 // One middle hidden layer: every chunk (CT output tiles over the full K) through the matrix cores,
-// bias + ReLU + 16-bit conversion into `out`; the next chunk's DMA runs under the products.
+// bias + ReLU + conversion into `out`; the next chunk's DMA runs under the products.
 template <Lp L, int S, int T, int CT, int PR, int NT, int CH>
-__device__ __forceinline__ void hidden_layer(const u32x4 (&in)[S], u32x4 (&out)[S], const float* bl,
-                                             const u32x4* __restrict__ wp, const ChunkTable& ct, u32x4* smem, int& c,
-                                             int tid, int lane, int g) {
+__device__ __forceinline__ void hidden_layer(const typename LpOp<L>::type (&in)[S], typename LpOp<L>::type (&out)[S],
+                                             const float* bl, float mul, float inv_next, const u32x4* __restrict__ wp,
+                                             const ChunkTable& ct, u32x4* smem, int& c, int tid, int lane, int g) {
+  typedef typename LpOp<L>::type Op;
 #pragma unroll
   for (int tc = 0; tc < T / CT; ++tc) {
     if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
     f32x16_t acc[CT];
 #pragma unroll
     for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
-    chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, in, lane, CT, acc);
+    chunk_mfma<L, S, CT, S>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), S, in, lane, CT, acc);
 #pragma unroll
     for (int u = 0; u < CT; ++u) {
       const int t = CT * tc + u;
-      hidden_epilogue<L>(acc[u], bl + 32 * t, g, &out[2 * t], &out[2 * t + 1]);
+      hidden_epilogue<L>(acc[u], bl + 32 * t, g, &out[2 * t], &out[2 * t + 1], mul, inv_next);
     }
     wait_dma();
     __syncthreads();
@@ -448,10 +520,11 @@ __device__ __forceinline__ void hidden_layer(const u32x4 (&in)[S], u32x4 (&out)[
 template <Lp L, int HID, int KS0, int NH>
 __global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_infer_lds(InferArgs a, ChunkTable ct) {
+  typedef typename LpOp<L>::type Op;
   constexpr int S = HID / 16;
   constexpr int T = HID / 32;
   constexpr int CT = kChunkTiles;
-  constexpr int CH = CT * S * 64;                       // u32x4 per chunk buffer
+  constexpr int CH = CT * S * 64 * (int)sizeof(Op) / 16;  // u32x4 per chunk buffer
   constexpr int NT = 64 * kLdsWaves;                    // threads
   constexpr int PR = (CH + NT - 1) / NT;                // DMA slots per thread
   static_assert(T % CT == 0 && kHeadTiles % CT == 0, "chunk tiles must divide the tile counts");
@@ -468,24 +541,29 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   const int64_t id = pos0 + j <= last ? pos0 + j : last;
   const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
   const u32x4* wp = reinterpret_cast<const u32x4*>(a.wpack);
+  const Fp8Factors f8 = fp8_factors<L>(a);
 
   chunk_dma<PR, NT>(wp, ct.src[0], ct.len[0], smem, tid);
   for (int i = tid; i < 256; i += NT) tab[i] = (float)i / 255.0f;
   for (int i = tid; i < ct.n_bias; i += NT) bias_s[i] = a.bias[i];
 
   // grid features: the first layer's B operands
-  u32x4 x0[KS0];
+  Op x0[KS0];
 #pragma unroll
   for (int s = 0; s < KS0; ++s) {
     float v[8];
     dev::features<8>(a.grid, 16 * s + 8 * g, bx, by, v);
+    if constexpr (L == Lp::FP8) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] *= f8.inv[0];
+    }
     x0[s] = x8_of<L>(v);
   }
   wait_dma();
   __syncthreads();
 
   int c = 0;
-  u32x4 bin[S], bout[S];
+  Op bin[S], bout[S];
   {
     const float* bl = bias_s + a.bias_off[0];
 #pragma unroll
@@ -494,11 +572,11 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
       f32x16_t acc[CT];
 #pragma unroll
       for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
-      chunk_mfma<L, KS0, CT, KS0>(smem + (c & 1) * CH, KS0, x0, lane, CT, acc);
+      chunk_mfma<L, KS0, CT, KS0>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), KS0, x0, lane, CT, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
         const int t = CT * tc + u;
-        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bin[2 * t], &bin[2 * t + 1]);
+        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bin[2 * t], &bin[2 * t + 1], f8.mul[0], f8.inv[1]);
       }
       wait_dma();
       __syncthreads();
@@ -510,16 +588,24 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   if constexpr (NH >= 0) {
     static_assert(NH <= 2, "at most two unrolled middle layers");
     if constexpr (NH >= 1)
-      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[1], wp, ct, smem, c, tid, lane, g);
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[1], f8.mul[1], f8.inv[2], wp, ct, smem, c,
+                                            tid, lane, g);
     if constexpr (NH >= 2)
-      hidden_layer<L, S, T, CT, PR, NT, CH>(bout, bin, bias_s + a.bias_off[2], wp, ct, smem, c, tid, lane, g);
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bout, bin, bias_s + a.bias_off[2], f8.mul[2], f8.inv[3], wp, ct, smem, c,
+                                            tid, lane, g);
     if constexpr (NH == 1) {
 #pragma unroll
       for (int s = 0; s < S; ++s) bin[s] = bout[s];
     }
   } else {
     for (int layer = 1; layer < a.n_layers - 1; ++layer) {
-      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], wp, ct, smem, c, tid, lane, g);
+      float mul = 1.0f, inv_next = 1.0f;
+      if constexpr (L == Lp::FP8) {
+        mul = a.fp8_scales[2 * layer] * a.fp8_scales[2 * layer + 1];
+        inv_next = 1.0f / a.fp8_scales[2 * layer + 2];
+      }
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], mul, inv_next, wp, ct, smem, c, tid,
+                                            lane, g);
 #pragma unroll
       for (int s = 0; s < S; ++s) bin[s] = bout[s];
     }
@@ -528,6 +614,8 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   const int head = a.n_layers - 1;
   const int nht = a.otiles[head];
   const float* bl = bias_s + a.bias_off[head];
+  float head_mul = 1.0f;
+  if constexpr (L == Lp::FP8) head_mul = a.fp8_scales[2 * head] * a.fp8_scales[2 * head + 1];
   f32x16_t hacc[kHeadTiles];
 #pragma unroll
   for (int t = 0; t < kHeadTiles; ++t) hacc[t] = f32x16_t{};
@@ -538,7 +626,7 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
       f32x16_t acc[CT];
 #pragma unroll
       for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
-      chunk_mfma<L, S, CT, S>(smem + (c & 1) * CH, S, bin, lane, nht - CT * tc, acc);
+      chunk_mfma<L, S, CT, S>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), S, bin, lane, nht - CT * tc, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) hacc[CT * tc + u] = acc[u];
       wait_dma();
@@ -555,7 +643,10 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
         const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
         const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hacc[t][4 * q + r] = sigmoid_fast(hacc[t][4 * q + r] + bv[r]);
+        for (int r = 0; r < 4; ++r) {
+          const float z = L == Lp::FP8 ? hacc[t][4 * q + r] * head_mul : hacc[t][4 * q + r];
+          hacc[t][4 * q + r] = sigmoid_fast(z + bv[r]);
+        }
       }
     }
   }
@@ -583,7 +674,15 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
 }
 
 // ------------------------------------------------------------------------------ FP32 kernel
-template <int HID>
+// CALIB: FP8 calibration pass over the sample ids i * stride (i < n): records max |input| of every
+// layer (float bits; non-negative floats order like their bits) and stops before the heads.
+__device__ __forceinline__ void record_max(unsigned* slot, float m) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
+}
+
+template <int HID, bool CALIB>
 __global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
   constexpr int S = HID / 4;   // K-steps (of 4) of a hidden input
   constexpr int T = HID / 16;  // output tiles of a hidden layer
@@ -594,16 +693,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t pos0 = a.first + (tile * kWaves + wave) * 16;
   const int64_t last = a.first + a.n - 1;
-  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  int64_t id = pos0 + j <= last ? pos0 + j : last;
+  if constexpr (CALIB) id *= a.stride;  // first = 0: sample index -> block id
   const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
 
   float bin[S];
+  float m_in = 0.0f;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     float v[1] = {0.0f};
     if (s < a.ksteps[0]) dev::features<1>(a.grid, 4 * s + g, bx, by, v);
     bin[s] = v[0];
+    m_in = fmaxf(m_in, fabsf(v[0]));
   }
+  if constexpr (CALIB) record_max(&a.amax[0], m_in);
   const float* wp = reinterpret_cast<const float*>(a.wpack);
   for (int layer = 0; layer < a.n_layers - 1; ++layer) {
     const int ks = a.ksteps[layer];
@@ -634,7 +737,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) bin[s] = bout[s];
+    if constexpr (CALIB) {
+      float m = 0.0f;
+#pragma unroll
+      for (int s = 0; s < S; ++s) m = fmaxf(m, bin[s]);
+      record_max(&a.amax[layer + 1], m);
+    }
   }
+  if constexpr (CALIB) return;
   float* y = lds + wave * 16 * a.head_stride;
   {
     const int layer = a.n_layers - 1;
@@ -673,6 +783,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
 }
 
 // ------------------------------------------------------------------------------ host side
+constexpr int64_t kCalibBytes = 256;  // 2 x kMaxLayers maxima, padded
+
 struct Plan {
   Shape s;
   int precision;
@@ -688,19 +800,18 @@ struct Plan {
 int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
   int st = make_shape(d, &p->s);
   if (st != NTBC_OK) return st;
-  if (precision != NTBC_FP32 && precision != NTBC_BF16 && precision != NTBC_FP16)
-    return fail(precision == NTBC_FP8_E4M3 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
-                "precision %d not available for inference", precision);
+  if (precision != NTBC_FP32 && precision != NTBC_BF16 && precision != NTBC_FP16 && precision != NTBC_FP8_E4M3)
+    return fail(NTBC_EINVAL, "precision %d not available for inference", precision);
   if (p->s.n_layers > kMaxLayers) return fail(NTBC_EUNSUPPORTED, "at most %d layers", kMaxLayers);
   p->precision = precision;
   const int h = p->s.hidden;
   p->hid_inst = h <= 64 ? 64 : (h <= 128 ? 128 : 256);
   if (p->s.in_dim > p->hid_inst) return fail(NTBC_EUNSUPPORTED, "in_dim %d > kernel width %d", p->s.in_dim, p->hid_inst);
-  const bool bf = precision == NTBC_BF16 || precision == NTBC_FP16;  // 16-bit operands
+  const bool bf = precision != NTBC_FP32;  // 32x32x16 matrix shapes (16-bit or FP8 operands)
   p->rows = bf ? 32 : 16;
   p->kstep = bf ? 16 : 4;
   p->positions_per_wave = bf ? 32 : 16;
-  const int64_t unit = bf ? 16 : 4;  // bytes per lane operand
+  const int64_t unit = precision == NTBC_FP8_E4M3 ? 8 : (bf ? 16 : 4);  // bytes per lane operand
   int64_t off = 0, boff = 0;
   for (int k = 0; k < p->s.n_layers; ++k) {
     const int in = k == 0 ? p->s.in_dim : p->hid_inst;
@@ -715,7 +826,102 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
   p->pack_bytes = off * unit;
   p->bias_bytes = boff * 4;
   p->total_bytes = ((p->pack_bytes + 255) / 256) * 256 + p->bias_bytes;
+  if (precision == NTBC_FP8_E4M3) {
+    // FP8 calibration (ntbc_fp8_calibrate) packs FP32 weights and keeps per-layer maxima in the same
+    // workspace
+    Plan f;
+    const int st32 = make_plan(d, NTBC_FP32, &f);
+    if (st32 != NTBC_OK) return st32;
+    p->total_bytes = std::max(p->total_bytes, f.total_bytes + kCalibBytes);
+  }
   return NTBC_OK;
+}
+
+// ------------------------------------------------------------------------------ FP8 calibration
+struct WMaxArgs {
+  const float* w;
+  int n_layers;
+  int64_t w_off[kMaxLayers], count[kMaxLayers];
+  unsigned* amax;  // [kMaxLayers] inputs, then [kMaxLayers] weights (float bits)
+};
+
+// max |W| of every layer's weight matrix (its bias excluded); grid (blocks, n_layers).
+__global__ void __launch_bounds__(256) k_weight_absmax(WMaxArgs a) {
+  const int layer = blockIdx.y;
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count[layer];
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(a.w[a.w_off[layer] + i]));
+  record_max(&a.amax[kMaxLayers + layer], m);
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// The smallest power of two s (down to 2^-126) with m / s <= 448; 1 for m = 0 or not finite.  Every
+// comparison is exact (448 * 2^e is a float), so the result is a pure function of m.
+__device__ float pow2_scale(float m) {
+  if (!(m > 0.0f) || !(m <= 3.4028235e38f)) return 1.0f;
+  int e = ilogbf(m) + 1 - 9;
+  while (m > ldexpf(448.0f, e)) ++e;
+  while (e > -126 && m <= ldexpf(448.0f, e - 1)) --e;
+  return ldexpf(1.0f, e);
+}
+
+__global__ void k_fp8_finalize(const unsigned* __restrict__ amax, int n_layers, float* __restrict__ scales) {
+  const int k = threadIdx.x;
+  if (k < n_layers) {
+    scales[2 * k] = pow2_scale(__uint_as_float(amax[k]));
+    scales[2 * k + 1] = pow2_scale(__uint_as_float(amax[kMaxLayers + k]));
+  }
+}
+
+// Kernel arguments common to inference and calibration: the grid view, the packed-weight plan and the
+// texture layout (block range, outputs and workspace pointers are set by the caller).
+InferArgs infer_args(const Plan& p, const ntbc_model_desc* d, const ntbc_params* prm) {
+  const Shape& s = p.s;
+  InferArgs a{};
+  a.grid.u8 = d->grid_dtype == NTBC_GRID_U8 ? static_cast<const uint8_t*>(prm->grid) : nullptr;
+  a.grid.f32 = d->grid_dtype == NTBC_GRID_F32 ? static_cast<const float*>(prm->grid) : nullptr;
+  a.grid.scale = prm->grid_scale;
+  a.grid.zero = prm->grid_zero;
+  a.grid.n_levels = s.n_levels;
+  a.grid.base_res = s.base_res;
+  a.grid.n_features = s.n_features;
+  a.grid.blocks_w = s.blocks_w;
+  a.grid.blocks_h = s.blocks_h;
+  for (int l = 0; l <= s.n_levels; ++l) a.grid.level_offset[l] = s.level_offset[l];
+  auto pow2_shift = [&](int blocks) {
+    const int64_t den = 2 * (int64_t)blocks;
+    const int64_t top = (int64_t)s.base_res << (s.n_levels - 1);
+    if ((den & (den - 1)) != 0 || (2 * (int64_t)blocks + 1) * top >= (1ll << 31) || top * den >= (1ll << 31)) return -1;
+    int sh = 0;
+    while ((1ll << sh) < den) ++sh;
+    return sh;
+  };
+  a.grid.shift_x = pow2_shift(s.blocks_w);
+  a.grid.shift_y = pow2_shift(s.blocks_h);
+  for (int k = 0; k < s.n_layers; ++k) {
+    a.pack_off[k] = p.pack_off[k];
+    a.bias_off[k] = p.bias_off[k];
+    a.ksteps[k] = p.ksteps[k];
+    a.otiles[k] = p.otiles[k];
+  }
+  a.n_layers = s.n_layers;
+  a.head_dim = s.head_dim;
+  a.head_stride = s.head_dim | 1;
+  a.n_textures = s.n_textures;
+  for (int t = 0; t < s.n_textures; ++t) {
+    a.formats[t] = s.formats[t];
+    a.ep_off[t] = s.ep_off[t];
+    a.ch_off[t] = s.ch_off[t];
+  }
+  a.endpoint_dim = s.endpoint_dim;
+  a.channels = s.channels;
+  a.fp8_scales = prm->fp8_scales;
+  a.stride = 1;
+  return a;
 }
 
 }  // namespace
@@ -753,6 +959,13 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   NTBC_REQUIRE(first_block >= 0 && n_blocks >= 0 && first_block + n_blocks <= s.n_positions,
                "block range [%lld, %lld) outside 0..%lld", (long long)first_block,
                (long long)(first_block + n_blocks), (long long)s.n_positions);
+  const bool lp16 = precision == NTBC_BF16 || precision == NTBC_FP16;
+  const bool fp8 = precision == NTBC_FP8_E4M3;
+  const bool lds_shape = p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2;
+  if (fp8) {
+    NTBC_REQUIRE(prm->fp8_scales != nullptr, "FP8 needs fp8_scales (see ntbc_fp8_calibrate)");
+    if (!lds_shape) return fail(NTBC_EUNSUPPORTED, "FP8 needs head_dim <= %d, in_dim <= 64 and a hidden layer", 32 * kHeadTiles);
+  }
   if (n_blocks == 0) return NTBC_OK;
   NTBC_REQUIRE(blocks_out != nullptr, "blocks_out is NULL");
   if (workspace == nullptr || workspace_bytes < (size_t)p.total_bytes)
@@ -776,9 +989,12 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     pa.pack_off[k] = p.pack_off[k];
     pa.bias_off[k] = p.bias_off[k];
   }
+  pa.fp8_scales = prm->fp8_scales;
   if (!(prm->flags & NTBC_REUSE_PACKED)) {
     const dim3 pgrid(64, s.n_layers);
-    if (precision == NTBC_BF16)
+    if (fp8)
+      hipLaunchKernelGGL(k_pack_lp<Lp::FP8>, pgrid, dim3(256), 0, strm, pa, static_cast<u32x2*>(wpack), bias);
+    else if (precision == NTBC_BF16)
       hipLaunchKernelGGL(k_pack_lp<Lp::BF16>, pgrid, dim3(256), 0, strm, pa, static_cast<u32x4*>(wpack), bias);
     else if (precision == NTBC_FP16)
       hipLaunchKernelGGL(k_pack_lp<Lp::FP16>, pgrid, dim3(256), 0, strm, pa, static_cast<u32x4*>(wpack), bias);
@@ -788,61 +1004,26 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     if (st != NTBC_OK) return st;
   }
 
-  InferArgs a{};
-  a.grid.u8 = d->grid_dtype == NTBC_GRID_U8 ? static_cast<const uint8_t*>(prm->grid) : nullptr;
-  a.grid.f32 = d->grid_dtype == NTBC_GRID_F32 ? static_cast<const float*>(prm->grid) : nullptr;
-  a.grid.scale = prm->grid_scale;
-  a.grid.zero = prm->grid_zero;
-  a.grid.n_levels = s.n_levels;
-  a.grid.base_res = s.base_res;
-  a.grid.n_features = s.n_features;
-  a.grid.blocks_w = s.blocks_w;
-  a.grid.blocks_h = s.blocks_h;
-  for (int l = 0; l <= s.n_levels; ++l) a.grid.level_offset[l] = s.level_offset[l];
-  auto pow2_shift = [&](int blocks) {
-    const int64_t den = 2 * (int64_t)blocks;
-    const int64_t top = (int64_t)s.base_res << (s.n_levels - 1);
-    if ((den & (den - 1)) != 0 || (2 * (int64_t)blocks + 1) * top >= (1ll << 31) || top * den >= (1ll << 31)) return -1;
-    int sh = 0;
-    while ((1ll << sh) < den) ++sh;
-    return sh;
-  };
-  a.grid.shift_x = pow2_shift(s.blocks_w);
-  a.grid.shift_y = pow2_shift(s.blocks_h);
+  InferArgs a = infer_args(p, d, prm);
   a.wpack = wpack;
   a.bias = bias;
-  for (int k = 0; k < s.n_layers; ++k) {
-    a.pack_off[k] = p.pack_off[k];
-    a.bias_off[k] = p.bias_off[k];
-    a.ksteps[k] = p.ksteps[k];
-    a.otiles[k] = p.otiles[k];
-  }
-  a.n_layers = s.n_layers;
-  a.head_dim = s.head_dim;
-  a.head_stride = s.head_dim | 1;
-  a.n_textures = s.n_textures;
-  for (int t = 0; t < s.n_textures; ++t) {
-    a.formats[t] = s.formats[t];
-    a.ep_off[t] = s.ep_off[t];
-    a.ch_off[t] = s.ch_off[t];
-  }
-  a.endpoint_dim = s.endpoint_dim;
-  a.channels = s.channels;
   a.first = first_block;
   a.n = n_blocks;
   a.out = blocks_out;
   a.heads = heads_out;
 
   const int ppw = p.positions_per_wave;
-  const bool lp16 = precision == NTBC_BF16 || precision == NTBC_FP16;
-  if (lp16 && p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2) {
+  if ((lp16 || fp8) && lds_shape) {
+    // chunk offsets and lengths in 16-byte units (an FP8 operand is 8 bytes; every chunk holds a
+    // multiple of 64 operands)
+    const int64_t op_bytes = fp8 ? 8 : 16;
     ChunkTable ct{};
     for (int k = 0; k < s.n_layers; ++k) {
       for (int t0 = 0; t0 < p.otiles[k]; t0 += kChunkTiles) {
         NTBC_REQUIRE(ct.n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
         const int nt = std::min(kChunkTiles, p.otiles[k] - t0);
-        ct.src[ct.n] = p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64;
-        ct.len[ct.n] = nt * p.ksteps[k] * 64;
+        ct.src[ct.n] = (p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64) * op_bytes / 16;
+        ct.len[ct.n] = (int)((int64_t)nt * p.ksteps[k] * 64 * op_bytes / 16);
         ++ct.n;
       }
     }
@@ -850,7 +1031,7 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     int64_t nb = 0;
     for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
     ct.n_bias = (int)((nb + 3) / 4 * 4);
-    const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * sizeof(u32x4);
+    const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * op_bytes;
     const size_t ybytes = (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
     const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
     ct.stage = (int)(stage / sizeof(u32x4));
@@ -861,15 +1042,16 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     // generic instances (run-time middle-layer count), then the unrolled ones for the shapes of the
     // paper-scale (width 256, 64 inputs) and mid (width 128, 48 inputs) models with two middle layers
     const int mid = s.n_layers - 2;
+    const Lp want = fp8 ? Lp::FP8 : (precision == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
 #define NTBC_LDS_INSTANCE_L(LP, H, K, NH)                                                             \
-    if (p.hid_inst == H && p.ksteps[0] == K && (NH < 0 || NH == mid) &&                              \
-        (precision == NTBC_FP16) == (LP == Lp::FP16)) {                                              \
+    if (p.hid_inst == H && p.ksteps[0] == K && (NH < 0 || NH == mid) && want == LP) {                \
       fn = (const void*)k_infer_lds<LP, H, K, NH>;                                                   \
       launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
         hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH>), gr, bl, sh, st, x, y);                       \
       };                                                                                             \
     }
-#define NTBC_LDS_INSTANCE(H, K, NH) NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH)
+#define NTBC_LDS_INSTANCE(H, K, NH) \
+    NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP8, H, K, NH)
     NTBC_LDS_INSTANCE(64, 1, -1) NTBC_LDS_INSTANCE(64, 2, -1) NTBC_LDS_INSTANCE(64, 3, -1) NTBC_LDS_INSTANCE(64, 4, -1)
     NTBC_LDS_INSTANCE(128, 1, -1) NTBC_LDS_INSTANCE(128, 2, -1) NTBC_LDS_INSTANCE(128, 3, -1) NTBC_LDS_INSTANCE(128, 4, -1)
     NTBC_LDS_INSTANCE(256, 1, -1) NTBC_LDS_INSTANCE(256, 2, -1) NTBC_LDS_INSTANCE(256, 3, -1) NTBC_LDS_INSTANCE(256, 4, -1)
@@ -895,8 +1077,8 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
                          ? (p.hid_inst == 64 ? (const void*)k_infer_lp<Lp::FP16, 64>
                                              : (p.hid_inst == 128 ? (const void*)k_infer_lp<Lp::FP16, 128>
                                                                   : (const void*)k_infer_lp<Lp::FP16, 256>))
-                         : (p.hid_inst == 64 ? (const void*)k_infer_f32<64>
-                                             : (p.hid_inst == 128 ? (const void*)k_infer_f32<128> : (const void*)k_infer_f32<256>));
+                         : (p.hid_inst == 64 ? (const void*)k_infer_f32<64, false>
+                                             : (p.hid_inst == 128 ? (const void*)k_infer_f32<128, false> : (const void*)k_infer_f32<256, false>));
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
   if (precision == NTBC_BF16) {
@@ -908,9 +1090,73 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     else if (p.hid_inst == 128) hipLaunchKernelGGL((k_infer_lp<Lp::FP16, 128>), grid, block, lds, strm, a);
     else hipLaunchKernelGGL((k_infer_lp<Lp::FP16, 256>), grid, block, lds, strm, a);
   } else {
-    if (p.hid_inst == 64) hipLaunchKernelGGL(k_infer_f32<64>, grid, block, lds, strm, a);
-    else if (p.hid_inst == 128) hipLaunchKernelGGL(k_infer_f32<128>, grid, block, lds, strm, a);
-    else hipLaunchKernelGGL(k_infer_f32<256>, grid, block, lds, strm, a);
+    if (p.hid_inst == 64) hipLaunchKernelGGL((k_infer_f32<64, false>), grid, block, lds, strm, a);
+    else if (p.hid_inst == 128) hipLaunchKernelGGL((k_infer_f32<128, false>), grid, block, lds, strm, a);
+    else hipLaunchKernelGGL((k_infer_f32<256, false>), grid, block, lds, strm, a);
   }
   return check_launch("ntbc_infer_blocks");
+}
+
+extern "C" int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* prm, int64_t n_sample, float* scales_out,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+  Plan p8, p;
+  int st = make_plan(d, NTBC_FP8_E4M3, &p8);
+  if (st != NTBC_OK) return st;
+  st = make_plan(d, NTBC_FP32, &p);
+  if (st != NTBC_OK) return st;
+  const Shape& s = p.s;
+  NTBC_REQUIRE(prm != nullptr && prm->grid != nullptr && prm->weights != nullptr, "params, grid or weights is NULL");
+  if (d->grid_dtype == NTBC_GRID_U8)
+    NTBC_REQUIRE(prm->grid_scale != nullptr && prm->grid_zero != nullptr, "U8 grid needs grid_scale and grid_zero");
+  NTBC_REQUIRE(n_sample >= 1, "n_sample %lld < 1", (long long)n_sample);
+  NTBC_REQUIRE(scales_out != nullptr, "scales_out is NULL");
+  if (workspace == nullptr || workspace_bytes < (size_t)p8.total_bytes)
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)p8.total_bytes);
+  hipStream_t strm = as_stream(stream);
+
+  char* ws = static_cast<char*>(workspace);
+  float* wpack = reinterpret_cast<float*>(ws);
+  float* bias = reinterpret_cast<float*>(ws + ((p.pack_bytes + 255) / 256) * 256);
+  unsigned* amax = reinterpret_cast<unsigned*>(ws + p.total_bytes);  // 2 * kMaxLayers words
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, strm, amax, 2 * kMaxLayers);
+
+  PackArgs pa{};
+  pa.w = prm->weights;
+  pa.n_layers = s.n_layers;
+  WMaxArgs wm{};
+  wm.w = prm->weights;
+  wm.n_layers = s.n_layers;
+  wm.amax = amax;
+  for (int k = 0; k < s.n_layers; ++k) {
+    pa.in_dim[k] = s.layer_in[k];
+    pa.out_dim[k] = s.layer_out[k];
+    pa.w_off[k] = s.w_off[k];
+    pa.b_off[k] = s.b_off[k];
+    pa.ksteps[k] = p.ksteps[k];
+    pa.otiles[k] = p.otiles[k];
+    pa.pack_off[k] = p.pack_off[k];
+    pa.bias_off[k] = p.bias_off[k];
+    wm.w_off[k] = s.w_off[k];
+    wm.count[k] = (int64_t)s.layer_in[k] * s.layer_out[k];
+  }
+  hipLaunchKernelGGL(k_pack_f32, dim3(64, s.n_layers), dim3(256), 0, strm, pa, wpack, bias);
+  hipLaunchKernelGGL(k_weight_absmax, dim3(64, s.n_layers), dim3(256), 0, strm, wm);
+  st = check_launch("ntbc_fp8_calibrate: weights");
+  if (st != NTBC_OK) return st;
+
+  InferArgs a = infer_args(p, d, prm);
+  a.wpack = wpack;
+  a.bias = bias;
+  a.first = 0;
+  a.n = std::min<int64_t>(n_sample, s.n_positions);
+  a.stride = std::max<int64_t>(1, s.n_positions / n_sample);
+  a.amax = amax;
+  const dim3 grid((unsigned)ceil_div(a.n, (int64_t)16 * kWaves)), block(64 * kWaves);
+  if (p.hid_inst == 64) hipLaunchKernelGGL((k_infer_f32<64, true>), grid, block, 0, strm, a);
+  else if (p.hid_inst == 128) hipLaunchKernelGGL((k_infer_f32<128, true>), grid, block, 0, strm, a);
+  else hipLaunchKernelGGL((k_infer_f32<256, true>), grid, block, 0, strm, a);
+  st = check_launch("ntbc_fp8_calibrate: activations");
+  if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_fp8_finalize, dim3(1), dim3(64), 0, strm, amax, s.n_layers, scales_out);
+  return check_launch("ntbc_fp8_calibrate");
 }

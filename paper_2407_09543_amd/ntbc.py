@@ -78,6 +78,7 @@ _SIGNATURES = {
     "ntbc_bc_decode": ([_P, _I32, _I32, _I32, _P, _I32, _P], ctypes.c_int),
     "ntbc_block_sse": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "ntbc_fallback": ([_P, _P, _P, _P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
+    "ntbc_fp8_calibrate": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I64, _P, _P, _SZ, _P], _I32),
     "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
                            _P, _SZ, _P], ctypes.c_int),
     "ntbc_forward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P], ctypes.c_int),
@@ -235,6 +236,20 @@ class Model:
             n = workspace_size(self.desc, precision, 0)
             self._ws[precision] = torch.empty(max(n, 1), dtype=torch.uint8, device=self.weights.device)
         return self._ws[precision]
+
+    def fp8_calibrate(self, n_sample: int = 65536) -> torch.Tensor:
+        """Per-layer FP8 scales [n_layers][2] = (s_x, s_w) from ntbc_fp8_calibrate; kept on the model for
+        FP8 inference."""
+        n_layers = len(self._layer_count())
+        scales = torch.empty((n_layers, 2), dtype=torch.float32, device=self.weights.device)
+        ws = self.workspace(FP8_E4M3)
+        _check(lib().ntbc_fp8_calibrate(ctypes.byref(self.desc), ctypes.byref(self.params()), n_sample, _ptr(scales),
+                                        _ptr(ws), ws.numel(), _stream()))
+        self.fp8_scales = scales
+        return scales
+
+    def _layer_count(self):
+        return range(self.desc.n_hidden + 1)
 
     def infer(self, precision: int = BF16, first_block: int = 0, n_blocks: Optional[int] = None,
               heads: bool = False, out: Optional[torch.Tensor] = None, reuse_packed: bool = False):

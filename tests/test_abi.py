@@ -65,3 +65,26 @@ def test_invalid_arguments_rejected_on_host():
     bad.hidden_width = 48
     with pytest.raises(ntbc.NtbcError):
         ntbc.model_sizes(bad)
+
+
+def test_fp8_arguments_rejected_on_host():
+    ensure_built()
+    lib = ntbc.lib()
+    desc = ntbc.desc_from_config(synth.config_small())
+    dummy = ctypes.c_void_p(0x1000)
+    p = ntbc.Params()
+    p.grid, p.weights = 0x1000, 0x1000
+    # FP8 without scales; calibration with n_sample < 1 or without an output
+    n_ws = ntbc.workspace_size(desc, ntbc.FP8_E4M3, 0)
+    assert n_ws > 0
+    assert lib.ntbc_infer_blocks(ctypes.byref(desc), ctypes.byref(p), ntbc.FP8_E4M3, 0, 16, dummy, None, dummy,
+                                 n_ws, None) == ntbc.EINVAL
+    assert b"fp8_scales" in lib.ntbc_last_error()
+    assert lib.ntbc_fp8_calibrate(ctypes.byref(desc), ctypes.byref(p), 0, dummy, dummy, n_ws, None) == ntbc.EINVAL
+    assert lib.ntbc_fp8_calibrate(ctypes.byref(desc), ctypes.byref(p), 64, None, dummy, n_ws, None) == ntbc.EINVAL
+    assert lib.ntbc_fp8_calibrate(ctypes.byref(desc), ctypes.byref(p), 64, dummy, dummy, 16, None) == ntbc.ENOWORKSPACE
+    # a first layer wider than 64 inputs has no FP8 kernel
+    wide = ntbc.make_desc(8, 8, 16, False, 256, 3, [ntbc.BC1, ntbc.BC4], 64, 64)
+    p.fp8_scales = 0x1000
+    assert lib.ntbc_infer_blocks(ctypes.byref(wide), ctypes.byref(p), ntbc.FP8_E4M3, 0, 16, dummy, None, dummy,
+                                 1 << 30, None) == ntbc.EUNSUPPORTED
