@@ -204,6 +204,9 @@ def main():
             "psnr_db_ntbc": ntbc_psnr, "psnr_db_after_judge": judged_psnr, "psnr_db_ref_encoder": ref_psnr,
             "judge": {"kappa": args.kappa, "delta": 0.0, "fallback_blocks": res.fallback_blocks},
             "model_bytes_bf16_weights": encode.model_bytes(cfg, 2), "bc_bytes": bc_bytes,
+            "storage_matched_baseline": {"what": "reference BC of the 2x2-averaged texture, nearest upsampled",
+                                         "bytes": bc_bytes // 4,
+                                         "psnr_db": encode.downsampled_ref_psnr(tex, cfg.formats, args.size)},
         }
         model_note = "parameters trained by the encode above"
     n_blocks = cfg.n_positions * len(cfg.formats)

@@ -97,3 +97,20 @@ def psnr_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats
 def model_bytes(cfg, weight_bytes: int = 2) -> int:
     """Stored size: uint8 grid + per-level (scale, zero) + weights at `weight_bytes` each."""
     return cfg.grid_vertices * cfg.n_features + 8 * cfg.n_levels + cfg.n_weights * weight_bytes
+
+
+def downsampled_ref_psnr(textures: Sequence[torch.Tensor], formats, size: int) -> List[float]:
+    """A storage-matched non-learned baseline: each texture averaged over 2x2 texels (rounded), encoded
+    by the reference encoder at half resolution (a quarter of the BC bytes), decoded and upsampled by
+    nearest neighbour; decoded PSNR (dB) against the full-resolution texture."""
+    out = []
+    half = size // 2
+    for t, f in zip(textures, formats):
+        x = t.reshape(size, size, -1).float()
+        small = x.reshape(half, 2, half, 2, x.shape[-1]).mean(dim=(1, 3))
+        small = torch.floor(small + 0.5).clamp(0, 255).to(torch.uint8).squeeze(-1).contiguous()
+        dec = ntbc.decode(ntbc.encode_ref(small, f), half, half, f).reshape(half, half, -1).float()
+        up = dec.repeat_interleave(2, dim=0).repeat_interleave(2, dim=1)
+        mse = ((up - x) ** 2).mean().item()
+        out.append(float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse))
+    return out

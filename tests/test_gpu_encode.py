@@ -46,3 +46,58 @@ def test_trained_network_beats_untrained_and_judge():
         words, n_w, r_w = u64(res.words[t]), u64(res.ntbc_words[t]), u64(res.ref_words[t])
         assert ((words == n_w) | (words == r_w)).all()
         assert int((words != n_w).sum()) <= res.fallback_blocks[t]
+
+
+def test_precision_sweep_on_trained_model():
+    # the 1024^2 five-texture model (6 levels up to 256^2, MLP 48-128x3-162) trained with QAT, then
+    # evaluated on the 4096^2 block grid (the network is a function of the normalised block
+    # coordinate): every precision's blocks against the oracle of the same precision on a sample
+    import dataclasses
+    from cases import oracle_levels
+    from oracle import metrics as OM
+    from oracle import ntbc as ON
+    cfg = synth.config_mid(1024)
+    mat = synth.material_five(1024, 2)
+    tex = [torch.from_numpy(t.texels).cuda() for t in mat.textures]
+    res = encode.encode_material(tex, cfg, steps=2000, batch=16384, seed=2)
+    big = dataclasses.replace(cfg, blocks_w=1024, blocks_h=1024)
+    m = res.model
+    model = ntbc.Model(ntbc.desc_from_config(big), m.weights, m.grid, m.grid_scale, m.grid_zero)
+    g = dict(codes=m.grid.cpu().numpy(), scale=m.grid_scale.cpu().numpy(), zero=m.grid_zero.cpu().numpy())
+    lv = oracle_levels(big, g)
+    layers = synth.unflatten_weights(big, res.weights.cpu().numpy())
+    scales = ON.fp8_calibration(big, lv, layers, 4096)
+    model.fp8_scales = torch.tensor(scales, dtype=torch.float32).cuda()
+    ids = np.sort(np.random.default_rng(12).choice(big.n_positions, 2000, replace=False))
+    idt = torch.from_numpy(ids).cuda()
+    words = {}
+    for prec, emu, tol in ((ntbc.FP32, "f64", 1e-5), (ntbc.BF16, "bf16", 1e-2), (ntbc.FP16, "fp16", 2e-3),
+                           (ntbc.FP8_E4M3, "fp8", 1e-1)):
+        w, h = model.infer(prec, heads=True)
+        words[prec] = w
+        y_or = ON.heads(big, lv, layers, ids, emu, scales if emu == "fp8" else None)
+        w_or = ON.pack(y_or, big.formats)
+        hs = h[idt].cpu().numpy()
+        ws = u64(w[:, idt])
+        r = OM.classify_differences(hs, ws, y_or, w_or, big.formats)
+        dy = np.abs(hs.astype(np.float64) - y_or).max()
+        log(f"sweep {emu}: identity vs oracle {OM.identity(ws, w_or):.5f} max|dY| {dy:.3g} differ {r['differ']} "
+            f"ties {r['ties']} identity vs FP32 GPU {float((w == words[ntbc.FP32]).float().mean()):.5f}")
+        assert r["repack_exact"] and r["ties"] == r["differ"] and dy <= tol
+        if prec == ntbc.FP32:
+            assert OM.identity(ws, w_or) >= 0.999
+
+
+def test_storage_matched_baseline_report():
+    # NTBC's bytes against the reference encoder on a 2x-downsampled texture upsampled by nearest
+    # neighbour (a quarter of the BC bytes): PSNR at comparable storage, reported as measured
+    cfg = synth.config_mid(256)
+    mat = synth.material_five(256, 4)
+    tex = [torch.from_numpy(t.texels).cuda() for t in mat.textures]
+    res = encode.encode_material(tex, cfg, steps=600, batch=2048, seed=4)
+    ntbc_psnr = encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, 256)
+    base = encode.downsampled_ref_psnr(tex, cfg.formats, 256)
+    log(f"storage: ntbc {encode.model_bytes(cfg)} B psnr {np.round(ntbc_psnr, 2)}; half-resolution BC "
+        f"{sum(256 * 256 // 16 // 4 * 8 for _ in cfg.formats)} B psnr {np.round(base, 2)}")
+    ref = encode.psnr_of_words(res.ref_words, tex, cfg.formats, 256)
+    assert all(b <= r + 1e-9 for b, r in zip(base, ref))
