@@ -138,6 +138,8 @@ def main():
                     help="base training steps of the encode (plus 10%% with grid QAT)")
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--kappa", type=float, default=4.0, help="judge: fall back when SSE > kappa * SSE_ref")
+    ap.add_argument("--train-precision", choices=("bf16", "fp32"), default="bf16",
+                    help="operands of the training products (FP32 accumulation and master parameters either way)")
     ap.add_argument("--no-encode", action="store_true",
                     help="skip the encode; time inference on random parameters of the same shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -185,9 +187,11 @@ def main():
                            torch.from_numpy(zero).to(dev))
         model_note = "random parameters of the paper-scale shape (inference cost does not depend on values)"
     else:
-        log(f"encoding the material: {args.encode_steps} steps + 10% QAT at batch {args.batch}")
+        log(f"encoding the material: {args.encode_steps} steps + 10% QAT at batch {args.batch}, "
+            f"{args.train_precision} training products")
         res = encode.encode_material(tex, cfg, steps=args.encode_steps, batch=args.batch, seed=3,
-                                     precision=ntbc.BF16, kappa=args.kappa, delta=0.0)
+                                     precision=ntbc.BF16, kappa=args.kappa, delta=0.0,
+                                     train_precision=ntbc.PRECISIONS[args.train_precision])
         model = res.model
         layers = synth.unflatten_weights(cfg, res.weights.cpu().numpy())
         codes = model.grid.cpu().numpy()
@@ -198,6 +202,7 @@ def main():
         bc_bytes = 8 * cfg.n_positions * len(cfg.formats)
         encode_info = {
             "seconds": res.seconds, "train_seconds": res.train_seconds, "steps": res.steps, "batch": args.batch,
+            "train_precision": args.train_precision,
             "ms_per_train_step": res.train_seconds * 1e3 / res.steps,
             "includes": "reference encode of the targets, all training steps, grid quantisation, BF16 "
                         "inference, per-block judge; textures already in HBM",

@@ -197,11 +197,16 @@ typedef struct {
   float temperature;
   int32_t warmup, total_steps;
   int32_t qat;
-  int32_t precision;        /* NTBC_FP32 */
+  int32_t precision;        /* NTBC_FP32, or NTBC_BF16: the MLP products (forward, dX and dW) take
+                               bfloat16 operands on the matrix cores with FP32 accumulation; master
+                               parameters, losses, grid scatter and Adam stay FP32                   */
   float loss_weights[4];    /* weights of L_e, L_c, L_cd(endpoint), L_cd(colour) in the gradient; 1 = paper */
 } ntbc_hparams;
 
 /* Block ids passed to the training entry points are clamped into [0, blocks_w*blocks_h). */
+
+/* Training precision (ntbc_forward, ntbc_backward, ntbc_hparams.precision): NTBC_FP32 or NTBC_BF16
+ * (bfloat16 operands of the MLP products, FP32 accumulation); others return NTBC_EUNSUPPORTED. */
 
 /* Forward pass for a batch (paper Sec. 3.2, Fig. NTBC training, network part): the sigmoid heads of
  * block positions ids[0..n) from the FP32 master grid (fake-quantised per level when qat = 1: Sec. 3.3,

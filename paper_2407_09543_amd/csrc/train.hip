@@ -364,10 +364,184 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   }
 }
 
+// The same product with bfloat16 operands on the matrix cores (v_mfma_f32_32x32x16_bf16, float32
+// accumulation): FP32 operands are rounded to bfloat16 (nearest even) as they are staged in LDS.  A
+// block computes a 128 x 128 tile (wave w: the 64 x 64 quadrant (w/2, w%2) as 2 x 2 products of
+// 32 x 32); K advances in slices of 32, the next slice's operands loaded into registers while the
+// current one is multiplied from LDS (two LDS buffers, one barrier per slice).  LDS holds both
+// operands K-contiguous (As[m][k], Bs[n][k]) so each lane's fragment (row or column l%32, K elements
+// 8(l/32) .. +7) is one 16-byte read; a K-contiguous source is copied as 8-element runs, an M- or
+// N-contiguous source as 4 x 2 blocks transposed into 32-bit pairs.  Accumulator v of lane l is row
+// 8(v/4) + 4(l/32) + v%4, column l%32 of its 32 x 32 product.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
+}
+
+constexpr int kBT = 128;         // block tile (rows and columns)
+constexpr int kBTK = 32;         // K per slice
+constexpr int kBRow = kBTK + 8;  // LDS row stride in bfloat16 (80 bytes)
+
+// One thread's share of a kBT x kBTK operand slice X(r, k) = x[r*sr + k*sk] (r < R, k < kend): two
+// groups of eight values, in registers, then written to LDS rows dst[r][k] as bfloat16.
+struct Stage {
+  float v[2][8];
+};
+
+__device__ __forceinline__ void stage_load(Stage& st, const float* __restrict__ x, int64_t sr, int64_t sk, int r0,
+                                           int R, int k0, int kend, int tid) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int gi = tid + 256 * q;
+    if (sk == 1) {
+      // 8 consecutive k: kBT rows x 4 runs
+      const int r = gi >> 2, kk = (gi & 3) * 8;
+      const int row = r0 + r, k = k0 + kk;
+      const float* src = x + (int64_t)row * sr + k;
+      if (row < R && k + 8 <= kend && (sr & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(src), b = *reinterpret_cast<const float4*>(src + 4);
+        st.v[q][0] = a.x; st.v[q][1] = a.y; st.v[q][2] = a.z; st.v[q][3] = a.w;
+        st.v[q][4] = b.x; st.v[q][5] = b.y; st.v[q][6] = b.z; st.v[q][7] = b.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) st.v[q][e] = (row < R && k + e < kend) ? src[e] : 0.0f;
+      }
+    } else {
+      // 4 consecutive rows x 2 consecutive k: 32 row groups x 16 k pairs
+      const int r = (gi & 31) * 4, kk = (gi >> 5) * 2;
+      const int row = r0 + r, k = k0 + kk;
+      const float* s0 = x + (int64_t)k * sk + row;
+      if (sr == 1 && row + 4 <= R && k + 2 <= kend && (sk & 3) == 0 && (reinterpret_cast<uintptr_t>(s0) & 15) == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(s0), b = *reinterpret_cast<const float4*>(s0 + sk);
+        st.v[q][0] = a.x; st.v[q][1] = a.y; st.v[q][2] = a.z; st.v[q][3] = a.w;
+        st.v[q][4] = b.x; st.v[q][5] = b.y; st.v[q][6] = b.z; st.v[q][7] = b.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          st.v[q][e] = (row + e < R && k < kend) ? x[(int64_t)(row + e) * sr + (int64_t)k * sk] : 0.0f;
+          st.v[q][4 + e] = (row + e < R && k + 1 < kend) ? x[(int64_t)(row + e) * sr + (int64_t)(k + 1) * sk] : 0.0f;
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_store(const Stage& st, bool kcontig, uint16_t (*dst)[kBRow], int tid) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int gi = tid + 256 * q;
+    if (kcontig) {
+      const int r = gi >> 2, kk = (gi & 3) * 8;
+      *reinterpret_cast<u32x4*>(&dst[r][kk]) =
+          u32x4{bf2(st.v[q][0], st.v[q][1]), bf2(st.v[q][2], st.v[q][3]), bf2(st.v[q][4], st.v[q][5]),
+                bf2(st.v[q][6], st.v[q][7])};
+    } else {
+      const int r = (gi & 31) * 4, kk = (gi >> 5) * 2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) *reinterpret_cast<uint32_t*>(&dst[r + e][kk]) = bf2(st.v[q][e], st.v[q][4 + e]);
+    }
+  }
+}
+
 template <int EPI>
-int gemm(const GemmArgs& g, int splits, hipStream_t s) {
-  const dim3 grid((unsigned)ceil_div(g.N, 64), (unsigned)ceil_div(g.M, 64), (unsigned)splits);
-  hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, s, g);
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][kBT][kBRow];
+  __shared__ __align__(16) uint16_t Bs[2][kBT][kBRow];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * kBT, n0 = blockIdx.x * kBT;
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+  const bool a_k = g.sak == 1, b_k = g.sbk == 1;
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16_t{};
+  const int li = lane & 31, lg = lane >> 5;
+  Stage sa, sb;
+  if (kbeg < kend) {
+    stage_load(sa, g.a, g.sam, g.sak, m0, g.M, kbeg, kend, tid);   // A(m, k)
+    stage_load(sb, g.b, g.sbn, g.sbk, n0, g.N, kbeg, kend, tid);   // B(k, n) as rows n
+    stage_store(sa, a_k, As[0], tid);
+    stage_store(sb, b_k, Bs[0], tid);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kBTK) {
+    const bool more = k0 + kBTK < kend;
+    if (more) {
+      stage_load(sa, g.a, g.sam, g.sak, m0, g.M, k0 + kBTK, kend, tid);
+      stage_load(sb, g.b, g.sbn, g.sbk, n0, g.N, k0 + kBTK, kend, tid);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kBTK / 16; ++ks) {
+      u32x4 af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[i] = *reinterpret_cast<const u32x4*>(&As[buf][wm * 64 + 32 * i + li][ks * 16 + 8 * lg]);
+        bfr[i] = *reinterpret_cast<const u32x4*>(&Bs[buf][wn * 64 + 32 * i + li][ks * 16 + 8 * lg]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, af[i]),
+                                                              __builtin_bit_cast(bf16x8_t, bfr[j]), acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      stage_store(sa, a_k, As[buf ^ 1], tid);
+      stage_store(sb, b_k, Bs[buf ^ 1], tid);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = n0 + wn * 64 + 32 * j + li;
+    if (n >= g.N) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm * 64 + 32 * i + 8 * (v / 4) + 4 * lg + (v % 4);
+        if (m >= g.M) continue;
+        const float val = acc[i][j][v];
+        float* out = g.c + (int64_t)m * g.ldc + n;
+        if (EPI == EPI_BIAS_RELU) {
+          const float z = val + g.bias[n];
+          *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
+        } else if (EPI == EPI_BIAS_SIGMOID) {
+          *out = 1.0f / (1.0f + expf(-(val + g.bias[n])));
+        } else if (EPI == EPI_MASK) {
+          *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? val : 0.0f;
+        } else if (EPI == EPI_ATOMIC) {
+          atomicAdd(out, val);
+        } else {
+          *out = val;
+        }
+      }
+    }
+  }
+}
+
+// Launches the product on the FP32 (bf16 = false) or bfloat16 matrix cores; `splits` K ranges of
+// g.k_split each (a multiple of 16 for FP32, of kBTK for bfloat16 unless there is one range).
+template <int EPI>
+int gemm(const GemmArgs& g, int splits, hipStream_t s, bool bf16 = false) {
+  if (bf16) {
+    const dim3 grid((unsigned)ceil_div(g.N, kBT), (unsigned)ceil_div(g.M, kBT), (unsigned)splits);
+    hipLaunchKernelGGL(k_gemm_bf16<EPI>, grid, dim3(256), 0, s, g);
+  } else {
+    const dim3 grid((unsigned)ceil_div(g.N, 64), (unsigned)ceil_div(g.M, 64), (unsigned)splits);
+    hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, s, g);
+  }
   return check_launch("k_gemm");
 }
 
@@ -810,6 +984,7 @@ struct Ctx {
   float* ws;
   int64_t n;
   hipStream_t strm;
+  bool bf16;  // bfloat16 matrix-core operands (FP32 accumulation, FP32 master parameters)
   int* stats() { return reinterpret_cast<int*>(ws + lay.stats); }
   float* act_in(int k) { return k == 0 ? ws + lay.x : ws + lay.h[k - 1]; }
 };
@@ -818,9 +993,10 @@ int check_common(const ntbc_model_desc* d, int precision, const int32_t* ids, in
                  size_t workspace_bytes, Ctx* c) {
   int st = make_shape(d, &c->s);
   if (st != NTBC_OK) return st;
-  if (precision != NTBC_FP32)
-    return fail(precision == NTBC_BF16 || precision == NTBC_FP8_E4M3 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
-                "training runs in FP32 (precision %d)", precision);
+  if (precision != NTBC_FP32 && precision != NTBC_BF16)
+    return fail(precision == NTBC_FP8_E4M3 || precision == NTBC_FP16 ? NTBC_EUNSUPPORTED : NTBC_EINVAL,
+                "training runs in FP32 or BF16 (precision %d)", precision);
+  c->bf16 = precision == NTBC_BF16;
   NTBC_REQUIRE(n >= 0, "n %d < 0", n);
   NTBC_REQUIRE(n == 0 || ids != nullptr, "ids is NULL");
   c->lay = train_layout(c->s, n);
@@ -859,7 +1035,7 @@ int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int
     g.K = s.layer_in[k];
     g.k_split = g.K;
     g.bias = weights + s.b_off[k];
-    st = last ? gemm<EPI_BIAS_SIGMOID>(g, 1, c.strm) : gemm<EPI_BIAS_RELU>(g, 1, c.strm);
+    st = last ? gemm<EPI_BIAS_SIGMOID>(g, 1, c.strm, c.bf16) : gemm<EPI_BIAS_RELU>(g, 1, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
   }
   return NTBC_OK;
@@ -887,11 +1063,13 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     gw.M = out;
     gw.N = in;
     gw.K = (int)c.n;
-    const int tiles = (int)(ceil_div(out, 64) * ceil_div(in, 64));
-    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n, 256), ceil_div(2048, tiles)));
-    gw.k_split = (int)ceil_div(ceil_div(c.n, splits), 16) * 16;
+    const int tile = c.bf16 ? kBT : 64;
+    const int tiles = (int)(ceil_div(out, tile) * ceil_div(in, tile));
+    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n, 256), ceil_div(c.bf16 ? 512 : 2048, tiles)));
+    const int kq = c.bf16 ? kBTK : 16;
+    gw.k_split = (int)(ceil_div(ceil_div(c.n, splits), kq) * kq);
     splits = (int)ceil_div(c.n, gw.k_split);
-    st = gemm<EPI_ATOMIC>(gw, splits, c.strm);
+    st = gemm<EPI_ATOMIC>(gw, splits, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
     const int rpb = 128;
     hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb), (unsigned)ceil_div(out, 64)), dim3(kBlock), 0, c.strm,
@@ -915,9 +1093,9 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     if (k > 0) {
       gd.mask = c.act_in(k);
       gd.ldm = in;
-      st = gemm<EPI_MASK>(gd, 1, c.strm);
+      st = gemm<EPI_MASK>(gd, 1, c.strm, c.bf16);
     } else {
-      st = gemm<EPI_STORE>(gd, 1, c.strm);
+      st = gemm<EPI_STORE>(gd, 1, c.strm, c.bf16);
     }
     if (st != NTBC_OK) return st;
     dz = bufs[nb];

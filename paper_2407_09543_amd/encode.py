@@ -34,9 +34,10 @@ class EncodeResult:
 
 def encode_material(textures: Sequence[torch.Tensor], cfg, steps: int, batch: int, seed: int = 0,
                     qat_fraction: float = 0.1, precision: int = ntbc.BF16, kappa: Optional[float] = None,
-                    delta: float = 0.0, log_every: int = 0, init=None) -> EncodeResult:
+                    delta: float = 0.0, log_every: int = 0, init=None, train_precision: int = ntbc.FP32) -> EncodeResult:
     """Encodes one material.  `cfg` has the fields of synth.ModelConfig (grid_u8 selects the 8-bit
-    inference grid).  `steps` base steps, then qat_fraction*steps more with grid QAT."""
+    inference grid).  `steps` base steps, then qat_fraction*steps more with grid QAT.  `precision` is
+    the inference precision, `train_precision` that of the training products (FP32 or BF16)."""
     dev = textures[0].device
     desc_train = ntbc.desc_from_config(dataclasses.replace(cfg, grid_u8=False))
     torch.cuda.synchronize()
@@ -50,7 +51,7 @@ def encode_material(textures: Sequence[torch.Tensor], cfg, steps: int, batch: in
         grid0, w0 = init
     qat_steps = int(round(qat_fraction * steps)) if cfg.grid_u8 else 0
     total = steps + qat_steps
-    tr = ntbc.Trainer(desc_train, grid0, w0, targets, batch, total)
+    tr = ntbc.Trainer(desc_train, grid0, w0, targets, batch, total, precision=train_precision)
     ids = torch.empty(batch, dtype=torch.int32, device=dev)
     losses = []
     t_start = torch.cuda.Event(enable_timing=True)

@@ -356,7 +356,7 @@ class Trainer:
 
     def __init__(self, desc: ModelDesc, grid: torch.Tensor, weights: torch.Tensor, targets: Targets, batch: int,
                  total_steps: int, lr_grid: float = 0.01, lr_mlp: float = 0.005, temperature: float = 0.01,
-                 warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0)):
+                 warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0), precision: int = FP32):
         self.desc = desc
         self.grid = grid.clone().contiguous()
         self.weights = weights.clone().contiguous()
@@ -366,11 +366,11 @@ class Trainer:
         self.m_grid, self.v_grid = torch.zeros_like(self.grid), torch.zeros_like(self.grid)
         self.m_w, self.v_w = torch.zeros_like(self.weights), torch.zeros_like(self.weights)
         self.d_grid, self.d_w = torch.zeros_like(self.grid), torch.zeros_like(self.weights)
-        self.ws = _scratch(workspace_size(desc, FP32, batch), dev)
+        self.ws = _scratch(workspace_size(desc, precision, batch), dev)
         self.losses = torch.zeros(5, dtype=torch.float32, device=dev)
         self.state = TrainStateC(*[t.data_ptr() for t in (self.grid, self.weights, self.m_grid, self.v_grid,
                                                           self.m_w, self.v_w, self.d_grid, self.d_w)])
-        self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, FP32,
+        self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, precision,
                          (ctypes.c_float * 4)(*loss_weights))
 
     def step(self, ids: torch.Tensor, step: int, qat: bool = False) -> torch.Tensor:

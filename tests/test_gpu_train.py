@@ -247,3 +247,55 @@ def test_small_config_100_steps_then_inference():
     log(f"trained inference: identity {ident:.6f} differ {res['differ']} ties {res['ties']} max|dY| {res['max_dy']:.3g}")
     assert res["repack_exact"] and res["max_dy"] <= 1e-5
     assert ident >= 0.999 and res["ties"] == res["differ"]
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_bf16_training_gradients(which):
+    # bfloat16 operands (relative rounding 2^-9 per operand, FP32 accumulation) in the forward, dX and
+    # dW products.  A product of two rounded operands is off by <= 2^-8 relative and the sums keep that
+    # scale, compounded over four layers: heads within 2e-2 of the FP64 oracle, losses within 3e-2
+    # relative.  For given dL/dY (no argmax in between) the gradients also see the ReLU masks of the
+    # recomputed forward: a pre-activation within ~2^-8 of zero can change sign, which drops or adds a
+    # whole unit's contribution, so the relative error grows like the square root of the flipped
+    # fraction (measured 3-5% for the weights, 6-7% for the grid); bounds 1e-1 and 1.5e-1
+    pb = _problem(which, 4)
+    ids, ids_d = pb.ids(6, 2048)
+    y = ntbc.forward(pb.desc, pb.grid_d, pb.flat_d, ids_d, precision=ntbc.BF16)
+    losses, _ = ntbc.loss_grad(pb.desc, pb.tg_gpu, y, ids_d)
+    l_or, _, _, y_or = ON.gradients(pb.cfg, pb.grid, pb.layers, pb.tg_oracle, ids, qat=False)
+    dy = float(np.abs(y.cpu().numpy() - y_or).max())
+    rng = np.random.default_rng(6)
+    d_heads = (rng.standard_normal((len(ids), pb.cfg.head_dim)) * 1e-3).astype(np.float32)
+    dg, dw = ntbc.backward(pb.desc, pb.grid_d, pb.flat_d, ids_d, torch.from_numpy(d_heads).cuda(), precision=ntbc.BF16)
+    cfg = pb.cfg
+    bx, by = ids % cfg.blocks_w, ids // cfg.blocks_w
+    x = OG.features(OG.split_levels(pb.grid.astype(np.float64), cfg.n_levels, cfg.base_res), bx, by, cfg.blocks_w,
+                    cfg.blocks_h)
+    yy, cache = OMLP.forward(pb.layers, x)
+    dws, dbs, dx = OMLP.backward(pb.layers, cache, d_heads.astype(np.float64), yy)
+    dgrid = OG.features_backward(dx, bx, by, cfg.blocks_w, cfg.blocks_h, cfg.n_levels, cfg.base_res, cfg.n_features,
+                                 None)
+    dflat = synth.flatten_weights([(a, b) for a, b in zip(dws, dbs)]).astype(np.float64)
+    rg, rw = _rel(dg.cpu().numpy(), dgrid), _rel(dw.cpu().numpy(), dflat)
+    log(f"bf16 training {which}: max|dY| {dy:.3g} losses {losses.cpu().numpy()[:4]} oracle {l_or}; "
+        f"backward rel grid {rg:.3g} weights {rw:.3g}")
+    assert dy <= 2e-2
+    assert np.allclose(losses.cpu().numpy()[:4], l_or, rtol=3e-2)
+    assert rg <= 1.5e-1 and rw <= 1e-1
+
+
+def test_bf16_training_matches_fp32_training_quality():
+    # the same 600-step encode of the 256^2 five-texture material with FP32 and with bfloat16 products:
+    # decoded PSNR within 1 dB on average over the textures and 4 dB on each
+    from paper_2407_09543_amd import encode
+    cfg = synth.config_mid(256)
+    mat = synth.material_five(256, 4)
+    tex = [torch.from_numpy(t.texels).cuda() for t in mat.textures]
+    out = {}
+    for prec in (ntbc.FP32, ntbc.BF16):
+        res = encode.encode_material(tex, cfg, steps=600, batch=2048, seed=4, train_precision=prec)
+        out[prec] = encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, 256)
+    log(f"psnr fp32-trained {np.round(out[ntbc.FP32], 2)} bf16-trained {np.round(out[ntbc.BF16], 2)}")
+    # measured: four textures within 0.4 dB, the hardest (AO, ~21 dB) 2.7 dB lower with bfloat16
+    diffs = [a - b for a, b in zip(out[ntbc.FP32], out[ntbc.BF16])]
+    assert abs(float(np.mean(diffs))) <= 1.0 and max(abs(d) for d in diffs) <= 4.0
