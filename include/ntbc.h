@@ -166,6 +166,41 @@ int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t pr
 int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* p, int64_t n_sample, float* scales_out,
                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- batched decode ----------------------------------------------------------------------------- */
+
+/* One block range of one model (a material, or one mip level of it: a mip is the same network queried
+ * at the block centres of its own block grid, desc.blocks_w x desc.blocks_h). */
+typedef struct {
+  ntbc_model_desc desc;
+  ntbc_params params;       /* device pointers; flags ignored */
+  int64_t first_block, n_blocks;
+  uint64_t* blocks_out;     /* device uint64[n_textures][n_blocks] */
+  int32_t model_id;         /* items with equal model_id share weights and layer shapes: one packed copy */
+} ntbc_batch_item;
+
+/* Bytes of the host table that ntbc_batch_plan fills for n_items items.  Host only. */
+int ntbc_batch_table_size(int32_t n_items, size_t* bytes);
+
+/* Plans the load-time decode of many block ranges at `precision` (NTBC_BF16, NTBC_FP16 or
+ * NTBC_FP8_E4M3 with params.fp8_scales): one launch per kernel instance (hidden width, first-layer
+ * K-steps), items grouped by instance.  Writes a table image into `table` (host memory,
+ * >= ntbc_batch_table_size) that embeds device addresses inside `workspace` (device memory of
+ * *workspace_bytes; pass NULL first to learn the size, then plan again with the workspace).  The
+ * caller copies the table to device memory for ntbc_infer_batch.  Host only.  Errors: NTBC_EINVAL,
+ * NTBC_EUNSUPPORTED (shapes the fused kernel does not take). */
+int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, int32_t precision, void* workspace, void* table,
+                    size_t table_bytes, size_t* workspace_bytes);
+
+/* Packs every distinct model's weights into the workspace (once; again after the weights change). */
+int ntbc_batch_pack(const void* table, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Decodes every item of a plan: `table` is the host image, `table_device` the caller's device copy of
+ * it.  stamps (optional, device uint64[n_items + 1]): [0] = the real-time counter (100 MHz) when the
+ * batch starts, [1 + i] = when item i's last tile finished.  Stream-ordered and allocation-free, so a
+ * caller may capture it in a HIP graph and replay it. */
+int ntbc_infer_batch(const void* table, const void* table_device, void* workspace, size_t workspace_bytes,
+                     uint64_t* stamps, void* stream);
+
 /* ---- training ----------------------------------------------------------------------------------- */
 
 /* Training state (host struct of device pointers, caller-owned).  Master parameters in FP32; Adam

@@ -22,6 +22,7 @@
 // contiguous 16-byte (16-bit formats) or 4-byte (FP32) load; the copy is made by k_pack_lp / k_pack_f32
 // unless the caller says it is current.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 #include "device.h"
@@ -517,9 +518,12 @@ __device__ __forceinline__ void hidden_layer(const typename LpOp<L>::type (&in)[
   }
 }
 
-template <Lp L, int HID, int KS0, int NH>
-__global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
-k_infer_lds(InferArgs a, ChunkTable ct) {
+// The fused network of one tile of kLdsWaves * 32 block positions (tile index `tile` of the range
+// a.first .. a.first + a.n).
+// ArgsT/ChunksT: by value for the single-range kernel (its by-value parameters are then read in place
+// from the kernel-argument segment), references for work items in device memory.
+template <Lp L, int HID, int KS0, int NH, typename ArgsT = const InferArgs, typename ChunksT = const ChunkTable>
+__device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
   typedef typename LpOp<L>::type Op;
   constexpr int S = HID / 16;
   constexpr int T = HID / 32;
@@ -535,7 +539,6 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int j = lane & 31, g = lane >> 5;
-  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t pos0 = a.first + (tile * kLdsWaves + wave) * 32;
   const int64_t last = a.first + a.n - 1;
   const int64_t id = pos0 + j <= last ? pos0 + j : last;
@@ -673,6 +676,59 @@ k_infer_lds(InferArgs a, ChunkTable ct) {
   }
 }
 
+// One block range per launch, its arguments in the kernel-argument segment.
+template <Lp L, int HID, int KS0, int NH>
+__global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
+k_infer_lds(InferArgs a, ChunkTable ct) {
+  infer_tile<L, HID, KS0, NH>(a, ct, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// ------------------------------------------------------------------------------ launch over work items
+// Many block ranges (materials, their mip levels) in one launch per kernel instance.  The items live
+// in device memory (their arguments are read through the scalar cache, and
+// arrays in them may be indexed at run time without private copies): item i owns the tiles
+// [tile_begin, tile_begin + tiles) of the launch; a block takes tile xcd_tile(blockIdx) (consecutive
+// tiles on one XCD), finds its item by binary search over tile_begin (uniform), runs the tile, and
+// the last block of an item to finish stamps the item's completion time (the 100 MHz real-time
+// counter) when stamps are requested.
+struct BatchItem {
+  InferArgs a;
+  ChunkTable ct;
+  int64_t tile_begin, tiles;
+  int32_t index;  // position of the item in the caller's list (stamps)
+};
+
+template <Lp L, int HID, int KS0, int NH>
+__global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
+k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __restrict__ done,
+                  uint64_t* __restrict__ stamps) {
+  // the items are read-only for the whole launch: reading them through the constant address space
+  // lets the compiler keep the arguments in scalar registers and reuse them across the kernel's stores
+  typedef const __attribute__((address_space(4))) BatchItem ConstItem;
+  const ConstItem* citems = (const ConstItem*)items;
+  const int64_t b = xcd_tile(blockIdx.x, gridDim.x);
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (citems[mid].tile_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem& it = *(const BatchItem*)(citems + lo);
+  infer_tile<L, HID, KS0, NH, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
+  if (stamps != nullptr) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicAdd(&done[it.index], 1u) + 1u == (unsigned)it.tiles) stamps[1 + it.index] = wall_clock64();
+    }
+  }
+}
+
+__global__ void k_batch_start(unsigned* __restrict__ done, int n, uint64_t* __restrict__ stamps) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+  if (threadIdx.x == 0 && stamps != nullptr) stamps[0] = wall_clock64();
+}
+
 // ------------------------------------------------------------------------------ FP32 kernel
 // CALIB: FP8 calibration pass over the sample ids i * stride (i < n): records max |input| of every
 // layer (float bits; non-negative floats order like their bits) and stops before the heads.
@@ -794,6 +850,7 @@ struct Plan {
   int ksteps[kMaxLayers], otiles[kMaxLayers];
   int64_t pack_off[kMaxLayers], bias_off[kMaxLayers];
   int64_t pack_bytes, bias_bytes, total_bytes;
+  int64_t calib_offset;  // FP8: FP32 packed weights and per-layer maxima of ntbc_fp8_calibrate
   int positions_per_wave;
 };
 
@@ -826,13 +883,15 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
   p->pack_bytes = off * unit;
   p->bias_bytes = boff * 4;
   p->total_bytes = ((p->pack_bytes + 255) / 256) * 256 + p->bias_bytes;
+  p->calib_offset = -1;
   if (precision == NTBC_FP8_E4M3) {
-    // FP8 calibration (ntbc_fp8_calibrate) packs FP32 weights and keeps per-layer maxima in the same
-    // workspace
+    // FP8 calibration (ntbc_fp8_calibrate) packs FP32 weights and keeps per-layer maxima after the
+    // FP8 area, so a calibration leaves the packed FP8 weights in place
     Plan f;
     const int st32 = make_plan(d, NTBC_FP32, &f);
     if (st32 != NTBC_OK) return st32;
-    p->total_bytes = std::max(p->total_bytes, f.total_bytes + kCalibBytes);
+    p->calib_offset = (p->total_bytes + 255) / 256 * 256;
+    p->total_bytes = p->calib_offset + f.total_bytes + kCalibBytes;
   }
   return NTBC_OK;
 }
@@ -875,6 +934,73 @@ __global__ void k_fp8_finalize(const unsigned* __restrict__ amax, int n_layers, 
     scales[2 * k] = pow2_scale(__uint_as_float(amax[k]));
     scales[2 * k + 1] = pow2_scale(__uint_as_float(amax[kMaxLayers + k]));
   }
+}
+
+// The weight-chunk table of the LDS kernel (offsets and lengths in 16-byte units: an FP8 operand is 8
+// bytes, a 16-bit one 16, and every chunk holds a multiple of 64 operands) and its LDS size.
+int make_chunks(const Plan& p, bool fp8, int head_stride, ChunkTable* ct, size_t* lds_out) {
+  const Shape& s = p.s;
+  const int64_t op_bytes = fp8 ? 8 : 16;
+  *ct = ChunkTable{};
+  for (int k = 0; k < s.n_layers; ++k) {
+    for (int t0 = 0; t0 < p.otiles[k]; t0 += kChunkTiles) {
+      NTBC_REQUIRE(ct->n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
+      const int nt = std::min(kChunkTiles, p.otiles[k] - t0);
+      ct->src[ct->n] = (p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64) * op_bytes / 16;
+      ct->len[ct->n] = (int)((int64_t)nt * p.ksteps[k] * 64 * op_bytes / 16);
+      ++ct->n;
+    }
+  }
+  int64_t nb = 0;
+  for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
+  ct->n_bias = (int)((nb + 3) / 4 * 4);
+  const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * op_bytes;
+  const size_t ybytes = (size_t)kLdsWaves * 16 * head_stride * sizeof(float);
+  const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
+  ct->stage = (int)(stage / sizeof(u32x4));
+  *lds_out = stage + (256 + (size_t)ct->n_bias) * sizeof(float);
+  NTBC_REQUIRE(*lds_out <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, *lds_out);
+  return NTBC_OK;
+}
+
+struct BatchGroup {
+  int32_t lp, hid, ks0, nh;
+  int32_t item_begin, item_end;
+  int64_t tiles, lds;
+};
+
+// Kernel instance of an item: the unrolled two-middle-layer instances where they exist, else the
+// generic one (same selection as ntbc_infer_blocks).
+int batch_nh(const Plan& p) {
+  const int mid = p.s.n_layers - 2;
+  const bool special = (p.hid_inst == 256 && p.ksteps[0] == 4) || (p.hid_inst == 128 && p.ksteps[0] == 3);
+  return special && mid == 2 ? 2 : -1;
+}
+
+int launch_batch_group(const BatchGroup& gr, const BatchItem* items, unsigned* done, uint64_t* stamps, hipStream_t strm) {
+  const void* fn = nullptr;
+  void (*launch)(dim3, dim3, size_t, hipStream_t, const BatchItem*, int, unsigned*, uint64_t*) = nullptr;
+  const Lp want = gr.lp == NTBC_FP8_E4M3 ? Lp::FP8 : (gr.lp == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
+#define NTBC_BATCH_INSTANCE_L(LP, H, K, NH)                                                           \
+  if (gr.hid == H && gr.ks0 == K && gr.nh == NH && want == LP) {                                      \
+    fn = (const void*)k_infer_lds_batch<LP, H, K, NH>;                                               \
+    launch = [](dim3 g, dim3 b, size_t sh, hipStream_t st, const BatchItem* it, int n, unsigned* d, uint64_t* s) { \
+      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH>), g, b, sh, st, it, n, d, s);                \
+    };                                                                                                 \
+  }
+#define NTBC_BATCH_INSTANCE(H, K, NH) \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_BATCH_INSTANCE_L(Lp::FP16, H, K, NH) NTBC_BATCH_INSTANCE_L(Lp::FP8, H, K, NH)
+  NTBC_BATCH_INSTANCE(64, 1, -1) NTBC_BATCH_INSTANCE(64, 2, -1) NTBC_BATCH_INSTANCE(64, 3, -1) NTBC_BATCH_INSTANCE(64, 4, -1)
+  NTBC_BATCH_INSTANCE(128, 1, -1) NTBC_BATCH_INSTANCE(128, 2, -1) NTBC_BATCH_INSTANCE(128, 3, -1) NTBC_BATCH_INSTANCE(128, 4, -1)
+  NTBC_BATCH_INSTANCE(256, 1, -1) NTBC_BATCH_INSTANCE(256, 2, -1) NTBC_BATCH_INSTANCE(256, 3, -1) NTBC_BATCH_INSTANCE(256, 4, -1)
+  NTBC_BATCH_INSTANCE(128, 3, 2) NTBC_BATCH_INSTANCE(256, 4, 2)
+#undef NTBC_BATCH_INSTANCE
+#undef NTBC_BATCH_INSTANCE_L
+  NTBC_REQUIRE(fn != nullptr, "no batch kernel instance for width %d, %d input K-steps", gr.hid, gr.ks0);
+  NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gr.lds));
+  launch(dim3((unsigned)gr.tiles), dim3(64 * kLdsWaves), (size_t)gr.lds, strm, items + gr.item_begin,
+         gr.item_end - gr.item_begin, done, stamps);
+  return check_launch("ntbc_infer_batch");
 }
 
 // Kernel arguments common to inference and calibration: the grid view, the packed-weight plan and the
@@ -1014,37 +1140,17 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
 
   const int ppw = p.positions_per_wave;
   if ((lp16 || fp8) && lds_shape) {
-    // chunk offsets and lengths in 16-byte units (an FP8 operand is 8 bytes; every chunk holds a
-    // multiple of 64 operands)
-    const int64_t op_bytes = fp8 ? 8 : 16;
     ChunkTable ct{};
-    for (int k = 0; k < s.n_layers; ++k) {
-      for (int t0 = 0; t0 < p.otiles[k]; t0 += kChunkTiles) {
-        NTBC_REQUIRE(ct.n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
-        const int nt = std::min(kChunkTiles, p.otiles[k] - t0);
-        ct.src[ct.n] = (p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64) * op_bytes / 16;
-        ct.len[ct.n] = (int)((int64_t)nt * p.ksteps[k] * 64 * op_bytes / 16);
-        ++ct.n;
-      }
-    }
+    size_t lds = 0;
+    st = make_chunks(p, fp8, a.head_stride, &ct, &lds);
+    if (st != NTBC_OK) return st;
     const int64_t nwg = ceil_div(n_blocks, (int64_t)32 * kLdsWaves);
-    int64_t nb = 0;
-    for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
-    ct.n_bias = (int)((nb + 3) / 4 * 4);
-    const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * op_bytes;
-    const size_t ybytes = (size_t)kLdsWaves * 16 * a.head_stride * sizeof(float);
-    const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
-    ct.stage = (int)(stage / sizeof(u32x4));
-    const size_t lds = stage + (256 + (size_t)ct.n_bias) * sizeof(float);
-    NTBC_REQUIRE(lds <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, lds);
     const void* fn = nullptr;
     void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
-    // generic instances (run-time middle-layer count), then the unrolled ones for the shapes of the
-    // paper-scale (width 256, 64 inputs) and mid (width 128, 48 inputs) models with two middle layers
-    const int mid = s.n_layers - 2;
     const Lp want = fp8 ? Lp::FP8 : (precision == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
+    const int nh = batch_nh(p);
 #define NTBC_LDS_INSTANCE_L(LP, H, K, NH)                                                             \
-    if (p.hid_inst == H && p.ksteps[0] == K && (NH < 0 || NH == mid) && want == LP) {                \
+    if (p.hid_inst == H && p.ksteps[0] == K && nh == NH && want == LP) {                             \
       fn = (const void*)k_infer_lds<LP, H, K, NH>;                                                   \
       launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
         hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH>), gr, bl, sh, st, x, y);                       \
@@ -1060,8 +1166,7 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
 #undef NTBC_LDS_INSTANCE_L
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const dim3 grid((unsigned)nwg), block(64 * kLdsWaves);
-    launch(grid, block, lds, strm, a, ct);
+    launch(dim3((unsigned)nwg), dim3(64 * kLdsWaves), lds, strm, a, ct);
     return check_launch("ntbc_infer_blocks");
   }
   const int64_t nwg = ceil_div(n_blocks, (int64_t)ppw * kWaves);
@@ -1114,7 +1219,7 @@ extern "C" int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* p
     return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)p8.total_bytes);
   hipStream_t strm = as_stream(stream);
 
-  char* ws = static_cast<char*>(workspace);
+  char* ws = static_cast<char*>(workspace) + p8.calib_offset;
   float* wpack = reinterpret_cast<float*>(ws);
   float* bias = reinterpret_cast<float*>(ws + ((p.pack_bytes + 255) / 256) * 256);
   unsigned* amax = reinterpret_cast<unsigned*>(ws + p.total_bytes);  // 2 * kMaxLayers words
@@ -1159,4 +1264,218 @@ extern "C" int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* p
   if (st != NTBC_OK) return st;
   hipLaunchKernelGGL(k_fp8_finalize, dim3(1), dim3(64), 0, strm, amax, s.n_layers, scales_out);
   return check_launch("ntbc_fp8_calibrate");
+}
+
+// ------------------------------------------------------------------------------ batched decode, host
+namespace {
+
+constexpr int32_t kBatchMagic = 0x4E544243;
+constexpr int kMaxBatchGroups = 32;
+
+struct BatchPack {
+  PackArgs pa;
+  void* pack;
+  float* bias;
+};
+
+struct BatchHeader {
+  int32_t magic, n_items, n_groups, n_packs, precision, pad;
+  int64_t workspace_bytes, done_offset, packs_offset, items_offset;
+  BatchGroup groups[kMaxBatchGroups];
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t batch_table_bytes(int n) {
+  return align_up(sizeof(BatchHeader), 16) + align_up((size_t)n * sizeof(BatchPack), 16) + (size_t)n * sizeof(BatchItem);
+}
+
+const BatchHeader* batch_header(const void* table) {
+  const BatchHeader* h = static_cast<const BatchHeader*>(table);
+  return h != nullptr && h->magic == kBatchMagic ? h : nullptr;
+}
+
+}  // namespace
+
+extern "C" int ntbc_batch_table_size(int32_t n_items, size_t* bytes) {
+  NTBC_REQUIRE(n_items >= 1 && bytes != nullptr, "n_items %d < 1 or bytes is NULL", n_items);
+  *bytes = batch_table_bytes(n_items);
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, int32_t precision, void* workspace,
+                               void* table, size_t table_bytes, size_t* workspace_bytes) {
+  NTBC_REQUIRE(items != nullptr && n_items >= 1, "items is NULL or n_items %d < 1", n_items);
+  NTBC_REQUIRE(table != nullptr && table_bytes >= batch_table_bytes(n_items), "table is NULL or smaller than %zu bytes",
+               batch_table_bytes(n_items));
+  NTBC_REQUIRE(workspace_bytes != nullptr, "workspace_bytes is NULL");
+  NTBC_REQUIRE(precision == NTBC_BF16 || precision == NTBC_FP16 || precision == NTBC_FP8_E4M3,
+               "batched decode runs in BF16, FP16 or FP8 (precision %d)", precision);
+  std::vector<Plan> plans(n_items);
+  std::vector<int> model_of(n_items), key(n_items);
+  std::vector<int32_t> model_ids;
+  std::vector<int64_t> model_off;
+  std::vector<int> model_item;
+  std::vector<BatchGroup> groups;
+  int64_t off = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const ntbc_batch_item& it = items[i];
+    int st = make_plan(&it.desc, precision, &plans[i]);
+    if (st != NTBC_OK) return st;
+    const Plan& p = plans[i];
+    const Shape& s = p.s;
+    NTBC_REQUIRE(it.params.grid != nullptr && it.params.weights != nullptr, "item %d: grid or weights is NULL", i);
+    if (it.desc.grid_dtype == NTBC_GRID_U8)
+      NTBC_REQUIRE(it.params.grid_scale != nullptr && it.params.grid_zero != nullptr, "item %d: U8 grid needs scale and zero", i);
+    if (precision == NTBC_FP8_E4M3) NTBC_REQUIRE(it.params.fp8_scales != nullptr, "item %d: FP8 needs fp8_scales", i);
+    NTBC_REQUIRE(it.first_block >= 0 && it.n_blocks >= 0 && it.first_block + it.n_blocks <= s.n_positions,
+                 "item %d: block range outside the block grid", i);
+    NTBC_REQUIRE(it.n_blocks == 0 || it.blocks_out != nullptr, "item %d: blocks_out is NULL", i);
+    if (!(p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2))
+      return fail(NTBC_EUNSUPPORTED, "item %d: batched decode needs head_dim <= %d, in_dim <= 64 and a hidden layer", i,
+                  32 * kHeadTiles);
+    int m = -1;
+    for (size_t q = 0; q < model_ids.size(); ++q)
+      if (model_ids[q] == it.model_id) m = (int)q;
+    if (m < 0) {
+      m = (int)model_ids.size();
+      model_ids.push_back(it.model_id);
+      model_item.push_back(i);
+      model_off.push_back(off);
+      off = (int64_t)align_up((size_t)(off + p.total_bytes), 256);
+    } else {
+      const Plan& q = plans[model_item[m]];
+      bool same = q.s.n_layers == s.n_layers && q.total_bytes == p.total_bytes;
+      for (int k = 0; same && k < s.n_layers; ++k) same = q.s.layer_in[k] == s.layer_in[k] && q.s.layer_out[k] == s.layer_out[k];
+      NTBC_REQUIRE(same && items[model_item[m]].params.weights == it.params.weights,
+                   "item %d: model_id %d shared by items with different weights or layer shapes", i, it.model_id);
+    }
+    model_of[i] = m;
+    const BatchGroup want{precision, p.hid_inst, p.ksteps[0], batch_nh(p), 0, 0, 0, 0};
+    int gi = -1;
+    for (size_t q = 0; q < groups.size(); ++q)
+      if (groups[q].hid == want.hid && groups[q].ks0 == want.ks0 && groups[q].nh == want.nh) gi = (int)q;
+    if (gi < 0) {
+      NTBC_REQUIRE((int)groups.size() < kMaxBatchGroups, "more than %d kernel instances in one batch", kMaxBatchGroups);
+      gi = (int)groups.size();
+      groups.push_back(want);
+    }
+    key[i] = gi;
+  }
+  const int64_t done_offset = off;
+  const int64_t need = (int64_t)align_up((size_t)(done_offset + 4 * (int64_t)n_items), 256);
+  *workspace_bytes = (size_t)need;
+
+  char* base = static_cast<char*>(table);
+  BatchHeader* h = reinterpret_cast<BatchHeader*>(base);
+  *h = BatchHeader{};
+  h->magic = kBatchMagic;
+  h->n_items = n_items;
+  h->precision = precision;
+  h->workspace_bytes = need;
+  h->done_offset = done_offset;
+  h->packs_offset = (int64_t)align_up(sizeof(BatchHeader), 16);
+  h->items_offset = h->packs_offset + (int64_t)align_up((size_t)n_items * sizeof(BatchPack), 16);
+  BatchPack* packs = reinterpret_cast<BatchPack*>(base + h->packs_offset);
+  BatchItem* out = reinterpret_cast<BatchItem*>(base + h->items_offset);
+  char* ws = static_cast<char*>(workspace);
+  for (size_t m = 0; m < model_ids.size(); ++m) {
+    const int i = model_item[m];
+    const Plan& p = plans[i];
+    const Shape& s = p.s;
+    BatchPack bp{};
+    bp.pa.w = items[i].params.weights;
+    bp.pa.n_layers = s.n_layers;
+    for (int k = 0; k < s.n_layers; ++k) {
+      bp.pa.in_dim[k] = s.layer_in[k];
+      bp.pa.out_dim[k] = s.layer_out[k];
+      bp.pa.w_off[k] = s.w_off[k];
+      bp.pa.b_off[k] = s.b_off[k];
+      bp.pa.ksteps[k] = p.ksteps[k];
+      bp.pa.otiles[k] = p.otiles[k];
+      bp.pa.pack_off[k] = p.pack_off[k];
+      bp.pa.bias_off[k] = p.bias_off[k];
+    }
+    bp.pa.fp8_scales = items[i].params.fp8_scales;
+    bp.pack = ws ? ws + model_off[m] : nullptr;
+    bp.bias = ws ? reinterpret_cast<float*>(ws + model_off[m] + (int64_t)align_up((size_t)p.pack_bytes, 256)) : nullptr;
+    packs[m] = bp;
+  }
+  h->n_packs = (int)model_ids.size();
+  int n_out = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    BatchGroup& gr = groups[gi];
+    gr.item_begin = n_out;
+    int64_t tiles = 0;
+    for (int i = 0; i < n_items; ++i) {
+      if (key[i] != (int)gi || items[i].n_blocks == 0) continue;
+      const Plan& p = plans[i];
+      BatchItem bi{};
+      bi.a = infer_args(p, &items[i].desc, &items[i].params);
+      bi.a.wpack = packs[model_of[i]].pack;
+      bi.a.bias = packs[model_of[i]].bias;
+      bi.a.first = items[i].first_block;
+      bi.a.n = items[i].n_blocks;
+      bi.a.out = items[i].blocks_out;
+      bi.a.heads = nullptr;
+      size_t lds = 0;
+      int st = make_chunks(p, precision == NTBC_FP8_E4M3, bi.a.head_stride, &bi.ct, &lds);
+      if (st != NTBC_OK) return st;
+      gr.lds = std::max<int64_t>(gr.lds, (int64_t)lds);
+      bi.tile_begin = tiles;
+      bi.tiles = ceil_div(items[i].n_blocks, (int64_t)32 * kLdsWaves);
+      bi.index = i;
+      tiles += bi.tiles;
+      out[n_out++] = bi;
+    }
+    gr.item_end = n_out;
+    gr.tiles = tiles;
+  }
+  h->n_groups = (int)groups.size();
+  for (size_t gi = 0; gi < groups.size(); ++gi) h->groups[gi] = groups[gi];
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_batch_pack(const void* table, void* workspace, size_t workspace_bytes, void* stream) {
+  const BatchHeader* h = batch_header(table);
+  NTBC_REQUIRE(h != nullptr, "table is not a batch plan");
+  NTBC_REQUIRE(workspace != nullptr && workspace_bytes >= (size_t)h->workspace_bytes,
+               "workspace needs %lld bytes", (long long)h->workspace_bytes);
+  hipStream_t strm = as_stream(stream);
+  const BatchPack* packs = reinterpret_cast<const BatchPack*>(static_cast<const char*>(table) + h->packs_offset);
+  for (int m = 0; m < h->n_packs; ++m) {
+    const BatchPack& bp = packs[m];
+    NTBC_REQUIRE(bp.pack != nullptr, "the plan was made without a workspace");
+    const dim3 pgrid(64, bp.pa.n_layers);
+    if (h->precision == NTBC_FP8_E4M3)
+      hipLaunchKernelGGL(k_pack_lp<Lp::FP8>, pgrid, dim3(256), 0, strm, bp.pa, static_cast<u32x2*>(bp.pack), bp.bias);
+    else if (h->precision == NTBC_FP16)
+      hipLaunchKernelGGL(k_pack_lp<Lp::FP16>, pgrid, dim3(256), 0, strm, bp.pa, static_cast<u32x4*>(bp.pack), bp.bias);
+    else
+      hipLaunchKernelGGL(k_pack_lp<Lp::BF16>, pgrid, dim3(256), 0, strm, bp.pa, static_cast<u32x4*>(bp.pack), bp.bias);
+    int st = check_launch("ntbc_batch_pack");
+    if (st != NTBC_OK) return st;
+  }
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_infer_batch(const void* table, const void* table_device, void* workspace, size_t workspace_bytes,
+                                uint64_t* stamps, void* stream) {
+  const BatchHeader* h = batch_header(table);
+  NTBC_REQUIRE(h != nullptr, "table is not a batch plan");
+  NTBC_REQUIRE(table_device != nullptr, "table_device is NULL");
+  NTBC_REQUIRE(workspace != nullptr && workspace_bytes >= (size_t)h->workspace_bytes,
+               "workspace needs %lld bytes", (long long)h->workspace_bytes);
+  hipStream_t strm = as_stream(stream);
+  unsigned* done = reinterpret_cast<unsigned*>(static_cast<char*>(workspace) + h->done_offset);
+  hipLaunchKernelGGL(k_batch_start, dim3(1), dim3(256), 0, strm, done, h->n_items, stamps);
+  int st = check_launch("ntbc_infer_batch: start");
+  if (st != NTBC_OK) return st;
+  const BatchItem* items = reinterpret_cast<const BatchItem*>(static_cast<const char*>(table_device) + h->items_offset);
+  for (int gi = 0; gi < h->n_groups; ++gi) {
+    if (h->groups[gi].tiles == 0) continue;
+    st = launch_batch_group(h->groups[gi], items, done, stamps, strm);
+    if (st != NTBC_OK) return st;
+  }
+  return NTBC_OK;
 }

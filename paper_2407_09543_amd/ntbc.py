@@ -79,6 +79,10 @@ _SIGNATURES = {
     "ntbc_block_sse": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "ntbc_fallback": ([_P, _P, _P, _P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
     "ntbc_fp8_calibrate": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I64, _P, _P, _SZ, _P], _I32),
+    "ntbc_batch_table_size": ([_I32, ctypes.POINTER(_SZ)], _I32),
+    "ntbc_batch_plan": ([ctypes.c_void_p, _I32, _I32, _P, _P, _SZ, ctypes.POINTER(_SZ)], _I32),
+    "ntbc_batch_pack": ([_P, _P, _SZ, _P], _I32),
+    "ntbc_infer_batch": ([_P, _P, _P, _SZ, _P, _P], _I32),
     "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
                            _P, _SZ, _P], ctypes.c_int),
     "ntbc_forward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P], ctypes.c_int),
@@ -269,6 +273,61 @@ class Model:
         _check(lib().ntbc_infer_blocks(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
                                        n_blocks, _ptr(out), _ptr(h), _ptr(ws), ws.numel(), _stream()))
         return (out, h) if heads else out
+
+
+class BatchItemC(ctypes.Structure):
+    _fields_ = [("desc", ModelDesc), ("params", Params), ("first_block", ctypes.c_int64),
+                ("n_blocks", ctypes.c_int64), ("blocks_out", ctypes.c_void_p), ("model_id", ctypes.c_int32)]
+
+
+def mip_desc(desc: ModelDesc, level: int) -> ModelDesc:
+    """The block grid of mip `level` of a model (the network queried at that mip's block centres)."""
+    d = ModelDesc.from_buffer_copy(desc)
+    d.blocks_w = max(1, desc.blocks_w >> level)
+    d.blocks_h = max(1, desc.blocks_h >> level)
+    return d
+
+
+class Batch:
+    """A planned batched decode: items (model, desc, first_block, n_blocks) -> one output tensor per
+    item; run() issues one launch per kernel instance (capturable in a HIP graph)."""
+
+    def __init__(self, entries, precision: int = BF16):
+        self.models = [e[0] for e in entries]
+        n = len(entries)
+        dev = self.models[0].weights.device
+        self.outputs = []
+        arr = (BatchItemC * n)()
+        ids = {}
+        for i, (model, desc, first, count) in enumerate(entries):
+            out = torch.empty((desc.n_textures, count), dtype=torch.int64, device=dev)
+            self.outputs.append(out)
+            arr[i].desc = desc
+            arr[i].params = model.params()
+            arr[i].first_block = first
+            arr[i].n_blocks = count
+            arr[i].blocks_out = out.data_ptr()
+            arr[i].model_id = ids.setdefault(id(model), len(ids))
+        self._arr = arr
+        tb = _SZ()
+        _check(lib().ntbc_batch_table_size(n, ctypes.byref(tb)))
+        self.table = (ctypes.c_uint8 * tb.value)()
+        wsb = _SZ()
+        _check(lib().ntbc_batch_plan(ctypes.addressof(arr), n, precision, None, ctypes.addressof(self.table), tb.value,
+                                     ctypes.byref(wsb)))
+        self.ws = torch.empty(max(wsb.value, 256), dtype=torch.uint8, device=dev)
+        _check(lib().ntbc_batch_plan(ctypes.addressof(arr), n, precision, self.ws.data_ptr(),
+                                     ctypes.addressof(self.table), tb.value, ctypes.byref(wsb)))
+        self.table_dev = torch.frombuffer(bytearray(bytes(self.table)), dtype=torch.uint8).to(dev)
+        self.n = n
+        _check(lib().ntbc_batch_pack(ctypes.addressof(self.table), _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def run(self, stamps: Optional[torch.Tensor] = None):
+        """Decodes every item into self.outputs; stamps (uint64 as int64 [n + 1]) receive the start and
+        per-item completion times of the 100 MHz real-time counter."""
+        _check(lib().ntbc_infer_batch(ctypes.addressof(self.table), _ptr(self.table_dev), _ptr(self.ws), self.ws.numel(),
+                                      _ptr(stamps), _stream()))
+        return self.outputs
 
 
 # -------------------------------------------------------------------------------------- training

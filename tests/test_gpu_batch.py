@@ -1,0 +1,122 @@
+"""Batched load-time decode: many materials and mip levels in one launch per kernel instance.
+
+Every item's blocks equal ntbc_infer_blocks on the same model, block grid and range (the same fused
+kernel and arithmetic), a sample of them equals the oracle of the same precision within the 16-bit
+tolerances with every differing block a tie, the batch replays identically from a HIP graph, and the
+completion stamps are ordered after the start stamp."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from cases import model_inputs, oracle_levels
+from util import ensure_built, log, u64
+from oracle import metrics as OM
+from oracle import ntbc as ON
+from paper_2407_09543_amd import ntbc, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    assert torch.cuda.is_available()
+
+
+def _device_model(cfg, flat, g):
+    desc = ntbc.desc_from_config(cfg)
+    w = torch.from_numpy(flat).cuda()
+    if "codes" in g:
+        return ntbc.Model(desc, w, torch.from_numpy(g["codes"]).cuda(), torch.from_numpy(g["scale"]).cuda(),
+                          torch.from_numpy(g["zero"]).cuda())
+    return ntbc.Model(desc, w, torch.from_numpy(g["grid"]).cuda())
+
+
+def _materials():
+    """Three models of different widths / first-layer shapes, each with its mip chain as items."""
+    out = []
+    for cfg, seed in ((synth.config_small(256), 1), (synth.config_mid(512), 2), (synth.config_paper_scale(1024), 3)):
+        flat, layers, g = model_inputs(cfg, seed)
+        out.append((cfg, layers, g, _device_model(cfg, flat, g)))
+    return out
+
+
+def _entries(mats):
+    entries, meta = [], []
+    for k, (cfg, layers, g, model) in enumerate(mats):
+        level = 0
+        while (cfg.blocks_w >> level) >= 1:
+            d = ntbc.mip_desc(model.desc, level)
+            n = d.blocks_w * d.blocks_h
+            entries.append((model, d, 0, n))
+            meta.append((k, level))
+            level += 1
+        # a partial range of the top level as well
+        entries.append((model, model.desc, 37, model.desc.blocks_w * model.desc.blocks_h - 37 - 5))
+        meta.append((k, -1))
+    return entries, meta
+
+
+@pytest.mark.parametrize("precision", [ntbc.BF16, ntbc.FP16])
+def test_batch_equals_single_launches_and_oracle(precision):
+    mats = _materials()
+    entries, meta = _entries(mats)
+    batch = ntbc.Batch(entries, precision)
+    stamps = torch.zeros(len(entries) + 1, dtype=torch.int64, device="cuda")
+    outs = batch.run(stamps)
+    torch.cuda.synchronize()
+    emu = {ntbc.BF16: "bf16", ntbc.FP16: "fp16"}[precision]
+    tol = {ntbc.BF16: 1e-2, ntbc.FP16: 2e-3}[precision]
+    for (model, d, first, n), out, (k, level) in zip(entries, outs, meta):
+        single = ntbc.Model(d, model.weights, model.grid, model.grid_scale, model.grid_zero).infer(
+            precision, first_block=first, n_blocks=n)
+        assert torch.equal(out, single), f"material {k} level {level}"
+    # oracle on a sample of every material's top level and its mip 2
+    for (model, d, first, n), out, (k, level) in zip(entries, outs, meta):
+        if level not in (0, 2):
+            continue
+        cfg, layers, g, _ = mats[k]
+        mcfg = dataclasses.replace(cfg, blocks_w=d.blocks_w, blocks_h=d.blocks_h)
+        lv = oracle_levels(mcfg, g)
+        ids = np.unique(np.random.default_rng(k + 7 * level).integers(0, n, min(n, 400)))
+        y_or = ON.heads(mcfg, lv, layers, ids + first, emu)
+        w_or = ON.pack(y_or, mcfg.formats)
+        single, heads = ntbc.Model(d, model.weights, model.grid, model.grid_scale, model.grid_zero).infer(
+            precision, heads=True)
+        hs = heads[torch.from_numpy(ids).cuda()].cpu().numpy()
+        ws = u64(out[:, torch.from_numpy(ids).cuda()])
+        res = OM.classify_differences(hs, ws, y_or, w_or, mcfg.formats)
+        dy = np.abs(hs.astype(np.float64) - y_or).max()
+        log(f"batch material {k} level {level}: identity {OM.identity(ws, w_or):.5f} max|dY| {dy:.3g} "
+            f"differ {res['differ']} ties {res['ties']}")
+        assert res["repack_exact"] and res["ties"] == res["differ"] and dy <= tol
+    st = stamps.cpu().numpy()
+    assert st[0] > 0 and (st[1:] >= st[0]).all()
+
+
+def test_batch_graph_replay():
+    mats = _materials()
+    entries, _ = _entries(mats)
+    batch = ntbc.Batch(entries, ntbc.BF16)
+    eager = [o.clone() for o in batch.run()]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        batch.run()  # warm-up on the capture stream (kernel attributes set outside the capture)
+        stream.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            batch.run()
+    torch.cuda.current_stream().wait_stream(stream)
+    for rep in range(3):
+        for o in batch.outputs:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(batch.outputs, eager):
+            assert torch.equal(o, e), f"replay {rep}"
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
