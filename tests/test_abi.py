@@ -88,3 +88,37 @@ def test_fp8_arguments_rejected_on_host():
     p.fp8_scales = 0x1000
     assert lib.ntbc_infer_blocks(ctypes.byref(wide), ctypes.byref(p), ntbc.FP8_E4M3, 0, 16, dummy, None, dummy,
                                  1 << 30, None) == ntbc.EUNSUPPORTED
+
+
+def test_batch_plan_validates_on_host():
+    ensure_built()
+    lib = ntbc.lib()
+    cfg = synth.config_small()
+    item = ntbc.BatchItemC()
+    item.desc = ntbc.desc_from_config(cfg)
+    item.params.grid, item.params.weights = 0x1000, 0x1000
+    item.first_block, item.n_blocks, item.blocks_out, item.model_id = 0, 16, 0x1000, 0
+    arr = (ntbc.BatchItemC * 1)(item)
+    tb = ntbc._SZ()
+    assert lib.ntbc_batch_table_size(1, ctypes.byref(tb)) == ntbc.OK and tb.value > 0
+    table = (ctypes.c_uint8 * tb.value)()
+    ws = ntbc._SZ()
+    assert lib.ntbc_batch_plan(ctypes.addressof(arr), 1, ntbc.BF16, None, ctypes.addressof(table), tb.value,
+                               ctypes.byref(ws)) == ntbc.OK
+    assert ws.value > 0
+    # FP32 is not a batched precision; a table that is too small; a range outside the block grid
+    assert lib.ntbc_batch_plan(ctypes.addressof(arr), 1, ntbc.FP32, None, ctypes.addressof(table), tb.value,
+                               ctypes.byref(ws)) == ntbc.EINVAL
+    assert lib.ntbc_batch_plan(ctypes.addressof(arr), 1, ntbc.BF16, None, ctypes.addressof(table), 8,
+                               ctypes.byref(ws)) == ntbc.EINVAL
+    arr[0].n_blocks = cfg.n_positions + 1
+    assert lib.ntbc_batch_plan(ctypes.addressof(arr), 1, ntbc.BF16, None, ctypes.addressof(table), tb.value,
+                               ctypes.byref(ws)) == ntbc.EINVAL
+    # a plan made without a workspace cannot be packed; a foreign buffer is not a plan
+    arr[0].n_blocks = 16
+    assert lib.ntbc_batch_plan(ctypes.addressof(arr), 1, ntbc.BF16, None, ctypes.addressof(table), tb.value,
+                               ctypes.byref(ws)) == ntbc.OK
+    assert lib.ntbc_batch_pack(ctypes.addressof(table), ctypes.c_void_p(0x1000), ws.value, None) == ntbc.EINVAL
+    junk = (ctypes.c_uint8 * 64)()
+    assert lib.ntbc_infer_batch(ctypes.addressof(junk), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 20,
+                                None, None) == ntbc.EINVAL
