@@ -199,17 +199,16 @@ __device__ __forceinline__ int expand6d(int v) { return (v << 2) | (v >> 4); }
 
 struct Bc1Pal {
   uint32_t c0, c1;
+  uint32_t map;     // stored 2-bit code of weight index n at bits 2n (0 for every texel when c0 == c1)
   float pal[4][3];  // weight order
 };
 
 // tab (optional): tab[c] = c / 255 as float32 (correctly rounded), replacing the division.
 __device__ __forceinline__ float unit8(int c, const float* tab) { return tab ? tab[c] : (float)c / 255.0f; }
 
-__device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep, const float* tab = nullptr) {
-  const int r0 = quant_bits(ep[0], 31.0f), g0 = quant_bits(ep[1], 63.0f), b0 = quant_bits(ep[2], 31.0f);
-  const int r1 = quant_bits(ep[3], 31.0f), g1 = quant_bits(ep[4], 63.0f), b1 = quant_bits(ep[5], 31.0f);
-  uint32_t c0 = ((uint32_t)r0 << 11) | ((uint32_t)g0 << 5) | (uint32_t)b0;
-  uint32_t c1 = ((uint32_t)r1 << 11) | ((uint32_t)g1 << 5) | (uint32_t)b1;
+// Palette of two quantised RGB565 endpoints: the larger word becomes c0 (four-colour mode, Sec. 3),
+// entries in weight order a, (2a+b)/3, (a+2b)/3, b of the expanded 8-bit channels.
+__device__ __forceinline__ Bc1Pal bc1_palette(uint32_t c0, uint32_t c1, const float* tab = nullptr) {
   if (c0 < c1) {
     const uint32_t t = c0;
     c0 = c1;
@@ -218,6 +217,7 @@ __device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep, const float* t
   Bc1Pal p;
   p.c0 = c0;
   p.c1 = c1;
+  p.map = c0 == c1 ? 0u : 0x78u;  // weight order 0,1,2,3 -> codes 0,2,3,1
   const int a[3] = {expand5d((c0 >> 11) & 31), expand6d((c0 >> 5) & 63), expand5d(c0 & 31)};
   const int b[3] = {expand5d((c1 >> 11) & 31), expand6d((c1 >> 5) & 63), expand5d(c1 & 31)};
 #pragma unroll
@@ -230,67 +230,92 @@ __device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep, const float* t
   return p;
 }
 
-// 2-bit stored code of the nearest palette entry to colour (r, g, b).
+// RGB565 word of one endpoint head triple.
+__device__ __forceinline__ uint32_t rgb565(float r, float g, float b) {
+  return ((uint32_t)quant_bits(r, 31.0f) << 11) | ((uint32_t)quant_bits(g, 63.0f) << 5) | (uint32_t)quant_bits(b, 31.0f);
+}
+
+__device__ __forceinline__ Bc1Pal bc1_from_heads(const float* ep, const float* tab = nullptr) {
+  return bc1_palette(rgb565(ep[0], ep[1], ep[2]), rgb565(ep[3], ep[4], ep[5]), tab);
+}
+
+// 2-bit stored code of the nearest palette entry to colour (r, g, b): first minimum in weight order.
 __device__ __forceinline__ uint32_t bc1_code(const Bc1Pal& p, float r, float g, float b) {
   float best = 0.0f;
-  int bn = 0;
+  uint32_t sh = 0;  // 2 * weight index of the best entry so far
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
     const float d0 = __fsub_rn(r, p.pal[n][0]), d1 = __fsub_rn(g, p.pal[n][1]), d2 = __fsub_rn(b, p.pal[n][2]);
     const float e = __fadd_rn(__fadd_rn(__fmul_rn(d0, d0), __fmul_rn(d1, d1)), __fmul_rn(d2, d2));
-    if (n == 0 || e < best) {
+    if (n == 0) {
       best = e;
-      bn = n;
+    } else {
+      sh = e < best ? 2u * n : sh;
+      best = e < best ? e : best;
     }
   }
-  if (p.c0 == p.c1) bn = 0;
-  return (0x78u >> (2 * bn)) & 3u;  // weight order 0,1,2,3 -> codes 0,2,3,1
+  return (p.map >> sh) & 3u;
 }
 
 struct Bc4Pal {
   int e0, e1;
   bool eight;
+  uint32_t map;  // stored 3-bit code of weight index n at bits 3n
   float pal[8];  // weight order
 };
 
-__device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep, const float* tab = nullptr) {
+// Palette of two quantised 8-bit endpoints: eight-value mode when e0 > e1, else six values plus 0 and
+// 255.  Stored codes in weight order: eight 0,2,3,4,5,6,7,1; six 6,0,2,3,4,5,1,7.
+__device__ __forceinline__ Bc4Pal bc4_palette(int e0, int e1, const float* tab = nullptr) {
   Bc4Pal p;
-  p.e0 = quant_bits(ep[0], 255.0f);
-  p.e1 = quant_bits(ep[1], 255.0f);
-  p.eight = p.e0 > p.e1;
+  p.e0 = e0;
+  p.e1 = e1;
+  p.eight = e0 > e1;
   int v[8];
   if (p.eight) {
-    v[0] = p.e0;
-    v[7] = p.e1;
+    v[0] = e0;
+    v[7] = e1;
 #pragma unroll
-    for (int j = 1; j <= 6; ++j) v[j] = ((7 - j) * p.e0 + j * p.e1 + 3) / 7;
+    for (int j = 1; j <= 6; ++j) v[j] = ((7 - j) * e0 + j * e1 + 3) / 7;
   } else {
     v[0] = 0;
-    v[1] = p.e0;
-    v[6] = p.e1;
+    v[1] = e0;
+    v[6] = e1;
     v[7] = 255;
 #pragma unroll
-    for (int j = 1; j <= 4; ++j) v[1 + j] = ((5 - j) * p.e0 + j * p.e1 + 2) / 5;
+    for (int j = 1; j <= 4; ++j) v[1 + j] = ((5 - j) * e0 + j * e1 + 2) / 5;
   }
+  constexpr uint32_t kMap8 = 0u | 2u << 3 | 3u << 6 | 4u << 9 | 5u << 12 | 6u << 15 | 7u << 18 | 1u << 21;
+  constexpr uint32_t kMap6 = 6u | 0u << 3 | 2u << 6 | 3u << 9 | 4u << 12 | 5u << 15 | 1u << 18 | 7u << 21;
+  p.map = p.eight ? kMap8 : kMap6;
 #pragma unroll
   for (int n = 0; n < 8; ++n) p.pal[n] = unit8(v[n], tab);
   return p;
 }
 
+__device__ __forceinline__ Bc4Pal bc4_from_heads(const float* ep, const float* tab = nullptr) {
+  return bc4_palette(quant_bits(ep[0], 255.0f), quant_bits(ep[1], 255.0f), tab);
+}
+
+// 3-bit stored code of the nearest palette entry to x, first minimum in weight order.  The palette is
+// monotone in weight order in both modes (eight: e0 > interpolants > e1; six: 0 <= e0 <= interpolants
+// <= e1 <= 1) and rounding is monotone, so the float32 squared distances are unimodal in the weight
+// index: the first minimum is the last index whose distance is strictly below its predecessor's.
 __device__ __forceinline__ uint32_t bc4_code(const Bc4Pal& p, float x) {
-  float best = 0.0f;
-  int bn = 0;
+  float prev;
+  {
+    const float d = __fsub_rn(x, p.pal[0]);
+    prev = __fmul_rn(d, d);
+  }
+  uint32_t sh = 0;  // 3 * weight index of the first minimum so far
 #pragma unroll
-  for (int n = 0; n < 8; ++n) {
+  for (int n = 1; n < 8; ++n) {
     const float d = __fsub_rn(x, p.pal[n]);
     const float e = __fmul_rn(d, d);
-    if (n == 0 || e < best) {
-      best = e;
-      bn = n;
-    }
+    sh = e < prev ? 3u * n : sh;
+    prev = e;
   }
-  if (p.eight) return bn == 0 ? 0u : (bn == 7 ? 1u : (uint32_t)(bn + 1));
-  return bn == 0 ? 6u : (bn == 1 ? 0u : (bn == 6 ? 1u : (bn == 7 ? 7u : (uint32_t)bn)));
+  return (p.map >> sh) & 7u;
 }
 
 }  // namespace dev

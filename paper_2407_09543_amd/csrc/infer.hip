@@ -101,6 +101,7 @@ __device__ __forceinline__ uint32_t relu16x2(uint32_t x) {
 }
 
 constexpr int kMaxLayers = 5;
+constexpr int kHeadRows = 192;  // head rows of the fused 16-bit/FP8 kernels (six 32-row tiles)
 constexpr int kWaves = 2;  // waves per workgroup
 
 struct PackArgs {
@@ -113,6 +114,8 @@ struct PackArgs {
   int64_t bias_off[kMaxLayers];  // floats
   int pos_hidden;                // hidden layers use the chained input permutation
   const float* fp8_scales;       // FP8: [n_layers][2] = (s_x, s_w)
+  int head_perm;                 // head rows permuted for the register-resident BC epilogue
+  int16_t head_src[kHeadRows];   // head_perm: canonical head neuron of packed row r, -1 = zero row
 };
 
 struct InferArgs {
@@ -132,6 +135,9 @@ struct InferArgs {
   const float* fp8_scales;      // FP8: [n_layers][2] = (s_x, s_w)
   int64_t stride;               // calibration: block id of sample i is i * stride
   unsigned* amax;               // calibration: per layer, max |layer input| as float bits
+  // register-resident BC epilogue: texture k of the slot layout (BC1 textures first, then BC4) is
+  // canonical texture reg_tex[k]; reg_ep / reg_ch are its endpoint and colour-channel offsets
+  int reg_tex[NTBC_MAX_TEXTURES], reg_ep[NTBC_MAX_TEXTURES], reg_ch[NTBC_MAX_TEXTURES];
 };
 
 // ------------------------------------------------------------------------------ weight packing
@@ -157,12 +163,13 @@ __global__ void k_pack_lp(PackArgs a, typename LpOp<L>::type* __restrict__ pack,
     const int l = (int)(e % 64);
     const int s = (int)((e / 64) % a.ksteps[layer]);
     const int t = (int)(e / (64 * (int64_t)a.ksteps[layer]));
-    const int row = 32 * t + (l % 32);
+    const int prow = 32 * t + (l % 32);
+    const int row = a.head_perm && layer == a.n_layers - 1 ? (prow < kHeadRows ? a.head_src[prow] : -1) : prow;
     float v[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int col = bf16_col(layer, s, l / 32, m);
-      v[m] = (row < a.out_dim[layer] && col < a.in_dim[layer])
+      v[m] = (row >= 0 && row < a.out_dim[layer] && col < a.in_dim[layer])
                  ? a.w[a.w_off[layer] + (int64_t)row * a.in_dim[layer] + col]
                  : 0.0f;
     }
@@ -173,8 +180,10 @@ __global__ void k_pack_lp(PackArgs a, typename LpOp<L>::type* __restrict__ pack,
     pack[a.pack_off[layer] + e] = x8_of<L>(v);
   }
   const int nb = a.otiles[layer] * 32;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
-    bias[a.bias_off[layer] + i] = i < a.out_dim[layer] ? a.w[a.b_off[layer] + i] : 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+    const int row = a.head_perm && layer == a.n_layers - 1 ? (i < kHeadRows ? a.head_src[i] : -1) : i;
+    bias[a.bias_off[layer] + i] = row >= 0 && row < a.out_dim[layer] ? a.w[a.b_off[layer] + row] : 0.0f;
+  }
 }
 
 __global__ void k_pack_f32(PackArgs a, float* __restrict__ pack, float* __restrict__ bias) {
@@ -380,6 +389,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_lp(InferArgs a) {
 // keeps its accumulators in registers and applies the sigmoid there; the heads are staged in LDS in
 // two halves of 16 positions per wave for the BC epilogue, which reads code/255 from an LDS table.
 constexpr int kHeadTiles = 6;
+static_assert(32 * kHeadTiles == kHeadRows, "head rows");
 constexpr int kMaxChunks = 48;
 constexpr int kLdsWaves = 4;
 constexpr int kChunkTiles = 2;
@@ -518,11 +528,89 @@ __device__ __forceinline__ void hidden_layer(const typename LpOp<L>::type (&in)[
   }
 }
 
+// Register-resident BC epilogue.  Lane (j, g) of a wave holds, after the head products, accumulator
+// v of head tile t = packed head row 32t + 8(v/4) + 4g + v%4 of position j; call 16t + v the lane's
+// slot.  The host permutes the head rows (weights and biases) so that, with NB1 BC1 and NB4 BC4
+// textures (BC1 first in slot order), lane group g holds for every texture the predicted colours of
+// texels 8g .. 8g+7 and endpoint g:
+//   BC1 texture k: colour channel c of texel 8g+i at slot 24k + 3i + c, endpoint g (R, G, B) at kE1 + 3k + c
+//   BC4 texture k: texel 8g+i at slot kC4 + 8k + i, endpoint g at kE4 + k
+// (27 NB1 + 9 NB4 = head_dim / 2 slots).  The two lanes of a position exchange their quantised
+// endpoint g and their half of the index bits with one lane swap each, so the BC words are made
+// without staging the heads in LDS, and each palette is built by two lanes instead of four.
+template <int NB1, int NB4>
+struct RegLayout {
+  static constexpr int kC4 = 24 * NB1;
+  static constexpr int kE1 = kC4 + 8 * NB4;
+  static constexpr int kE4 = kE1 + 3 * NB1;
+  static constexpr int kUsed = kE4 + NB4;
+  static_assert(NB1 <= 2 && NB4 <= 4 && kUsed <= 16 * kHeadTiles, "slot layout");
+};
+
+// Canonical head neuron of slot `slot` in lane group g (the inverse of the host's row permutation).
+template <int NB1, int NB4, typename ArgsT>
+__device__ __forceinline__ int reg_canonical(ArgsT a, int slot, int g) {
+  using Y = RegLayout<NB1, NB4>;
+  if (slot < Y::kC4) return a.endpoint_dim + (8 * g + (slot % 24) / 3) * a.channels + a.reg_ch[slot / 24] + slot % 3;
+  if (slot < Y::kE1) return a.endpoint_dim + (8 * g + (slot - Y::kC4) % 8) * a.channels + a.reg_ch[NB1 + (slot - Y::kC4) / 8];
+  if (slot < Y::kE4) return a.reg_ep[(slot - Y::kE1) / 3] + 3 * g + (slot - Y::kE1) % 3;
+  return a.reg_ep[NB1 + slot - Y::kE4] + g;
+}
+
+template <int NB1, int NB4, typename ArgsT>
+__device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadTiles], const float* tab, int g,
+                                             int64_t id, bool valid) {
+  using Y = RegLayout<NB1, NB4>;
+#define NTBC_SLOT(x) h[(x) / 16][(x) % 16]
+  // endpoint g of every texture, quantised here; the partner lane (lane ^ 32) holds the other one
+  uint32_t w1 = 0, w4 = 0;
+#pragma unroll
+  for (int k = 0; k < NB1; ++k)
+    w1 |= dev::rgb565(NTBC_SLOT(Y::kE1 + 3 * k), NTBC_SLOT(Y::kE1 + 3 * k + 1), NTBC_SLOT(Y::kE1 + 3 * k + 2)) << (16 * k);
+#pragma unroll
+  for (int k = 0; k < NB4; ++k) w4 |= (uint32_t)dev::quant_bits(NTBC_SLOT(Y::kE4 + k), 255.0f) << (8 * k);
+  const uint32_t o1 = NB1 > 0 ? (uint32_t)__shfl_xor((int)w1, 32) : 0u;
+  const uint32_t o4 = NB4 > 0 ? (uint32_t)__shfl_xor((int)w4, 32) : 0u;
+  const uint32_t a1 = g ? o1 : w1, b1 = g ? w1 : o1;  // endpoint 0 / endpoint 1 words
+  const uint32_t a4 = g ? o4 : w4, b4 = g ? w4 : o4;
+  const int64_t row = id - a.first;
+#pragma unroll
+  for (int k = 0; k < NB1; ++k) {
+    const dev::Bc1Pal p = dev::bc1_palette((a1 >> (16 * k)) & 0xFFFFu, (b1 >> (16 * k)) & 0xFFFFu, tab);
+    uint32_t codes = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      codes |= dev::bc1_code(p, NTBC_SLOT(24 * k + 3 * i), NTBC_SLOT(24 * k + 3 * i + 1), NTBC_SLOT(24 * k + 3 * i + 2))
+               << (2 * i);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)codes, 32);  // texels 8..15 from lane group 1
+    if (g == 0 && valid)
+      a.out[(int64_t)a.reg_tex[k] * a.n + row] = (uint64_t)p.c0 | ((uint64_t)p.c1 << 16) | ((uint64_t)(codes | (hi << 16)) << 32);
+  }
+#pragma unroll
+  for (int k = 0; k < NB4; ++k) {
+    const dev::Bc4Pal p = dev::bc4_palette((int)((a4 >> (8 * k)) & 255u), (int)((b4 >> (8 * k)) & 255u), tab);
+    uint32_t codes = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) codes |= dev::bc4_code(p, NTBC_SLOT(Y::kC4 + 8 * k + i)) << (3 * i);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)codes, 32);
+    if (g == 0 && valid)
+      a.out[(int64_t)a.reg_tex[NB1 + k] * a.n + row] =
+          (uint64_t)p.e0 | ((uint64_t)p.e1 << 8) | (((uint64_t)codes | ((uint64_t)hi << 24)) << 16);
+  }
+  if (a.heads && valid) {
+    float* hr = a.heads + row * a.head_dim;
+#pragma unroll
+    for (int x = 0; x < Y::kUsed; ++x) hr[reg_canonical<NB1, NB4>(a, x, g)] = NTBC_SLOT(x);
+  }
+#undef NTBC_SLOT
+}
+
 // The fused network of one tile of kLdsWaves * 32 block positions (tile index `tile` of the range
 // a.first .. a.first + a.n).
 // ArgsT/ChunksT: by value for the single-range kernel (its by-value parameters are then read in place
 // from the kernel-argument segment), references for work items in device memory.
-template <Lp L, int HID, int KS0, int NH, typename ArgsT = const InferArgs, typename ChunksT = const ChunkTable>
+template <Lp L, int HID, int KS0, int NH, int NB1 = -1, int NB4 = 0, typename ArgsT = const InferArgs,
+          typename ChunksT = const ChunkTable>
 __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
   typedef typename LpOp<L>::type Op;
   constexpr int S = HID / 16;
@@ -637,22 +725,30 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
       ++c;
     }
   }
-  // sigmoid heads in registers (all lanes), then staged in LDS 16 positions at a time for the pack
+  // sigmoid heads in registers (all lanes; the register epilogue's layout uses the first kUsed slots)
+  constexpr int used = NB1 >= 0 ? RegLayout<NB1 < 0 ? 0 : NB1, NB4>::kUsed : 16 * kHeadTiles;
 #pragma unroll
   for (int t = 0; t < kHeadTiles; ++t) {
     if (t < nht) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (16 * t + 4 * q >= used) continue;
         const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
         const float bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          if (16 * t + 4 * q + r >= used) continue;
           const float z = L == Lp::FP8 ? hacc[t][4 * q + r] * head_mul : hacc[t][4 * q + r];
           hacc[t][4 * q + r] = sigmoid_fast(z + bv[r]);
         }
       }
     }
   }
+  if constexpr (NB1 >= 0) {
+    reg_epilogue<NB1, NB4>(a, hacc, tab, g, id, pos0 + j <= last);
+    return;
+  }
+  // otherwise staged in LDS 16 positions at a time for the pack
   float* y = ybase + wave * 16 * a.head_stride;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
@@ -677,10 +773,10 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
 }
 
 // One block range per launch, its arguments in the kernel-argument segment.
-template <Lp L, int HID, int KS0, int NH>
+template <Lp L, int HID, int KS0, int NH, int NB1, int NB4>
 __global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_infer_lds(InferArgs a, ChunkTable ct) {
-  infer_tile<L, HID, KS0, NH>(a, ct, xcd_tile(blockIdx.x, gridDim.x));
+  infer_tile<L, HID, KS0, NH, NB1, NB4>(a, ct, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ------------------------------------------------------------------------------ launch over work items
@@ -714,7 +810,7 @@ k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __
     else hi = mid - 1;
   }
   const BatchItem& it = *(const BatchItem*)(citems + lo);
-  infer_tile<L, HID, KS0, NH, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
+  infer_tile<L, HID, KS0, NH, -1, 0, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
   if (stamps != nullptr) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1003,6 +1099,56 @@ int launch_batch_group(const BatchGroup& gr, const BatchItem* items, unsigned* d
   return check_launch("ntbc_infer_batch");
 }
 
+// Register-resident BC epilogue (see RegLayout): the slot layout of a model when the fused kernel has
+// an instance for its texture mix and network shape, else nb1 = -1 (heads staged in LDS).
+struct RegPlan {
+  int nb1 = -1, nb4 = 0;
+  int tex[NTBC_MAX_TEXTURES] = {};
+};
+
+bool reg_instance(const Plan& p, int nb1, int nb4) {
+  const bool shape = (p.hid_inst == 256 && p.ksteps[0] == 4) || (p.hid_inst == 128 && p.ksteps[0] == 3);
+  return shape && batch_nh(p) == 2 && nb1 == 2 && nb4 == 3;
+}
+
+RegPlan reg_plan(const Plan& p) {
+  const Shape& s = p.s;
+  RegPlan r;
+  int nb1 = 0, nb4 = 0;
+  for (int t = 0; t < s.n_textures; ++t)
+    if (s.formats[t] == NTBC_BC1) r.tex[nb1++] = t;
+  for (int t = 0; t < s.n_textures; ++t)
+    if (s.formats[t] == NTBC_BC4) r.tex[nb1 + nb4++] = t;
+  if (reg_instance(p, nb1, nb4) && 27 * nb1 + 9 * nb4 <= 16 * p.otiles[s.n_layers - 1]) {
+    r.nb1 = nb1;
+    r.nb4 = nb4;
+  }
+  return r;
+}
+
+// Canonical head neuron of packed head row `row` under the register layout, -1 for a padding row.
+int reg_source(const Shape& s, const RegPlan& r, int row) {
+  const int t = row / 32, q = (row % 32) / 8, g = (row % 8) / 4, slot = 16 * t + 4 * q + row % 4;
+  const int c4 = 24 * r.nb1, e1 = c4 + 8 * r.nb4, e4 = e1 + 3 * r.nb1, used = e4 + r.nb4;
+  if (slot < c4)
+    return s.endpoint_dim + (8 * g + (slot % 24) / 3) * s.channels + s.ch_off[r.tex[slot / 24]] + slot % 3;
+  if (slot < e1) return s.endpoint_dim + (8 * g + (slot - c4) % 8) * s.channels + s.ch_off[r.tex[r.nb1 + (slot - c4) / 8]];
+  if (slot < e4) return s.ep_off[r.tex[(slot - e1) / 3]] + 3 * g + (slot - e1) % 3;
+  if (slot < used) return s.ep_off[r.tex[r.nb1 + slot - e4]] + g;
+  return -1;
+}
+
+void apply_reg_plan(const Shape& s, const RegPlan& r, PackArgs* pa, InferArgs* a) {
+  if (r.nb1 < 0) return;
+  pa->head_perm = 1;
+  for (int row = 0; row < kHeadRows; ++row) pa->head_src[row] = (int16_t)reg_source(s, r, row);
+  for (int k = 0; k < r.nb1 + r.nb4; ++k) {
+    a->reg_tex[k] = r.tex[k];
+    a->reg_ep[k] = s.ep_off[r.tex[k]];
+    a->reg_ch[k] = s.ch_off[r.tex[k]];
+  }
+}
+
 // Kernel arguments common to inference and calibration: the grid view, the packed-weight plan and the
 // texture layout (block range, outputs and workspace pointers are set by the caller).
 InferArgs infer_args(const Plan& p, const ntbc_model_desc* d, const ntbc_params* prm) {
@@ -1116,6 +1262,9 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     pa.bias_off[k] = p.bias_off[k];
   }
   pa.fp8_scales = prm->fp8_scales;
+  InferArgs a = infer_args(p, d, prm);
+  const RegPlan rp = (lp16 || fp8) && lds_shape ? reg_plan(p) : RegPlan{};
+  apply_reg_plan(s, rp, &pa, &a);
   if (!(prm->flags & NTBC_REUSE_PACKED)) {
     const dim3 pgrid(64, s.n_layers);
     if (fp8)
@@ -1130,7 +1279,6 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     if (st != NTBC_OK) return st;
   }
 
-  InferArgs a = infer_args(p, d, prm);
   a.wpack = wpack;
   a.bias = bias;
   a.first = first_block;
@@ -1149,19 +1297,22 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
     const Lp want = fp8 ? Lp::FP8 : (precision == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
     const int nh = batch_nh(p);
-#define NTBC_LDS_INSTANCE_L(LP, H, K, NH)                                                             \
-    if (p.hid_inst == H && p.ksteps[0] == K && nh == NH && want == LP) {                             \
-      fn = (const void*)k_infer_lds<LP, H, K, NH>;                                                   \
+#define NTBC_LDS_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                   \
+    if (p.hid_inst == H && p.ksteps[0] == K && nh == NH && want == LP && rp.nb1 == NB1 && (NB1 < 0 || rp.nb4 == NB4)) { \
+      fn = (const void*)k_infer_lds<LP, H, K, NH, NB1, NB4>;                                         \
       launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
-        hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH>), gr, bl, sh, st, x, y);                       \
+        hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH, NB1, NB4>), gr, bl, sh, st, x, y);             \
       };                                                                                             \
     }
-#define NTBC_LDS_INSTANCE(H, K, NH) \
-    NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH) NTBC_LDS_INSTANCE_L(Lp::FP8, H, K, NH)
-    NTBC_LDS_INSTANCE(64, 1, -1) NTBC_LDS_INSTANCE(64, 2, -1) NTBC_LDS_INSTANCE(64, 3, -1) NTBC_LDS_INSTANCE(64, 4, -1)
-    NTBC_LDS_INSTANCE(128, 1, -1) NTBC_LDS_INSTANCE(128, 2, -1) NTBC_LDS_INSTANCE(128, 3, -1) NTBC_LDS_INSTANCE(128, 4, -1)
-    NTBC_LDS_INSTANCE(256, 1, -1) NTBC_LDS_INSTANCE(256, 2, -1) NTBC_LDS_INSTANCE(256, 3, -1) NTBC_LDS_INSTANCE(256, 4, -1)
-    NTBC_LDS_INSTANCE(128, 3, 2) NTBC_LDS_INSTANCE(256, 4, 2)
+#define NTBC_LDS_INSTANCE(H, K, NH, NB1, NB4)                                                                   \
+    NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH, NB1, NB4) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH, NB1, NB4) \
+    NTBC_LDS_INSTANCE_L(Lp::FP8, H, K, NH, NB1, NB4)
+    NTBC_LDS_INSTANCE(64, 1, -1, -1, 0) NTBC_LDS_INSTANCE(64, 2, -1, -1, 0) NTBC_LDS_INSTANCE(64, 3, -1, -1, 0)
+    NTBC_LDS_INSTANCE(64, 4, -1, -1, 0) NTBC_LDS_INSTANCE(128, 1, -1, -1, 0) NTBC_LDS_INSTANCE(128, 2, -1, -1, 0)
+    NTBC_LDS_INSTANCE(128, 3, -1, -1, 0) NTBC_LDS_INSTANCE(128, 4, -1, -1, 0) NTBC_LDS_INSTANCE(256, 1, -1, -1, 0)
+    NTBC_LDS_INSTANCE(256, 2, -1, -1, 0) NTBC_LDS_INSTANCE(256, 3, -1, -1, 0) NTBC_LDS_INSTANCE(256, 4, -1, -1, 0)
+    NTBC_LDS_INSTANCE(128, 3, 2, -1, 0) NTBC_LDS_INSTANCE(256, 4, 2, -1, 0) NTBC_LDS_INSTANCE(128, 3, 2, 2, 3)
+    NTBC_LDS_INSTANCE(256, 4, 2, 2, 3)
 #undef NTBC_LDS_INSTANCE
 #undef NTBC_LDS_INSTANCE_L
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);

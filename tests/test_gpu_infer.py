@@ -119,16 +119,23 @@ def test_paper_scale_sampled(precision):
 
 
 @pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
-def test_ranges_and_ragged_tail(precision):
-    cfg = synth.config_small(256)
+@pytest.mark.parametrize("which", ["small", "mid"])
+def test_ranges_and_ragged_tail(which, precision):
+    # small: heads staged in LDS; mid (two BC1 + three BC4 textures): register-resident BC epilogue
+    cfg = synth.config_small(256) if which == "small" else synth.config_mid(1024)
     flat, layers, g = model_inputs(cfg, 4)
     m = _device_model(cfg, flat, g)
     full = u64(m.infer(precision))
-    for first, n in ((5, 77), (0, 1), (4000, 96), (4095, 1), (17, 33)):
+    words_h, heads = m.infer(precision, heads=True)
+    assert np.array_equal(u64(words_h), full), "blocks differ when the heads are also written"
+    last = cfg.n_positions - 1
+    for first, n in ((5, 77), (0, 1), (4000, 96), (last, 1), (17, 33), (last - 200, 201)):
         part = u64(m.infer(precision, first, n))
         assert np.array_equal(part, full[:, first:first + n]), (first, n)
+        part_w, part_h = m.infer(precision, first, n, heads=True)
+        assert torch.equal(part_h, heads[first:first + n]), (first, n)
     empty = m.infer(precision, 10, 0)
-    assert empty.shape == (2, 0)
+    assert empty.shape == (len(cfg.formats), 0)
 
 
 VARIANTS = [
