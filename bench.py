@@ -40,11 +40,19 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
 
 
-def time_call(fn, steps, warmup, torch):
-    """Average ms per call over `steps` calls (HIP events on the current stream), after `warmup`."""
+def time_call(fn, steps, warmup, torch, settle_s=0.2):
+    """Average ms per call over `steps` calls (HIP events on the current stream), after `warmup` calls
+    and, untimed too, further calls until the GPU has been busy with this call for `settle_s` seconds
+    (its clocks settle to the sustained rate of the workload)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0, n = time.perf_counter(), 0
+    while time.perf_counter() - t0 < settle_s and n < 100000:
+        for _ in range(8):
+            fn()
+        n += 8
+        torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record()

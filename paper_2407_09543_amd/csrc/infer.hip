@@ -419,9 +419,29 @@ struct ChunkTable {
   int stage;                // u32x4 slots of the staging area: the two chunk buffers, later the heads
 };
 
-// acc + bias (bias4[q] = the four consecutive neurons 32t + 8q + 4g .. +3), ReLU, conversion: the two
-// B-operand words of K-steps 2t and 2t+1 of the next layer.  FP8: z = acc * (s_x s_w) + b, then the
-// ReLU output is divided by the next layer's s_x (`mul`, `inv_next`: exact powers of two).
+// Start value of a tile's accumulators: the bias of its neurons (bias4[q] = neurons 32t + 8q + 4g .. +3,
+// the accumulator layout) for the 16-bit formats, so the products add onto it; zero for FP8, whose
+// products are rescaled before the bias is added.
+template <Lp L>
+__device__ __forceinline__ f32x16_t acc_init(const float* bt, int g) {
+  f32x16_t r{};
+  if constexpr (L != Lp::FP8) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+      r[4 * q] = b.x;
+      r[4 * q + 1] = b.y;
+      r[4 * q + 2] = b.z;
+      r[4 * q + 3] = b.w;
+    }
+  }
+  return r;
+}
+
+// ReLU and conversion of a tile's accumulators (which started from the bias): the two B-operand words
+// of K-steps 2t and 2t+1 of the next layer.  FP8: z = acc * (s_x s_w) + b (bias4[q] = the four
+// consecutive neurons 32t + 8q + 4g .. +3), then the ReLU output is divided by the next layer's s_x
+// (`mul`, `inv_next`: exact powers of two).
 template <Lp L>
 __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float* bt, int g, typename LpOp<L>::type* lo,
                                                 typename LpOp<L>::type* hi, float mul, float inv_next) {
@@ -440,12 +460,11 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
     *lo = x8_of<L>(r);
     *hi = x8_of<L>(r + 8);
   } else {
-    uint32_t w[8];
+    uint32_t w[8];  // the accumulators started from the bias (acc_init)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
-      w[2 * q] = relu16x2(cvt2<L>(acc[4 * q] + b.x, acc[4 * q + 1] + b.y));
-      w[2 * q + 1] = relu16x2(cvt2<L>(acc[4 * q + 2] + b.z, acc[4 * q + 3] + b.w));
+      w[2 * q] = relu16x2(cvt2<L>(acc[4 * q], acc[4 * q + 1]));
+      w[2 * q + 1] = relu16x2(cvt2<L>(acc[4 * q + 2], acc[4 * q + 3]));
     }
     *lo = mk4(w[0], w[1], w[2], w[3]);
     *hi = mk4(w[4], w[5], w[6], w[7]);
@@ -454,7 +473,7 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
 
 // One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `valid`) over KS K-steps, the
 // A fragments read from LDS kPrefetch K-steps ahead of their product.
-constexpr int kPrefetch = 2;
+constexpr int kPrefetch = 4;
 
 template <Lp L, int KS, int CT, int S>
 __device__ __forceinline__ void chunk_mfma(const typename LpOp<L>::type* wb, int ks_stride,
@@ -480,7 +499,7 @@ __device__ __forceinline__ void chunk_mfma(const typename LpOp<L>::type* wb, int
 #pragma unroll
     for (int u = 0; u < CT; ++u)
       if (u < valid) acc[u] = mfma16<L>(cur[u], b[s], acc[u]);
-    asm volatile("" ::: "memory");  // A fragments are read PD K-steps ahead, no further
+    __builtin_amdgcn_sched_barrier(0);  // A fragments are read PD K-steps ahead, no further
   }
 }
 
@@ -515,7 +534,7 @@ __device__ __forceinline__ void hidden_layer(const typename LpOp<L>::type (&in)[
     if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
     f32x16_t acc[CT];
 #pragma unroll
-    for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+    for (int u = 0; u < CT; ++u) acc[u] = acc_init<L>(bl + 32 * (CT * tc + u), g);
     chunk_mfma<L, S, CT, S>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), S, in, lane, CT, acc);
 #pragma unroll
     for (int u = 0; u < CT; ++u) {
@@ -662,7 +681,7 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
       if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
       f32x16_t acc[CT];
 #pragma unroll
-      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+      for (int u = 0; u < CT; ++u) acc[u] = acc_init<L>(bl + 32 * (CT * tc + u), g);
       chunk_mfma<L, KS0, CT, KS0>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), KS0, x0, lane, CT, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
@@ -716,7 +735,7 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
       if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
       f32x16_t acc[CT];
 #pragma unroll
-      for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+      for (int u = 0; u < CT; ++u) acc[u] = CT * tc + u < nht ? acc_init<L>(bl + 32 * (CT * tc + u), g) : f32x16_t{};
       chunk_mfma<L, S, CT, S>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), S, bin, lane, nht - CT * tc, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) hacc[CT * tc + u] = acc[u];
@@ -733,13 +752,16 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (16 * t + 4 * q >= used) continue;
-        const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
-        const float bv[4] = {b.x, b.y, b.z, b.w};
+        float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // 16-bit formats: the bias is in the accumulators
+        if constexpr (L == Lp::FP8) {
+          const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
+          bv[0] = b.x, bv[1] = b.y, bv[2] = b.z, bv[3] = b.w;
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if (16 * t + 4 * q + r >= used) continue;
-          const float z = L == Lp::FP8 ? hacc[t][4 * q + r] * head_mul : hacc[t][4 * q + r];
-          hacc[t][4 * q + r] = sigmoid_fast(z + bv[r]);
+          const float z = L == Lp::FP8 ? hacc[t][4 * q + r] * head_mul + bv[r] : hacc[t][4 * q + r];
+          hacc[t][4 * q + r] = sigmoid_fast(z);
         }
       }
     }
