@@ -397,9 +397,28 @@ constexpr int kChunkTiles = 2;
 // Direct global -> LDS copy of a weight chunk (global_load_lds_dwordx4): element e = tid + NT*r goes
 // to dst[e]; within a wave the 64 lanes write 64 consecutive 16-byte slots from the wave's LDS base.
 // The copy completes at the next s_waitcnt vmcnt(0).
+// A wave-uniform pointer made opaque to the optimizer (kept in scalar registers), so that a load from
+// it plus a 32-bit lane offset uses the scalar-base form instead of a per-lane 64-bit address.
+__device__ __forceinline__ const char* scalar_ptr(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<const char*>(((uint64_t)hi << 32) | lo);
+}
+
 template <int PR, int NT>
 __device__ __forceinline__ void chunk_dma(const u32x4* __restrict__ wp, int64_t src, int len, u32x4* dst, int tid) {
-  const int wave_base = tid & ~63;
+  const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
+  if (len == PR * NT) {
+    // a full chunk (the usual case, uniform): no per-slot bounds test, the same per-lane byte offset
+    // for every slot, the slot's global base and LDS destination are scalars
+    const uint32_t voff = (uint32_t)tid * 16u;
+#pragma unroll
+    for (int r = 0; r < PR; ++r)
+      __builtin_amdgcn_global_load_lds(scalar_ptr(wp + src + NT * r) + voff,
+                                       (__attribute__((address_space(3))) void*)(dst + wave_base + NT * r), 16, 0, 0);
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < PR; ++r) {
     const int e = tid + NT * r;
@@ -581,6 +600,9 @@ __device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadT
                                              int64_t id, bool valid) {
   using Y = RegLayout<NB1, NB4>;
 #define NTBC_SLOT(x) h[(x) / 16][(x) % 16]
+  // value of the partner lane (lane ^ 32): one LDS-crossbar permute with a fixed address
+  const int partner = (((int)threadIdx.x & 63) ^ 32) << 2;
+  auto swap = [partner](uint32_t v) { return (uint32_t)__builtin_amdgcn_ds_bpermute(partner, (int)v); };
   // endpoint g of every texture, quantised here; the partner lane (lane ^ 32) holds the other one
   uint32_t w1 = 0, w4 = 0;
 #pragma unroll
@@ -588,8 +610,8 @@ __device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadT
     w1 |= dev::rgb565(NTBC_SLOT(Y::kE1 + 3 * k), NTBC_SLOT(Y::kE1 + 3 * k + 1), NTBC_SLOT(Y::kE1 + 3 * k + 2)) << (16 * k);
 #pragma unroll
   for (int k = 0; k < NB4; ++k) w4 |= (uint32_t)dev::quant_bits(NTBC_SLOT(Y::kE4 + k), 255.0f) << (8 * k);
-  const uint32_t o1 = NB1 > 0 ? (uint32_t)__shfl_xor((int)w1, 32) : 0u;
-  const uint32_t o4 = NB4 > 0 ? (uint32_t)__shfl_xor((int)w4, 32) : 0u;
+  const uint32_t o1 = NB1 > 0 ? swap(w1) : 0u;
+  const uint32_t o4 = NB4 > 0 ? swap(w4) : 0u;
   const uint32_t a1 = g ? o1 : w1, b1 = g ? w1 : o1;  // endpoint 0 / endpoint 1 words
   const uint32_t a4 = g ? o4 : w4, b4 = g ? w4 : o4;
   const int64_t row = id - a.first;
@@ -601,7 +623,7 @@ __device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadT
     for (int i = 0; i < 8; ++i)
       codes |= dev::bc1_code(p, NTBC_SLOT(24 * k + 3 * i), NTBC_SLOT(24 * k + 3 * i + 1), NTBC_SLOT(24 * k + 3 * i + 2))
                << (2 * i);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)codes, 32);  // texels 8..15 from lane group 1
+    const uint32_t hi = swap(codes);  // texels 8..15 from lane group 1
     if (g == 0 && valid)
       a.out[(int64_t)a.reg_tex[k] * a.n + row] = (uint64_t)p.c0 | ((uint64_t)p.c1 << 16) | ((uint64_t)(codes | (hi << 16)) << 32);
   }
@@ -611,7 +633,7 @@ __device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadT
     uint32_t codes = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) codes |= dev::bc4_code(p, NTBC_SLOT(Y::kC4 + 8 * k + i)) << (3 * i);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)codes, 32);
+    const uint32_t hi = swap(codes);
     if (g == 0 && valid)
       a.out[(int64_t)a.reg_tex[NB1 + k] * a.n + row] =
           (uint64_t)p.e0 | ((uint64_t)p.e1 << 8) | (((uint64_t)codes | ((uint64_t)hi << 24)) << 16);
@@ -816,7 +838,7 @@ struct BatchItem {
   int32_t index;  // position of the item in the caller's list (stamps)
 };
 
-template <Lp L, int HID, int KS0, int NH>
+template <Lp L, int HID, int KS0, int NH, int NB1, int NB4>
 __global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __restrict__ done,
                   uint64_t* __restrict__ stamps) {
@@ -832,7 +854,7 @@ k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __
     else hi = mid - 1;
   }
   const BatchItem& it = *(const BatchItem*)(citems + lo);
-  infer_tile<L, HID, KS0, NH, -1, 0, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
+  infer_tile<L, HID, KS0, NH, NB1, NB4, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
   if (stamps != nullptr) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1056,7 +1078,8 @@ __global__ void k_fp8_finalize(const unsigned* __restrict__ amax, int n_layers, 
 
 // The weight-chunk table of the LDS kernel (offsets and lengths in 16-byte units: an FP8 operand is 8
 // bytes, a 16-bit one 16, and every chunk holds a multiple of 64 operands) and its LDS size.
-int make_chunks(const Plan& p, bool fp8, int head_stride, ChunkTable* ct, size_t* lds_out) {
+// staged: the LDS-staged BC epilogue (the heads reuse the chunk buffers, which must hold them).
+int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTable* ct, size_t* lds_out) {
   const Shape& s = p.s;
   const int64_t op_bytes = fp8 ? 8 : 16;
   *ct = ChunkTable{};
@@ -1073,7 +1096,7 @@ int make_chunks(const Plan& p, bool fp8, int head_stride, ChunkTable* ct, size_t
   for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
   ct->n_bias = (int)((nb + 3) / 4 * 4);
   const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * op_bytes;
-  const size_t ybytes = (size_t)kLdsWaves * 16 * head_stride * sizeof(float);
+  const size_t ybytes = staged ? (size_t)kLdsWaves * 16 * head_stride * sizeof(float) : 0;
   const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
   ct->stage = (int)(stage / sizeof(u32x4));
   *lds_out = stage + (256 + (size_t)ct->n_bias) * sizeof(float);
@@ -1082,7 +1105,7 @@ int make_chunks(const Plan& p, bool fp8, int head_stride, ChunkTable* ct, size_t
 }
 
 struct BatchGroup {
-  int32_t lp, hid, ks0, nh;
+  int32_t lp, hid, ks0, nh, nb1, nb4;
   int32_t item_begin, item_end;
   int64_t tiles, lds;
 };
@@ -1099,19 +1122,25 @@ int launch_batch_group(const BatchGroup& gr, const BatchItem* items, unsigned* d
   const void* fn = nullptr;
   void (*launch)(dim3, dim3, size_t, hipStream_t, const BatchItem*, int, unsigned*, uint64_t*) = nullptr;
   const Lp want = gr.lp == NTBC_FP8_E4M3 ? Lp::FP8 : (gr.lp == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
-#define NTBC_BATCH_INSTANCE_L(LP, H, K, NH)                                                           \
-  if (gr.hid == H && gr.ks0 == K && gr.nh == NH && want == LP) {                                      \
-    fn = (const void*)k_infer_lds_batch<LP, H, K, NH>;                                               \
+#define NTBC_BATCH_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                 \
+  if (gr.hid == H && gr.ks0 == K && gr.nh == NH && want == LP && gr.nb1 == NB1 && (NB1 < 0 || gr.nb4 == NB4)) { \
+    fn = (const void*)k_infer_lds_batch<LP, H, K, NH, NB1, NB4>;                                     \
     launch = [](dim3 g, dim3 b, size_t sh, hipStream_t st, const BatchItem* it, int n, unsigned* d, uint64_t* s) { \
-      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH>), g, b, sh, st, it, n, d, s);                \
+      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH, NB1, NB4>), g, b, sh, st, it, n, d, s);    \
     };                                                                                                 \
   }
-#define NTBC_BATCH_INSTANCE(H, K, NH) \
-  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH) NTBC_BATCH_INSTANCE_L(Lp::FP16, H, K, NH) NTBC_BATCH_INSTANCE_L(Lp::FP8, H, K, NH)
+#define NTBC_BATCH_INSTANCE(H, K, NH)                                                        \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, -1, 0) NTBC_BATCH_INSTANCE_L(Lp::FP16, H, K, NH, -1, 0) \
+  NTBC_BATCH_INSTANCE_L(Lp::FP8, H, K, NH, -1, 0)
+#define NTBC_BATCH_REG(H, K, NH)                                                                 \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 1) NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 2) \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 3)
   NTBC_BATCH_INSTANCE(64, 1, -1) NTBC_BATCH_INSTANCE(64, 2, -1) NTBC_BATCH_INSTANCE(64, 3, -1) NTBC_BATCH_INSTANCE(64, 4, -1)
   NTBC_BATCH_INSTANCE(128, 1, -1) NTBC_BATCH_INSTANCE(128, 2, -1) NTBC_BATCH_INSTANCE(128, 3, -1) NTBC_BATCH_INSTANCE(128, 4, -1)
   NTBC_BATCH_INSTANCE(256, 1, -1) NTBC_BATCH_INSTANCE(256, 2, -1) NTBC_BATCH_INSTANCE(256, 3, -1) NTBC_BATCH_INSTANCE(256, 4, -1)
   NTBC_BATCH_INSTANCE(128, 3, 2) NTBC_BATCH_INSTANCE(256, 4, 2)
+  NTBC_BATCH_REG(64, 4, -1) NTBC_BATCH_REG(128, 4, -1) NTBC_BATCH_REG(256, 4, 2)
+#undef NTBC_BATCH_REG
 #undef NTBC_BATCH_INSTANCE
 #undef NTBC_BATCH_INSTANCE_L
   NTBC_REQUIRE(fn != nullptr, "no batch kernel instance for width %d, %d input K-steps", gr.hid, gr.ks0);
@@ -1128,12 +1157,20 @@ struct RegPlan {
   int tex[NTBC_MAX_TEXTURES] = {};
 };
 
-bool reg_instance(const Plan& p, int nb1, int nb4) {
+// Instances with the register epilogue: single range (any precision) for two BC1 + three BC4 textures
+// at the paper-scale and 1024^2 shapes; batched (BF16) for two BC1 + one to three BC4 textures at
+// widths 64, 128 (four input K-steps, run-time layer count) and 256 (four K-steps, two middle layers).
+bool reg_instance(const Plan& p, int nb1, int nb4, bool batch) {
+  if (batch) {
+    const bool shape = (p.hid_inst == 256 && p.ksteps[0] == 4 && batch_nh(p) == 2) ||
+                       ((p.hid_inst == 64 || p.hid_inst == 128) && p.ksteps[0] == 4 && batch_nh(p) == -1);
+    return p.precision == NTBC_BF16 && shape && nb1 == 2 && nb4 >= 1 && nb4 <= 3;
+  }
   const bool shape = (p.hid_inst == 256 && p.ksteps[0] == 4) || (p.hid_inst == 128 && p.ksteps[0] == 3);
   return shape && batch_nh(p) == 2 && nb1 == 2 && nb4 == 3;
 }
 
-RegPlan reg_plan(const Plan& p) {
+RegPlan reg_plan(const Plan& p, bool batch = false) {
   const Shape& s = p.s;
   RegPlan r;
   int nb1 = 0, nb4 = 0;
@@ -1141,7 +1178,7 @@ RegPlan reg_plan(const Plan& p) {
     if (s.formats[t] == NTBC_BC1) r.tex[nb1++] = t;
   for (int t = 0; t < s.n_textures; ++t)
     if (s.formats[t] == NTBC_BC4) r.tex[nb1 + nb4++] = t;
-  if (reg_instance(p, nb1, nb4) && 27 * nb1 + 9 * nb4 <= 16 * p.otiles[s.n_layers - 1]) {
+  if (reg_instance(p, nb1, nb4, batch) && 27 * nb1 + 9 * nb4 <= 16 * p.otiles[s.n_layers - 1]) {
     r.nb1 = nb1;
     r.nb4 = nb4;
   }
@@ -1162,8 +1199,11 @@ int reg_source(const Shape& s, const RegPlan& r, int row) {
 
 void apply_reg_plan(const Shape& s, const RegPlan& r, PackArgs* pa, InferArgs* a) {
   if (r.nb1 < 0) return;
-  pa->head_perm = 1;
-  for (int row = 0; row < kHeadRows; ++row) pa->head_src[row] = (int16_t)reg_source(s, r, row);
+  if (pa) {
+    pa->head_perm = 1;
+    for (int row = 0; row < kHeadRows; ++row) pa->head_src[row] = (int16_t)reg_source(s, r, row);
+  }
+  if (!a) return;
   for (int k = 0; k < r.nb1 + r.nb4; ++k) {
     a->reg_tex[k] = r.tex[k];
     a->reg_ep[k] = s.ep_off[r.tex[k]];
@@ -1312,7 +1352,7 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
   if ((lp16 || fp8) && lds_shape) {
     ChunkTable ct{};
     size_t lds = 0;
-    st = make_chunks(p, fp8, a.head_stride, &ct, &lds);
+    st = make_chunks(p, fp8, a.head_stride, rp.nb1 < 0, &ct, &lds);
     if (st != NTBC_OK) return st;
     const int64_t nwg = ceil_div(n_blocks, (int64_t)32 * kLdsWaves);
     const void* fn = nullptr;
@@ -1518,16 +1558,20 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
       off = (int64_t)align_up((size_t)(off + p.total_bytes), 256);
     } else {
       const Plan& q = plans[model_item[m]];
-      bool same = q.s.n_layers == s.n_layers && q.total_bytes == p.total_bytes;
+      bool same = q.s.n_layers == s.n_layers && q.total_bytes == p.total_bytes && q.s.n_textures == s.n_textures;
       for (int k = 0; same && k < s.n_layers; ++k) same = q.s.layer_in[k] == s.layer_in[k] && q.s.layer_out[k] == s.layer_out[k];
+      for (int t = 0; same && t < s.n_textures; ++t) same = q.s.formats[t] == s.formats[t];
       NTBC_REQUIRE(same && items[model_item[m]].params.weights == it.params.weights,
-                   "item %d: model_id %d shared by items with different weights or layer shapes", i, it.model_id);
+                   "item %d: model_id %d shared by items with different weights, layer shapes or textures", i, it.model_id);
     }
     model_of[i] = m;
-    const BatchGroup want{precision, p.hid_inst, p.ksteps[0], batch_nh(p), 0, 0, 0, 0};
+    const RegPlan rp = reg_plan(p, true);
+    const BatchGroup want{precision, p.hid_inst, p.ksteps[0], batch_nh(p), rp.nb1, rp.nb4, 0, 0, 0, 0};
     int gi = -1;
     for (size_t q = 0; q < groups.size(); ++q)
-      if (groups[q].hid == want.hid && groups[q].ks0 == want.ks0 && groups[q].nh == want.nh) gi = (int)q;
+      if (groups[q].hid == want.hid && groups[q].ks0 == want.ks0 && groups[q].nh == want.nh &&
+          groups[q].nb1 == want.nb1 && groups[q].nb4 == want.nb4)
+        gi = (int)q;
     if (gi < 0) {
       NTBC_REQUIRE((int)groups.size() < kMaxBatchGroups, "more than %d kernel instances in one batch", kMaxBatchGroups);
       gi = (int)groups.size();
@@ -1570,6 +1614,7 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
       bp.pa.bias_off[k] = p.bias_off[k];
     }
     bp.pa.fp8_scales = items[i].params.fp8_scales;
+    apply_reg_plan(s, reg_plan(p, true), &bp.pa, nullptr);  // head rows permuted for the register epilogue
     bp.pack = ws ? ws + model_off[m] : nullptr;
     bp.bias = ws ? reinterpret_cast<float*>(ws + model_off[m] + (int64_t)align_up((size_t)p.pack_bytes, 256)) : nullptr;
     packs[m] = bp;
@@ -1585,6 +1630,7 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
       const Plan& p = plans[i];
       BatchItem bi{};
       bi.a = infer_args(p, &items[i].desc, &items[i].params);
+      apply_reg_plan(p.s, reg_plan(p, true), nullptr, &bi.a);
       bi.a.wpack = packs[model_of[i]].pack;
       bi.a.bias = packs[model_of[i]].bias;
       bi.a.first = items[i].first_block;
@@ -1592,7 +1638,7 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
       bi.a.out = items[i].blocks_out;
       bi.a.heads = nullptr;
       size_t lds = 0;
-      int st = make_chunks(p, precision == NTBC_FP8_E4M3, bi.a.head_stride, &bi.ct, &lds);
+      int st = make_chunks(p, precision == NTBC_FP8_E4M3, bi.a.head_stride, reg_plan(p, true).nb1 < 0, &bi.ct, &lds);
       if (st != NTBC_OK) return st;
       gr.lds = std::max<int64_t>(gr.lds, (int64_t)lds);
       bi.tile_begin = tiles;

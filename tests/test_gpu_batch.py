@@ -35,9 +35,15 @@ def _device_model(cfg, flat, g):
 
 
 def _materials():
-    """Three models of different widths / first-layer shapes, each with its mip chain as items."""
+    """Five models of different widths / first-layer shapes / texture mixes, each with its mip chain as
+    items.  In BF16 the paper-scale model (two BC1 + three BC4, width 256) and the two 64-input models
+    (two BC1 + two BC4 at width 128, two BC1 + one BC4 at width 64, run-time layer count) use the
+    register-resident BC epilogue in the batch, while their single launches use the LDS-staged one."""
     out = []
-    for cfg, seed in ((synth.config_small(256), 1), (synth.config_mid(512), 2), (synth.config_paper_scale(1024), 3)):
+    w128 = dataclasses.replace(synth.config_mid(256), n_levels=8, base_res=2, hidden=128, n_hidden=2, formats=(1, 1, 4, 4))
+    w64 = dataclasses.replace(synth.config_mid(128), n_levels=8, base_res=2, hidden=64, n_hidden=3, formats=(1, 1, 4))
+    for cfg, seed in ((synth.config_small(256), 1), (synth.config_mid(512), 2), (synth.config_paper_scale(1024), 3),
+                      (w128, 4), (w64, 5)):
         flat, layers, g = model_inputs(cfg, seed)
         out.append((cfg, layers, g, _device_model(cfg, flat, g)))
     return out
