@@ -80,7 +80,7 @@ def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
         t0 = time.perf_counter()
         ON.infer_blocks(cfg, levels, layers, ids)
         t_used = time.perf_counter() - t0
-        if t_used * 2 > budget_s or n >= 262144:
+        if t_used * 2 > budget_s or 2 * n > cfg.n_positions:
             break
         n *= 2
     blocks = n * len(cfg.formats)
@@ -371,7 +371,7 @@ def main():
                    "grid": "8 levels 8..1024 x 8 uint8", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                     "kernel": "k_infer_lds<BF16,256,4,2>", "flop_per_launch": flop},
+                     "kernel": "k_infer_lds<BF16,256,4,2,2,3>", "flop_per_launch": flop},
         "fp32": {"blocks_per_s": n_blocks / (ms_fp * 1e-3), "ms_per_step": ms_fp,
                  "tflops": flop / (ms_fp * 1e-3) / 1e12, "frac_fp32_peak": flop / (ms_fp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
         "speedup_bf16_vs_fp32": ms_fp / ms_bf,
