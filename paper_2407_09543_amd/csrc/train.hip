@@ -5,8 +5,9 @@
 //   k_features                      bilinear features of the (fake-quantised) grid -> X [B][in]
 //   k_gemm (bias+ReLU / sigmoid)    MLP forward, every layer's input kept for the batch
 //   k_loss_grad                     L_e, L_c and both decoded-colour terms, dL/dY with the STE
-//   k_dsigmoid                      dZ_out = dY * Y (1 - Y)
+//   k_dsigmoid                      dZ_out = dY * Y (1 - Y) (in the training step: inside k_loss_grad)
 //   k_gemm (mask / split-K atomic)  dH_k = dZ_k W_k masked by ReLU, dW_k = dZ_k^T H_k, db by k_colsum
+//                                   (bfloat16 products: db fused into the dW product)
 //   k_scatter                       dX through the bilinear weights into d_grid (atomic), QAT
 //                                   pass-through mask
 //   k_adam                          dense bias-corrected Adam, learning rate from the host schedule
@@ -274,6 +275,7 @@ struct GemmArgs {
   const float* bias;  // [N]
   const float* mask;  // C(m, n) *= (mask[m*ldm + n] > 0)
   int64_t ldm;
+  float* colsum;      // bfloat16 split-K product only: colsum[m] += sum over k of A(m, k) in FP32 (bias gradient)
 };
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -455,8 +457,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * kBT, n0 = blockIdx.x * kBT;
-  const int kbeg = blockIdx.z * g.k_split;
+  const int tn = blockIdx.x, tm = blockIdx.y, tz = blockIdx.z;
+  const int m0 = tm * kBT, n0 = tn * kBT;
+  const int kbeg = tz * g.k_split;
   const int kend = min(g.K, kbeg + g.k_split);
   const bool a_k = g.sak == 1, b_k = g.sbk == 1;
   f32x16_t acc[2][2];
@@ -465,10 +468,21 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x16_t{};
   const int li = lane & 31, lg = lane >> 5;
+  // fused bias gradient (EPI_ATOMIC with colsum, the first column of tiles, A staged MN-contiguous):
+  // the thread's A values are rows (tid % 32) * 4 .. +3 of every slice, summed in FP32 before rounding
+  const bool rows = EPI == EPI_ATOMIC && g.colsum != nullptr && tn == 0 && !a_k;
+  float rs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  auto row_sums = [&](const Stage& st) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rs[e] += st.v[q][e] + st.v[q][4 + e];
+  };
   Stage sa, sb;
   if (kbeg < kend) {
     stage_load(sa, g.a, g.sam, g.sak, m0, g.M, kbeg, kend, tid);   // A(m, k)
     stage_load(sb, g.b, g.sbn, g.sbk, n0, g.N, kbeg, kend, tid);   // B(k, n) as rows n
+    if (rows) row_sums(sa);
     stage_store(sa, a_k, As[0], tid);
     stage_store(sb, b_k, Bs[0], tid);
   }
@@ -479,6 +493,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     if (more) {
       stage_load(sa, g.a, g.sam, g.sak, m0, g.M, k0 + kBTK, kend, tid);
       stage_load(sb, g.b, g.sbn, g.sbk, n0, g.N, k0 + kBTK, kend, tid);
+      if (rows) row_sums(sa);
     }
 #pragma unroll
     for (int ks = 0; ks < kBTK / 16; ++ks) {
@@ -501,6 +516,21 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     }
     __syncthreads();
     buf ^= 1;
+  }
+  if (rows) {
+    // eight threads hold partial sums of each group of four rows: combine them in LDS (the staging
+    // buffers are free after the last barrier of the loop)
+    float* part = reinterpret_cast<float*>(&As[0][0][0]);  // [8][kBT]
+    const int r = (tid & 31) * 4, grp = tid >> 5;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[grp * kBT + r + e] = rs[e];
+    __syncthreads();
+    if (tid < kBT && m0 + tid < g.M) {
+      float t = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += part[q * kBT + tid];
+      atomicAdd(g.colsum + m0 + tid, t);
+    }
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -580,7 +610,13 @@ struct LossArgs {
   float inv_t, w_e, w_c, w_cde, w_cdc;
   float inv_ne, inv_nc;  // 1/(n E), 1/(n 16 C)
   float* losses;         // [5]
+  int dsigmoid;          // write dL/dZ = dL/dY * Y (1 - Y) (the head's pre-activation) instead of dL/dY
 };
+
+// The gradient written for a head value y: dL/dY, or dL/dZ through the sigmoid.
+__device__ __forceinline__ float head_grad(const LossArgs& a, float g, float y) {
+  return a.dsigmoid ? g * y * (1.0f - y) : g;
+}
 
 // Palette coefficients of logical index n (Eq. palette, Eq. weightBC4): c_n = a e0 + b e1 + k, with
 // the weights w_n = n/3 (BC1), n/7 (BC4, e0 > e1) or (n-1)/5 plus the constants 0 and 1 (BC4, e0 <= e1).
@@ -777,7 +813,7 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
     }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-      dyp[ci + ch] = dchat[ch];
+      dyp[ci + ch] = head_grad(a, dchat[ch], chat[ch]);
       *bad |= !isfinite(dchat[ch]);
     }
   }
@@ -825,11 +861,12 @@ __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
     if (active && sub == 0) {
       const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
       float* dyp = a.dy + p * a.head_dim + a.ep_off[t];
+      const float* yp = a.y + p * a.head_dim + a.ep_off[t];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         if (ch < ch_n) {
-          dyp[ch] = de0[ch];
-          dyp[ch_n + ch] = de1[ch];
+          dyp[ch] = head_grad(a, de0[ch], yp[ch]);
+          dyp[ch_n + ch] = head_grad(a, de1[ch], yp[ch_n + ch]);
           bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
         }
       }
@@ -1069,13 +1106,18 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     const int kq = c.bf16 ? kBTK : 16;
     gw.k_split = (int)(ceil_div(ceil_div(c.n, splits), kq) * kq);
     splits = (int)ceil_div(c.n, gw.k_split);
+    // db_k += column sums of dZ_k: fused into the bfloat16 product, a separate kernel otherwise
+    const bool fused = c.bf16 && gw.sak != 1;  // the kernel sums A staged MN-contiguous
+    if (fused) gw.colsum = d_weights + s.b_off[k];
     st = gemm<EPI_ATOMIC>(gw, splits, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
-    const int rpb = 128;
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb), (unsigned)ceil_div(out, 64)), dim3(kBlock), 0, c.strm,
-                       dz, c.n, out, rpb, d_weights + s.b_off[k]);
-    st = check_launch("k_colsum");
-    if (st != NTBC_OK) return st;
+    if (!fused) {
+      const int rpb = 128;
+      hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb), (unsigned)ceil_div(out, 64)), dim3(kBlock), 0,
+                         c.strm, dz, c.n, out, rpb, d_weights + s.b_off[k]);
+      st = check_launch("k_colsum");
+      if (st != NTBC_OK) return st;
+    }
     // dH_k = dZ_k W_k, masked by the ReLU of the layer input (none for the grid features)
     GemmArgs gd{};
     gd.a = dz;
@@ -1116,13 +1158,15 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
   return check_launch("k_scatter");
 }
 
+// dsigmoid: write dL/dZ of the head pre-activations (dL/dY * Y (1 - Y)) instead of dL/dY.
 int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, float temperature,
-              const float* lw, float* losses, float* dheads, hipStream_t strm) {
+              const float* lw, float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false) {
   int st = fill(losses, 5, 0.0f, strm);
   if (st != NTBC_OK) return st;
   LossArgs a{};
   a.y = heads;
   a.dy = dheads;
+  a.dsigmoid = dsigmoid ? 1 : 0;
   a.ids = ids;
   a.n = n;
   a.n_positions = s.n_positions;
@@ -1235,12 +1279,8 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   float* y = c.ws + c.lay.y;
   st = forward(c, tsd->grid, tsd->weights, qat, batch_ids, y);
   if (st != NTBC_OK) return st;
-  st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm);
-  if (st != NTBC_OK) return st;
-  const int64_t ny = c.n * s.head_dim;
-  hipLaunchKernelGGL(k_dsigmoid, dim3((unsigned)std::min<int64_t>(ceil_div(ny, 256), 4096)), dim3(256), 0, c.strm,
-                     c.ws + c.lay.dy, y, c.ws + c.lay.dy, ny);
-  st = check_launch("k_dsigmoid");
+  // dL/dZ of the head pre-activations straight from the loss kernel (the sigmoid derivative fused)
+  st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm, true);
   if (st != NTBC_OK) return st;
   const int64_t ng = s.grid_vertices * s.n_features;
   st = fill(tsd->d_grid, ng, 0.0f, c.strm);
