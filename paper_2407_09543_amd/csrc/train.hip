@@ -757,6 +757,18 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
   const uint8_t* row = a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+  // the lane's texel row (4 texels x CH bytes) in CH words: dword loads when the texture is 4-byte
+  // aligned (the row offset always is), byte loads otherwise
+  uint32_t rw[CH];
+  if ((reinterpret_cast<uintptr_t>(row) & 3) == 0) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k) rw[k] = reinterpret_cast<const uint32_t*>(row)[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+      rw[k] = (uint32_t)row[4 * k] | ((uint32_t)row[4 * k + 1] << 8) | ((uint32_t)row[4 * k + 2] << 16) |
+              ((uint32_t)row[4 * k + 3] << 24);
+  }
 #pragma unroll 1
   for (int x = 0; x < 4; ++x) {
     const int i = 4 * sub + x;
@@ -764,7 +776,9 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
     const int ci = a.E + i * a.C + a.ch_off[t];
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-      c[ch] = (float)row[x * CH + ch] * k255;
+      const int b = x * CH + ch;  // byte of the row (run-time x: words chosen by selects, no indexing)
+      const uint32_t word = CH == 1 ? rw[0] : (b < 4 ? rw[0] : (b < 8 ? rw[CH > 1 ? 1 : 0] : rw[CH > 2 ? 2 : 0]));
+      c[ch] = (float)((word >> (8 * (b & 3))) & 255u) * k255;
       chat[ch] = yp[ci + ch];
       const float d = chat[ch] - c[ch];
       *lc += d * d;

@@ -286,7 +286,8 @@ def test_bf16_training_gradients(which):
 
 def test_bf16_training_matches_fp32_training_quality():
     # the same 600-step encode of the 256^2 five-texture material with FP32 and with bfloat16 products:
-    # decoded PSNR within 1 dB on average over the textures and 4 dB on each
+    # the bfloat16-trained PSNR at most 1 dB lower on average over the textures and 4 dB on each
+    # (being better is not a failure: the runs differ by rounding, which changes the trajectory)
     from paper_2407_09543_amd import encode
     cfg = synth.config_mid(256)
     mat = synth.material_five(256, 4)
@@ -296,6 +297,7 @@ def test_bf16_training_matches_fp32_training_quality():
         res = encode.encode_material(tex, cfg, steps=600, batch=2048, seed=4, train_precision=prec)
         out[prec] = encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, 256)
     log(f"psnr fp32-trained {np.round(out[ntbc.FP32], 2)} bf16-trained {np.round(out[ntbc.BF16], 2)}")
-    # measured: four textures within 0.4 dB, the hardest (AO, ~21 dB) 2.7 dB lower with bfloat16
-    diffs = [a - b for a, b in zip(out[ntbc.FP32], out[ntbc.BF16])]
-    assert abs(float(np.mean(diffs))) <= 1.0 and max(abs(d) for d in diffs) <= 4.0
+    # measured: four textures within 0.6 dB; the hardest (AO, ~21 dB, the most trajectory-sensitive)
+    # 2.7 dB lower with bfloat16 in one version of the kernels and 5.0 dB higher in another
+    loss = [a - b for a, b in zip(out[ntbc.FP32], out[ntbc.BF16])]  # > 0: bfloat16 worse
+    assert float(np.mean(loss)) <= 1.0 and max(loss) <= 4.0
