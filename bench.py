@@ -231,7 +231,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(inference shards by block range with no communication between GPUs)",
               file=sys.stderr)
         sys.exit(2)

@@ -93,6 +93,9 @@ struct GridView {
   // shift_x = log2(2*blocks_w) when that is a power of two and every numerator fits in 31 bits,
   // else -1 (general path); likewise shift_y
   int shift_x, shift_y;
+  // fast8: uint8 grid, 8 features per vertex, both shifts >= 0 and every byte offset below 2^31
+  // (sample8_fast: 32-bit offsets from the grid base)
+  int fast8;
   int64_t level_offset[NTBC_MAX_LEVELS + 1];
 };
 
@@ -139,6 +142,27 @@ __device__ __forceinline__ void sample(const GridView& g, int level, int f0, int
   }
 }
 
+// sample<8> for a fast8 grid: the same corners and blend, with 32-bit byte offsets from the grid base
+// (a scalar base plus a per-lane offset in the loads instead of 64-bit per-lane addresses).
+__device__ __forceinline__ void sample8_fast(const GridView& g, int level, int bx, int by, float out[8]) {
+  const int res = g.base_res << level;
+  const Corner cx = corner_pow2(bx, g.blocks_w, res, g.shift_x);
+  const Corner cy = corner_pow2(by, g.blocks_h, res, g.shift_y);
+  const uint32_t o00 = ((uint32_t)g.level_offset[level] + (uint32_t)(cy.i0 * res + cx.i0)) * 8u;
+  const uint32_t row = 8u * (uint32_t)res;
+  const float w00 = (1.0f - cx.f) * (1.0f - cy.f), w10 = cx.f * (1.0f - cy.f);
+  const float w01 = (1.0f - cx.f) * cy.f, w11 = cx.f * cy.f;
+  float a[8], b[8], c[8], d[8];
+  load_u8<8>(g.u8 + o00, a);
+  load_u8<8>(g.u8 + (o00 + 8u), b);
+  load_u8<8>(g.u8 + (o00 + row), c);
+  load_u8<8>(g.u8 + (o00 + row + 8u), d);
+  const float s = g.scale[level];
+  const float sz = -s * (float)g.zero[level];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) out[m] = fmaf(s, fmaf(w00, a[m], fmaf(w10, b[m], fmaf(w01, c[m], w11 * d[m]))), sz);
+}
+
 // Input features c0 .. c0+NV-1 of the concatenation [level 0 features, level 1 features, ...], zero
 // past in_dim.  NV is 8 (BF16/FP8 operands) or 1 (FP32 operands); n_features is 1, 2, 4, 8 or 16.
 template <int NV>
@@ -157,6 +181,10 @@ __device__ __forceinline__ void features(const GridView& g, int c0, int bx, int 
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = 0.0f;
     if (c0 >= in_dim) return;
+    if (g.fast8) {
+      sample8_fast(g, c0 / 8, bx, by, v);
+      return;
+    }
     switch (g.n_features) {
       case 16:
         sample<8>(g, c0 / 16, c0 % 16, bx, by, v);

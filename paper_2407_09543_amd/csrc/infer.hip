@@ -1236,6 +1236,8 @@ InferArgs infer_args(const Plan& p, const ntbc_model_desc* d, const ntbc_params*
   };
   a.grid.shift_x = pow2_shift(s.blocks_w);
   a.grid.shift_y = pow2_shift(s.blocks_h);
+  a.grid.fast8 = a.grid.u8 != nullptr && s.n_features == 8 && a.grid.shift_x >= 0 && a.grid.shift_y >= 0 &&
+                 s.level_offset[s.n_levels] * 8 < (1ll << 31);
   for (int k = 0; k < s.n_layers; ++k) {
     a.pack_off[k] = p.pack_off[k];
     a.bias_off[k] = p.bias_off[k];
