@@ -91,7 +91,8 @@ def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
 
 def traffic_from_profile(path, kernel_src):
     """HBM bytes per launch of the inference kernel from a committed counter summary, or None if the
-    summary is missing or was taken on a different kernel source (its sha256 is recorded in it)."""
+    summary is missing or was taken on a different kernel source (the sha256 of the kernel's source
+    files, concatenated in order, is recorded in it)."""
     import hashlib
     if not os.path.exists(path):
         return None
@@ -101,8 +102,11 @@ def traffic_from_profile(path, kernel_src):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    with open(kernel_src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for src in kernel_src:  # the kernel's sources, in order
+        with open(src, "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
     if fields.get("kernel_source_sha256") != digest or "hbm_bytes_per_launch" not in fields:
         return None
     return float(fields["hbm_bytes_per_launch"])
@@ -351,7 +355,8 @@ def main():
     flop = flops_per_position(cfg) * cfg.n_positions
     achieved = flop / (ms_bf * 1e-3) / 1e12
     traffic = traffic_from_profile(os.path.join(ROOT, "profiles", "k_infer_lds_bf16_4096_five_texture_traffic.txt"),
-                                   os.path.join(ROOT, "paper_2407_09543_amd", "csrc", "infer.hip"))
+                                   [os.path.join(ROOT, "paper_2407_09543_amd", "csrc", f)
+                                    for f in ("infer.hip", "device.h")])
     result = {
         "metric": METRIC,
         "value": n_blocks / (ms_bf * 1e-3),

@@ -1163,7 +1163,7 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
   while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * 4 <= 48 * 1024) ++n_coarse;
   if (n_coarse > 0) {
     const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * sizeof(float);
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 128));
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 512));
     hipLaunchKernelGGL(k_scatter_coarse, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dz, d_grid, n_coarse);
   }
   if (n_coarse < s.n_levels)
