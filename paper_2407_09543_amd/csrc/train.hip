@@ -536,21 +536,27 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   for (int j = 0; j < 2; ++j) {
     const int n = n0 + wn * 64 + 32 * j + li;
     if (n >= g.N) continue;
+    // the lane's column: its bias read once, rows addressed from one base with 32-bit row offsets
+    const float bn = (EPI == EPI_BIAS_RELU || EPI == EPI_BIAS_SIGMOID) ? g.bias[n] : 0.0f;
+    const int mb = m0 + wm * 64 + 4 * lg;
+    float* __restrict__ cb = g.c + (int64_t)mb * g.ldc + n;
+    const float* __restrict__ kb = EPI == EPI_MASK ? g.mask + (int64_t)mb * g.ldm + n : nullptr;
+    const int ldc = (int)g.ldc, ldm = (int)g.ldm;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int m = m0 + wm * 64 + 32 * i + 8 * (v / 4) + 4 * lg + (v % 4);
-        if (m >= g.M) continue;
+        const int dm = 32 * i + 8 * (v / 4) + (v % 4);
+        if (mb + dm >= g.M) continue;
         const float val = acc[i][j][v];
-        float* out = g.c + (int64_t)m * g.ldc + n;
+        float* out = cb + dm * ldc;
         if (EPI == EPI_BIAS_RELU) {
-          const float z = val + g.bias[n];
+          const float z = val + bn;
           *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
         } else if (EPI == EPI_BIAS_SIGMOID) {
-          *out = 1.0f / (1.0f + expf(-(val + g.bias[n])));
+          *out = 1.0f / (1.0f + expf(-(val + bn)));
         } else if (EPI == EPI_MASK) {
-          *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? val : 0.0f;
+          *out = kb[dm * ldm] > 0.0f ? val : 0.0f;
         } else if (EPI == EPI_ATOMIC) {
           atomicAdd(out, val);
         } else {
