@@ -112,6 +112,8 @@ def test_paper_scale_sampled(precision):
     log(f"paper scale infer precision {precision}")
     words, heads = m.infer(precision, heads=True)
     torch.cuda.synchronize()
+    # the timed launch writes no heads: its blocks must be the same
+    assert torch.equal(m.infer(precision, reuse_packed=True), words)
     ids = np.sort(np.random.default_rng(9).choice(cfg.n_positions, 3000, replace=False))
     ids = np.concatenate([ids, [0, cfg.n_positions - 1]])
     idt = torch.from_numpy(ids).cuda()
