@@ -126,3 +126,19 @@ def test_batch_graph_replay():
         for o, e in zip(batch.outputs, eager):
             assert torch.equal(o, e), f"replay {rep}"
         _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_fp8_batch_equals_single_launches():
+    # FP8 E4M3 with each model's calibrated per-layer scales: the batch (staged epilogue for every
+    # item) equals the single-range launches (register epilogue where an instance exists)
+    mats = _materials()
+    for _, _, _, model in mats:
+        model.fp8_calibrate(4096)
+    entries, meta = _entries(mats)
+    batch = ntbc.Batch(entries, ntbc.FP8_E4M3)
+    outs = batch.run()
+    torch.cuda.synchronize()
+    for (model, d, first, n), out, (k, level) in zip(entries, outs, meta):
+        single = ntbc.Model(d, model.weights, model.grid, model.grid_scale, model.grid_zero)
+        single.fp8_scales = model.fp8_scales
+        assert torch.equal(out, single.infer(ntbc.FP8_E4M3, first_block=first, n_blocks=n)), f"material {k} level {level}"
