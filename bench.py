@@ -295,6 +295,9 @@ def main():
             "includes": "reference encode of the targets, all training steps, grid quantisation, BF16 "
                         "inference, per-block judge; textures already in HBM",
             "psnr_db_ntbc": ntbc_psnr, "psnr_db_after_judge": judged_psnr, "psnr_db_ref_encoder": ref_psnr,
+            "ssim_central_1024": {"ntbc": encode.ssim_of_words(res.ntbc_words, tex, cfg.formats, args.size),
+                                  "after_judge": encode.ssim_of_words(res.words, tex, cfg.formats, args.size),
+                                  "ref_encoder": encode.ssim_of_words(torch.stack(ref), tex, cfg.formats, args.size)},
             "judge": {"kappa": args.kappa, "delta": 0.0, "fallback_blocks": res.fallback_blocks},
             "model_bytes_bf16_weights": encode.model_bytes(cfg, 2), "bc_bytes": bc_bytes,
             "storage_matched_baseline": {"what": "reference BC of the 2x2-averaged texture, nearest upsampled",

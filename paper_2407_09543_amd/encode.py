@@ -95,6 +95,22 @@ def psnr_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats
     return out
 
 
+def ssim_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats, size: int,
+                  crop: int = 1024) -> List[float]:
+    """Decoded SSIM of every texture's blocks against its uncompressed texels, on the central
+    crop x crop texels (SSIM on the host; the crop bounds its cost)."""
+    from . import quality
+    crop = min(crop, size)
+    c0 = (size - crop) // 2
+    out = []
+    for w, t, f in zip(words, textures, formats):
+        dec = ntbc.decode(w.contiguous(), size, size, f).reshape(size, size, -1)
+        ref = t.reshape(size, size, -1)
+        out.append(quality.ssim(dec[c0:c0 + crop, c0:c0 + crop].cpu().numpy(),
+                                ref[c0:c0 + crop, c0:c0 + crop].cpu().numpy()))
+    return out
+
+
 def model_bytes(cfg, weight_bytes: int = 2) -> int:
     """Stored size: uint8 grid + per-level (scale, zero) + weights at `weight_bytes` each."""
     return cfg.grid_vertices * cfg.n_features + 8 * cfg.n_levels + cfg.n_weights * weight_bytes
