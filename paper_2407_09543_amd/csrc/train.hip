@@ -839,28 +839,27 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
   }
 }
 
-// Four lanes per (texture, position), texture-major so that a wave works on one format.  A grid-
-// stride loop over whole waves keeps the shuffles uniform; the loss sums are reduced per block and
-// added with one atomic per block and loss (same-address atomics from every wave serialise in L2).
-constexpr int kLossBlocks = 768;  // about one resident round at three waves per SIMD
+// Four lanes per (texture, position).  A block has one wave per texture (so a wave works on one
+// format) and covers 16 positions at a time: the waves of a block read the same rows of the heads and
+// write the same rows of their gradient at about the same time, so those rows pass through L2 once
+// instead of once per texture.  A grid-stride loop over groups of 16 positions keeps the shuffles
+// uniform; the loss sums are reduced per block and added with one atomic per block and loss
+// (same-address atomics from every wave serialise in L2).
+constexpr int kLossBlocks = 1024;  // about two resident rounds of five-wave blocks
 
-__global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
-  __shared__ float part[kBlock / 64][4];
-  __shared__ int part_bad[kBlock / 64];
+__global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a) {
+  __shared__ float part[NTBC_MAX_TEXTURES][4];
+  __shared__ int part_bad[NTBC_MAX_TEXTURES];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t per_tex = 4 * a.n;
-  const int64_t total = per_tex * a.n_textures;
+  const int t = wave;  // the block has a.n_textures waves
+  const int64_t groups = (a.n + 15) / 16;
   float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
   bool bad = false;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < total;
-       base += (int64_t)gridDim.x * kBlock) {
-    const int64_t gid = base + lane;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
-    const bool active = gid < total;
-    const int t = active ? (int)(gid / per_tex) : 0;
-    const int64_t r = gid - (int64_t)t * per_tex;
-    const int64_t p = r >> 2;
-    const int sub = (int)(r & 3);
+    const int64_t p = grp * 16 + (lane >> 2);
+    const int sub = lane & 3;
+    const bool active = p < a.n;
     if (active) {
       const int id = clamp_id(a.ids[p], a.n_positions);
       if (a.formats[t] == NTBC_BC1)
@@ -868,8 +867,7 @@ __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
       else
         texture_loss<1>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
     }
-    // combine the endpoint gradients of the four lanes (per_tex is a multiple of 4, so the four
-    // lanes of a (texture, position) sit in one aligned group of the wave)
+    // combine the endpoint gradients of the four lanes of a position (an aligned group of the wave)
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
 #pragma unroll
@@ -908,14 +906,15 @@ __global__ void __launch_bounds__(kBlock) k_loss_grad(LossArgs a) {
     part_bad[wave] = anybad != 0;
   }
   __syncthreads();
+  const int n_waves = (int)(blockDim.x / 64);
   if (threadIdx.x < 4) {
     float s = 0.0f;
-    for (int w = 0; w < kBlock / 64; ++w) s += part[w][threadIdx.x];
+    for (int w = 0; w < n_waves; ++w) s += part[w][threadIdx.x];
     const float scale = threadIdx.x == 0 ? a.inv_ne : a.inv_nc;
     atomicAdd(&a.losses[threadIdx.x], s * scale);
   } else if (threadIdx.x == 4) {
     int any = 0;
-    for (int w = 0; w < kBlock / 64; ++w) any |= part_bad[w];
+    for (int w = 0; w < n_waves; ++w) any |= part_bad[w];
     if (any) atomicExch(&a.losses[4], 1.0f);
   }
 }
@@ -1210,8 +1209,8 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   a.inv_ne = (float)(1.0 / ((double)n * s.endpoint_dim));
   a.inv_nc = (float)(1.0 / ((double)n * 16.0 * s.channels));
   a.losses = losses;
-  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)std::min<int64_t>(ceil_div(4 * n * s.n_textures, kBlock), kLossBlocks)),
-                     dim3(kBlock), 0, strm, a);
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks))),
+                     dim3(64 * s.n_textures), 0, strm, a);
   return check_launch("k_loss_grad");
 }
 
