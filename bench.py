@@ -379,7 +379,10 @@ def main():
                    "grid": "8 levels 8..1024 x 8 uint8", "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                     "kernel": "k_infer_lds<BF16,256,4,2,2,3>", "flop_per_launch": flop},
+                     "kernel": "k_infer_lds<BF16,256,4,2,2,3>", "flop_per_launch": flop,
+                     "note": "priced against the BF16 matrix-core peak; the kernel is limited by its vector-ALU "
+                             "work (exact float32 nearest-palette searches, sigmoid, grid gather): "
+                             "profiles/k_infer_lds_bf16_4096_five_texture_counters.txt"},
         "fp32": {"blocks_per_s": n_blocks / (ms_fp * 1e-3), "ms_per_step": ms_fp,
                  "tflops": flop / (ms_fp * 1e-3) / 1e12, "frac_fp32_peak": flop / (ms_fp * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
         "speedup_bf16_vs_fp32": ms_fp / ms_bf,
