@@ -225,7 +225,8 @@ typedef struct {
 
 /* Hyper-parameters (host struct).  Paper Sec. 3.4: Adam beta1 0.9, beta2 0.999, eps 1e-15; learning
  * rates 0.01 (grid) and 0.005 (MLP); 10 warm-up steps then cosine annealing to 0 at total_steps;
- * T = 0.01.  Sec. 3.3: qat = 1 fake-quantises every grid level to 8 bits with its current min/max. */
+ * T = 0.01.  Sec. 3.3: qat = 1 fake-quantises every grid level to 8 bits with its current min/max (the range
+ * widened to contain 0, as for ntbc_quantize_grid). */
 typedef struct {
   float lr_grid, lr_mlp;
   float beta1, beta2, eps;
@@ -285,8 +286,10 @@ int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const 
 int ntbc_batch_ids(uint64_t seed, int64_t step, int32_t batch, int64_t n_positions, int32_t* ids_out,
                    void* stream);
 
-/* 8-bit grid for inference (Sec. 3.3): per level l, s_l = (max-min)/255 and z_l = clamp(rne(-min/s_l),
- * 0, 255) (s = 1, z = 0 for a flat level), codes q = clamp(rne(g/s_l) + z_l, 0, 255); all in float32.
+/* 8-bit grid for inference (Sec. 3.3): per level l, over the level's range widened to contain 0 (Sec.
+ * 2.3: the zero point makes real 0 an exact code) lo = min(min, 0), hi = max(max, 0): s_l = (hi-lo)/255
+ * and z_l = clamp(rne(-lo/s_l), 0, 255) (s = 1, z = 0 for an all-zero level), codes q = clamp(rne(g/s_l)
+ * + z_l, 0, 255); all in float32.  The same (s, z) drive the fake quantisation of training (qat = 1).
  * codes: uint8[V][F]; scale: float[n_levels]; zero: int32[n_levels]. */
 int ntbc_quantize_grid(const ntbc_model_desc* d, const float* grid, uint8_t* codes, float* scale,
                        int32_t* zero, void* workspace, size_t workspace_bytes, void* stream);

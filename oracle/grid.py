@@ -17,6 +17,10 @@ Readings where the paper is silent or garbled:
   * Storage: level-major, then row-major vertex index j*res + i (j = y), then feature.
   * Zero point: the printed z = round(alpha * s) is dimensionally wrong; the zero point that makes
     real 0 representable is z = clamp(round(-alpha / s), 0, 255).
+  * Range: the zero point exists so that real 0 is an exact code (Sec. 2.3), which needs alpha <= 0 <=
+    beta; a level whose values all share one sign has its range widened to include 0 (alpha = min(min,
+    0), beta = max(max, 0)), so every value of the level stays inside [alpha, beta] and none is
+    clamped.
   * The quantiser's gradient is 1 where the value is not clamped and 0 where it is (the printed
     "w" is read as 1); alpha and beta carry no gradient.
   * The half-way rounding is round-half-to-even.  s and z, and every code, are computed in float32
@@ -107,10 +111,11 @@ def split_levels(grid, n_levels: int, base_res: int):
 # 8-bit quantisation
 # ------------------------------------------------------------------------------------------------
 def qat_params(level_values):
-    """(s, z) of one level from its real values: s float32, z int (float32 arithmetic)."""
+    """(s, z) of one level from its real values: s float32, z int (float32 arithmetic), over the
+    level's range widened to include 0."""
     v = np.asarray(level_values, dtype=np.float32)
-    lo = np.float32(v.min())
-    hi = np.float32(v.max())
+    lo = min(np.float32(v.min()), np.float32(0.0))
+    hi = max(np.float32(v.max()), np.float32(0.0))
     if hi == lo:
         return np.float32(1.0), 0
     s = np.float32(np.float32(hi - lo) / np.float32(255.0))

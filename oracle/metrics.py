@@ -7,8 +7,10 @@ Tie classification of a block that differs between an implementation under test 
 block is a quantisation-boundary tie when (1) packing the implementation's own head values with the
 oracle's float32 packer reproduces its word bit for bit, and (2) the oracle's smallest decision margin
 for that block (distance of an endpoint value to its rounding boundary, in y units; gap between the two
-nearest squared palette distances) is within what the head difference d = |Y_impl - Y_oracle|_inf of
-the block, plus the implementation's float32 rounding of the decision itself, can move it:
+nearest squared palette distances) is within what the head difference d of the block, plus the
+implementation's float32 rounding of the decision itself, can move it.  d = |Y_impl - Y_oracle|_inf
+over the heads that decide this texture's word only (its endpoint values and its 16 predicted
+colours), so a large difference in another texture's heads explains nothing here:
   * endpoint: d + 1.25e-7.  The implementation decides floor(fl(fl(y*m) + 0.5)) in float32; both
     roundings together move y*m by at most one ulp of values below m+1, i.e. 2^-23 * 2^ceil(log2(m+1)),
     which is < 1.25e-7 * m for m = 31, 63, 255;
@@ -36,16 +38,31 @@ def identity(words_a, words_b):
     return float((a == b).mean())
 
 
-def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
+def texture_head_difference(abs_diff, lay, t):
+    """Per block, the largest |difference| among the heads that decide texture t's word: its endpoint
+    values (6 for BC1, 2 for BC4) and its 16 x channels predicted colours.  abs_diff: [n, H]."""
+    e = lay.ep_off[t]
+    n_ep = 6 if lay.formats[t] == ntbc.BC1 else 2
+    cols = lay.colour_index(t).ravel()
+    sel = np.concatenate([np.arange(e, e + n_ep), cols])
+    return abs_diff[:, sel].max(axis=1) if len(abs_diff) else np.zeros(0)
+
+
+def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats, endpoint_slack=1.25e-7,
+                         index_factor=2.0, index_slack=2e-6):
     """Per texture: number of differing blocks and how many of them are boundary ties.
 
+    The allowances are those derived above (a block is a tie when its endpoint margin is at most
+    d + endpoint_slack, or its index gap at most index_factor * ch * d + index_slack); they are
+    arguments only so that a test can show that a wrong constant changes a verdict.
     Returns dict with 'differ', 'ties', 'repack_exact' (condition 1 over all blocks)."""
     lay = ntbc.Layout(formats)
     Y_impl = np.asarray(Y_impl)
-    dy = np.abs(Y_impl.astype(np.float64) - Y_oracle).max(axis=1)
-    out = {"differ": 0, "ties": 0, "repack_exact": True, "max_dy": float(dy.max()) if len(dy) else 0.0,
-           "non_ties": []}
+    diff_all = np.abs(Y_impl.astype(np.float64) - np.asarray(Y_oracle, dtype=np.float64))
+    out = {"differ": 0, "ties": 0, "repack_exact": True,
+           "max_dy": float(diff_all.max()) if diff_all.size else 0.0, "non_ties": []}
     for t in range(len(lay.formats)):
+        dy = texture_head_difference(diff_all, lay, t)
         repacked = ntbc.pack_texture(Y_impl, lay, t, "f32")
         if not np.array_equal(repacked, words_impl[t]):
             out["repack_exact"] = False
@@ -54,7 +71,7 @@ def classify_differences(Y_impl, words_impl, Y_oracle, words_oracle, formats):
             continue
         _, ep_m, idx_m = ntbc.pack_texture(Y_oracle[diff], lay, t, "f64", return_margin=True)
         ch = lay.channels(t)
-        tie = (ep_m <= dy[diff] + 1.25e-7) | (idx_m <= 2.0 * ch * dy[diff] + 2e-6)
+        tie = (ep_m <= dy[diff] + endpoint_slack) | (idx_m <= index_factor * ch * dy[diff] + index_slack)
         out["differ"] += int(diff.sum())
         out["ties"] += int(tie.sum())
         idx = np.nonzero(diff)[0]

@@ -124,11 +124,13 @@ __global__ void __launch_bounds__(kBlock) k_level_minmax(MinMaxArgs a, int* __re
   }
 }
 
-// (s, z) of every level in float32: s = (max-min)/255, z = clamp(rne(-min/s), 0, 255); flat: s=1, z=0.
+// (s, z) of every level in float32 over the level's range widened to contain 0 (the zero point makes
+// real 0 an exact code, Sec. 2.3): lo = min(min, 0), hi = max(max, 0), s = (hi-lo)/255,
+// z = clamp(rne(-lo/s), 0, 255); an all-zero level: s = 1, z = 0.
 __global__ void k_qat_params(int* __restrict__ stats, int n_levels) {
   const int l = threadIdx.x;
   if (l >= n_levels) return;
-  const float lo = unordered(stats[l]), hi = unordered(stats[NTBC_MAX_LEVELS + l]);
+  const float lo = fminf(unordered(stats[l]), 0.0f), hi = fmaxf(unordered(stats[NTBC_MAX_LEVELS + l]), 0.0f);
   float s = 1.0f, z = 0.0f;
   if (hi != lo) {
     s = __fdiv_rn(__fsub_rn(hi, lo), 255.0f);

@@ -1,6 +1,7 @@
 """Pins of the grid oracle: closed forms of the bilinear sampling, the adjoint of the scatter, the
 8-bit quantiser identities, and the paper's printed storage sizes (no GPU)."""
 import numpy as np
+import pytest
 
 from conftest import read_golden
 from oracle import grid as G
@@ -77,14 +78,32 @@ def test_quantiser_identities():
             assert zero[0] == 0.0                           # real zero is representable
         _, codes = G.quant_codes(w, s, z)
         assert codes.min() <= 1 and codes.max() >= 254      # the range spans the 8-bit codes
-    # a flat level: s = 1, z = 0
-    s, z = G.qat_params(np.full(10, 0.25, np.float32))
+    # a flat level (every value 0, so the range widened to contain 0 is empty): s = 1, z = 0
+    s, z = G.qat_params(np.zeros(10, np.float32))
     assert float(s) == 1.0 and z == 0
     # clamped values get no gradient
     w = np.array([-1.0, 0.0, 1.0], np.float32)
     s, z = G.qat_params(w)
     _, mask = G.fake_quant(np.array([-3.0, 0.5, 3.0], np.float32), s, z)
     assert mask.tolist() == [0.0, 1.0, 0.0]
+
+
+@pytest.mark.parametrize("lo,hi", [(0.5, 2.0), (-3.0, -1.0), (0.25, 0.25)])
+def test_one_signed_level_keeps_its_range(lo, hi):
+    # Sec. 2.3: the zero point makes real 0 an exact code, so the range [alpha, beta] must contain 0.
+    # A level whose values all share one sign is quantised over [min(alpha, 0), max(beta, 0)]: for
+    # values in [0.5, 2] that is s = 2/255, z = 0; for [-3, -1] s = 3/255, z = 255.  No value of the
+    # level is clamped and every one is within s/2 of its quantised value.
+    w = np.linspace(lo, hi, 257).astype(np.float32)
+    s, z = G.qat_params(w)
+    span = max(hi, 0.0) - min(lo, 0.0)
+    assert float(s) == pytest.approx(span / 255.0, rel=1e-6)
+    assert z == (0 if lo >= 0 else 255)
+    q, mask = G.fake_quant(w, s, z)
+    assert mask.all()
+    assert np.abs(q - w.astype(np.float64)).max() <= float(s) / 2 * (1 + 1e-5)
+    zero, _ = G.fake_quant(np.zeros(1, np.float32), s, z)
+    assert zero[0] == 0.0
 
 
 def test_storage_matches_paper():
