@@ -16,7 +16,10 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libntbc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "codec.hip", "infer.hip", "train.hip"]
+# (source, object, extra flags): infer.hip compiles in parts (its NTBC_INFER_PART macro) so that its
+# many kernel instances build in parallel
+SOURCES = [("api.cpp", "api.o", []), ("codec.hip", "codec.o", []), ("train.hip", "train.o", [])] + [
+    ("infer.hip", f"infer_p{k}.o", [f"-DNTBC_INFER_PART={k}"]) for k in range(7)]
 
 # Packed FP32 instructions are disabled (-packed-fp32-ops); contraction of a*b+c into FMA is disabled so
 # that the integer decisions taken in float32 (endpoint rounding, nearest palette entry) are the exact
@@ -26,12 +29,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(unit, verbose: bool) -> str:
+    src, obj, extra = unit
     path = os.path.join(CSRC, src)
-    obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
+    obj = os.path.join(CSRC, obj)
+    cmd = [HIPCC] + FLAGS + extra + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, "-x", "hip"] + FLAGS + ["-c", path, "-o", obj]
+        cmd = [HIPCC, "-x", "hip"] + FLAGS + extra + ["-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -40,7 +44,8 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     # the translation units compile in parallel (one compiler process each)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
         objs = list(pool.map(lambda src: _compile(src, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

@@ -27,6 +27,15 @@
 #include "common.h"
 #include "device.h"
 
+// The build compiles this file once per part so that the many kernel instances compile in parallel:
+// NTBC_INFER_PART = 0 holds the host code, the FP32 kernels and the weight packing, 1-3 the
+// single-range 16-bit/FP8 instances (BF16, FP16, FP8), 4-6 the batched ones.  Without the macro one
+// translation unit holds everything.
+#ifndef NTBC_INFER_PART
+#define NTBC_INFER_PART -1
+#endif
+#define NTBC_PART(k) (NTBC_INFER_PART < 0 || NTBC_INFER_PART == (k))
+
 namespace {
 
 using namespace ntbc;
@@ -1104,6 +1113,119 @@ int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTabl
   return NTBC_OK;
 }
 
+}  // namespace
+
+// ------------------------------------------------------------------------------ kernel instances
+// The fused 16-bit/FP8 kernels exist per (precision, hidden width, first-layer K-steps, unrolled
+// middle layers, register-epilogue texture mix); the host code finds one through these lookups, each
+// defined in the part that compiles its instances.
+namespace ntbc {
+typedef void (*LdsLaunch)(dim3, dim3, size_t, hipStream_t, const void* args, const void* chunks);
+typedef void (*BatchLaunch)(dim3, dim3, size_t, hipStream_t, const void* items, int n_items, unsigned* done,
+                            uint64_t* stamps);
+bool lds_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
+bool lds_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
+bool lds_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
+bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
+bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
+bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
+}  // namespace ntbc
+
+// Single-range instances: every precision at widths 64/128/256 with one to four input K-steps and a
+// run-time layer count, the two-middle-layer shapes (128, 3) and (256, 4) unrolled, with the LDS-staged
+// epilogue and with the register epilogue for two BC1 + three BC4 textures.
+#define NTBC_LDS_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                          \
+  if (hid == H && ks0 == K && nh == NH && nb1 == NB1 && (NB1 < 0 || nb4 == NB4)) {                         \
+    *fn = (const void*)k_infer_lds<LP, H, K, NH, NB1, NB4>;                                                  \
+    *launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const void* x, const void* y) {               \
+      hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH, NB1, NB4>), gr, bl, sh, st,                             \
+                         *static_cast<const InferArgs*>(x), *static_cast<const ChunkTable*>(y));            \
+    };                                                                                                       \
+    return true;                                                                                             \
+  }
+#define NTBC_LDS_INSTANCES(LP)                                                                                    \
+  NTBC_LDS_INSTANCE_L(LP, 64, 1, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 64, 2, -1, -1, 0)                            \
+  NTBC_LDS_INSTANCE_L(LP, 64, 3, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 64, 4, -1, -1, 0)                            \
+  NTBC_LDS_INSTANCE_L(LP, 128, 1, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 128, 2, -1, -1, 0)                          \
+  NTBC_LDS_INSTANCE_L(LP, 128, 3, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 128, 4, -1, -1, 0)                          \
+  NTBC_LDS_INSTANCE_L(LP, 256, 1, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 256, 2, -1, -1, 0)                          \
+  NTBC_LDS_INSTANCE_L(LP, 256, 3, -1, -1, 0) NTBC_LDS_INSTANCE_L(LP, 256, 4, -1, -1, 0)                          \
+  NTBC_LDS_INSTANCE_L(LP, 128, 3, 2, -1, 0) NTBC_LDS_INSTANCE_L(LP, 256, 4, 2, -1, 0)                            \
+  NTBC_LDS_INSTANCE_L(LP, 128, 3, 2, 2, 3) NTBC_LDS_INSTANCE_L(LP, 256, 4, 2, 2, 3)
+
+// Batched instances: the same shapes with the LDS-staged epilogue in every precision, and BF16 with the
+// register epilogue for two BC1 + one to three BC4 textures at widths 64, 128 (run-time layer count)
+// and 256 (two middle layers unrolled).
+#define NTBC_BATCH_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                         \
+  if (hid == H && ks0 == K && nh == NH && nb1 == NB1 && (NB1 < 0 || nb4 == NB4)) {                         \
+    *fn = (const void*)k_infer_lds_batch<LP, H, K, NH, NB1, NB4>;                                            \
+    *launch = [](dim3 g, dim3 b, size_t sh, hipStream_t st, const void* it, int n, unsigned* d, uint64_t* s) { \
+      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH, NB1, NB4>), g, b, sh, st,                         \
+                         static_cast<const BatchItem*>(it), n, d, s);                                        \
+    };                                                                                                       \
+    return true;                                                                                             \
+  }
+#define NTBC_BATCH_INSTANCES(LP)                                                                                    \
+  NTBC_BATCH_INSTANCE_L(LP, 64, 1, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 64, 2, -1, -1, 0)                          \
+  NTBC_BATCH_INSTANCE_L(LP, 64, 3, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 64, 4, -1, -1, 0)                          \
+  NTBC_BATCH_INSTANCE_L(LP, 128, 1, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 128, 2, -1, -1, 0)                        \
+  NTBC_BATCH_INSTANCE_L(LP, 128, 3, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 128, 4, -1, -1, 0)                        \
+  NTBC_BATCH_INSTANCE_L(LP, 256, 1, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 256, 2, -1, -1, 0)                        \
+  NTBC_BATCH_INSTANCE_L(LP, 256, 3, -1, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 256, 4, -1, -1, 0)                        \
+  NTBC_BATCH_INSTANCE_L(LP, 128, 3, 2, -1, 0) NTBC_BATCH_INSTANCE_L(LP, 256, 4, 2, -1, 0)
+#define NTBC_BATCH_REG(H, K, NH)                                                                                \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 1) NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 2)                 \
+  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 3)
+
+namespace ntbc {
+#if NTBC_PART(1)
+bool lds_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch) {
+  NTBC_LDS_INSTANCES(Lp::BF16)
+  return false;
+}
+#endif
+#if NTBC_PART(2)
+bool lds_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch) {
+  NTBC_LDS_INSTANCES(Lp::FP16)
+  return false;
+}
+#endif
+#if NTBC_PART(3)
+bool lds_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch) {
+  NTBC_LDS_INSTANCES(Lp::FP8)
+  return false;
+}
+#endif
+#if NTBC_PART(4)
+bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
+  NTBC_BATCH_INSTANCES(Lp::BF16)
+  NTBC_BATCH_REG(64, 4, -1) NTBC_BATCH_REG(128, 4, -1) NTBC_BATCH_REG(256, 4, 2)
+  return false;
+}
+#endif
+#if NTBC_PART(5)
+bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
+  NTBC_BATCH_INSTANCES(Lp::FP16)
+  return false;
+}
+#endif
+#if NTBC_PART(6)
+bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
+  NTBC_BATCH_INSTANCES(Lp::FP8)
+  return false;
+}
+#endif
+}  // namespace ntbc
+#undef NTBC_LDS_INSTANCE_L
+#undef NTBC_LDS_INSTANCES
+#undef NTBC_BATCH_INSTANCE_L
+#undef NTBC_BATCH_INSTANCES
+#undef NTBC_BATCH_REG
+
+// ------------------------------------------------------------------------------ host code (part 0)
+#if NTBC_PART(0)
+namespace {
+
 struct BatchGroup {
   int32_t lp, hid, ks0, nh, nb1, nb4;
   int32_t item_begin, item_end;
@@ -1120,29 +1242,12 @@ int batch_nh(const Plan& p) {
 
 int launch_batch_group(const BatchGroup& gr, const BatchItem* items, unsigned* done, uint64_t* stamps, hipStream_t strm) {
   const void* fn = nullptr;
-  void (*launch)(dim3, dim3, size_t, hipStream_t, const BatchItem*, int, unsigned*, uint64_t*) = nullptr;
-  const Lp want = gr.lp == NTBC_FP8_E4M3 ? Lp::FP8 : (gr.lp == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
-#define NTBC_BATCH_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                 \
-  if (gr.hid == H && gr.ks0 == K && gr.nh == NH && want == LP && gr.nb1 == NB1 && (NB1 < 0 || gr.nb4 == NB4)) { \
-    fn = (const void*)k_infer_lds_batch<LP, H, K, NH, NB1, NB4>;                                     \
-    launch = [](dim3 g, dim3 b, size_t sh, hipStream_t st, const BatchItem* it, int n, unsigned* d, uint64_t* s) { \
-      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH, NB1, NB4>), g, b, sh, st, it, n, d, s);    \
-    };                                                                                                 \
-  }
-#define NTBC_BATCH_INSTANCE(H, K, NH)                                                        \
-  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, -1, 0) NTBC_BATCH_INSTANCE_L(Lp::FP16, H, K, NH, -1, 0) \
-  NTBC_BATCH_INSTANCE_L(Lp::FP8, H, K, NH, -1, 0)
-#define NTBC_BATCH_REG(H, K, NH)                                                                 \
-  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 1) NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 2) \
-  NTBC_BATCH_INSTANCE_L(Lp::BF16, H, K, NH, 2, 3)
-  NTBC_BATCH_INSTANCE(64, 1, -1) NTBC_BATCH_INSTANCE(64, 2, -1) NTBC_BATCH_INSTANCE(64, 3, -1) NTBC_BATCH_INSTANCE(64, 4, -1)
-  NTBC_BATCH_INSTANCE(128, 1, -1) NTBC_BATCH_INSTANCE(128, 2, -1) NTBC_BATCH_INSTANCE(128, 3, -1) NTBC_BATCH_INSTANCE(128, 4, -1)
-  NTBC_BATCH_INSTANCE(256, 1, -1) NTBC_BATCH_INSTANCE(256, 2, -1) NTBC_BATCH_INSTANCE(256, 3, -1) NTBC_BATCH_INSTANCE(256, 4, -1)
-  NTBC_BATCH_INSTANCE(128, 3, 2) NTBC_BATCH_INSTANCE(256, 4, 2)
-  NTBC_BATCH_REG(64, 4, -1) NTBC_BATCH_REG(128, 4, -1) NTBC_BATCH_REG(256, 4, 2)
-#undef NTBC_BATCH_REG
-#undef NTBC_BATCH_INSTANCE
-#undef NTBC_BATCH_INSTANCE_L
+  BatchLaunch launch = nullptr;
+  const bool found =
+      gr.lp == NTBC_FP8_E4M3 ? batch_instance_fp8(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch)
+      : gr.lp == NTBC_FP16   ? batch_instance_fp16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch)
+                             : batch_instance_bf16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch);
+  if (!found) fn = nullptr;
   NTBC_REQUIRE(fn != nullptr, "no batch kernel instance for width %d, %d input K-steps", gr.hid, gr.ks0);
   NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gr.lds));
   launch(dim3((unsigned)gr.tiles), dim3(64 * kLdsWaves), (size_t)gr.lds, strm, items + gr.item_begin,
@@ -1358,30 +1463,15 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     if (st != NTBC_OK) return st;
     const int64_t nwg = ceil_div(n_blocks, (int64_t)32 * kLdsWaves);
     const void* fn = nullptr;
-    void (*launch)(dim3, dim3, size_t, hipStream_t, const InferArgs&, const ChunkTable&) = nullptr;
-    const Lp want = fp8 ? Lp::FP8 : (precision == NTBC_FP16 ? Lp::FP16 : Lp::BF16);
+    LdsLaunch launch = nullptr;
     const int nh = batch_nh(p);
-#define NTBC_LDS_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                   \
-    if (p.hid_inst == H && p.ksteps[0] == K && nh == NH && want == LP && rp.nb1 == NB1 && (NB1 < 0 || rp.nb4 == NB4)) { \
-      fn = (const void*)k_infer_lds<LP, H, K, NH, NB1, NB4>;                                         \
-      launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const InferArgs& x, const ChunkTable& y) { \
-        hipLaunchKernelGGL((k_infer_lds<LP, H, K, NH, NB1, NB4>), gr, bl, sh, st, x, y);             \
-      };                                                                                             \
-    }
-#define NTBC_LDS_INSTANCE(H, K, NH, NB1, NB4)                                                                   \
-    NTBC_LDS_INSTANCE_L(Lp::BF16, H, K, NH, NB1, NB4) NTBC_LDS_INSTANCE_L(Lp::FP16, H, K, NH, NB1, NB4) \
-    NTBC_LDS_INSTANCE_L(Lp::FP8, H, K, NH, NB1, NB4)
-    NTBC_LDS_INSTANCE(64, 1, -1, -1, 0) NTBC_LDS_INSTANCE(64, 2, -1, -1, 0) NTBC_LDS_INSTANCE(64, 3, -1, -1, 0)
-    NTBC_LDS_INSTANCE(64, 4, -1, -1, 0) NTBC_LDS_INSTANCE(128, 1, -1, -1, 0) NTBC_LDS_INSTANCE(128, 2, -1, -1, 0)
-    NTBC_LDS_INSTANCE(128, 3, -1, -1, 0) NTBC_LDS_INSTANCE(128, 4, -1, -1, 0) NTBC_LDS_INSTANCE(256, 1, -1, -1, 0)
-    NTBC_LDS_INSTANCE(256, 2, -1, -1, 0) NTBC_LDS_INSTANCE(256, 3, -1, -1, 0) NTBC_LDS_INSTANCE(256, 4, -1, -1, 0)
-    NTBC_LDS_INSTANCE(128, 3, 2, -1, 0) NTBC_LDS_INSTANCE(256, 4, 2, -1, 0) NTBC_LDS_INSTANCE(128, 3, 2, 2, 3)
-    NTBC_LDS_INSTANCE(256, 4, 2, 2, 3)
-#undef NTBC_LDS_INSTANCE
-#undef NTBC_LDS_INSTANCE_L
+    const bool found = fp8 ? lds_instance_fp8(p.hid_inst, p.ksteps[0], nh, rp.nb1, rp.nb4, &fn, &launch)
+                       : precision == NTBC_FP16 ? lds_instance_fp16(p.hid_inst, p.ksteps[0], nh, rp.nb1, rp.nb4, &fn, &launch)
+                                                : lds_instance_bf16(p.hid_inst, p.ksteps[0], nh, rp.nb1, rp.nb4, &fn, &launch);
+    if (!found) fn = nullptr;
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    launch(dim3((unsigned)nwg), dim3(64 * kLdsWaves), lds, strm, a, ct);
+    launch(dim3((unsigned)nwg), dim3(64 * kLdsWaves), lds, strm, &a, &ct);
     return check_launch("ntbc_infer_blocks");
   }
   const int64_t nwg = ceil_div(n_blocks, (int64_t)ppw * kWaves);
@@ -1700,3 +1790,4 @@ extern "C" int ntbc_infer_batch(const void* table, const void* table_device, voi
   }
   return NTBC_OK;
 }
+#endif  // NTBC_PART(0)
