@@ -36,8 +36,8 @@ def flops_per_position(cfg):
 
 
 def psnr(a, b):
-    mse = float(((a.astype(np.float64) - b.astype(np.float64)) ** 2).mean())
-    return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+    from paper_2407_09543_amd import quality
+    return quality.psnr(a, b)
 
 
 def time_call(fn, steps, warmup, torch, settle_s=0.2):
@@ -84,9 +84,40 @@ def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
             break
         n *= 2
     blocks = n * len(cfg.formats)
-    return {"value": blocks / t_used, "unit": "blocks/s", "cores": int(threads), "kind": "oracle",
+    info = {"value": blocks / t_used, "unit": "blocks/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} random block positions of the 4096^2 five-texture material "
                       f"({blocks} BC blocks), FP64 heads + packing, {t_used:.1f} s"}
+    return info, ids, ON.infer_blocks(cfg, levels, layers, ids)[0]
+
+
+def versus_oracle(cfg, mat, outs, ids, words_or, names):
+    """Block identity and decoded-PSNR delta of every precision's blocks against the FP64 oracle's, on
+    the oracle's sample of block positions (all of them when the sample covers the material): PSNR of
+    the sampled blocks' decoded texels against the texture, both sides decoded by the oracle's decoder."""
+    from oracle import bc as OB
+    from paper_2407_09543_amd import quality
+    orig = [OB.image_to_blocks(m.texels)[ids] for m in mat.textures]
+
+    def decode(t, words):
+        return OB.bc1_decode(words) if cfg.formats[t] == 1 else OB.bc4_decode(words)[..., None]
+
+    sse_or = [quality.squared_error(decode(t, words_or[t]), orig[t]) for t in range(len(cfg.formats))]
+    n_vals = [o.size for o in orig]
+    psnr_or = [quality.psnr_from_sse(e, n) for e, n in zip(sse_or, n_vals)]
+    mat_or = quality.psnr_from_sse(sum(sse_or), sum(n_vals))
+    out = {"positions": int(len(ids)), "psnr_db_oracle": psnr_or, "psnr_db_material_oracle": mat_or}
+    for prec, name in names.items():
+        w = outs[prec][:, ids].cpu().numpy().view(np.uint64)
+        sse = [quality.squared_error(decode(t, w[t]), orig[t]) for t in range(len(cfg.formats))]
+        ps = [quality.psnr_from_sse(e, n) for e, n in zip(sse, n_vals)]
+        d = [abs(a - b) if np.isfinite(a) and np.isfinite(b) else (0.0 if a == b else float("inf"))
+             for a, b in zip(ps, psnr_or)]
+        dm = abs(quality.psnr_from_sse(sum(sse), sum(n_vals)) - mat_or)
+        out[name] = {"identity": float((w == words_or).mean()),
+                     "identity_per_texture": [float((w[t] == words_or[t]).mean()) for t in range(len(cfg.formats))],
+                     "dpsnr_db": {"per_texture": d, "max": max(d), "material": dm},
+                     "gate_dpsnr_0p1db": bool(max(d) <= 0.1 and dm <= 0.1)}
+    return out
 
 
 def traffic_from_profile(path, kernel_src):
@@ -248,7 +279,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2407_09543_amd import encode, ntbc, synth
+    from paper_2407_09543_amd import encode, ntbc, quality, synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
@@ -345,13 +376,13 @@ def main():
         psnrs[prec], sq_err[prec] = [], 0.0
         for t, (f, m) in enumerate(zip(cfg.formats, mat.textures)):
             dec = ntbc.decode(words[t].contiguous(), args.size, args.size, f).cpu().numpy()
-            psnrs[prec].append(psnr(dec, m.texels))
-            sq_err[prec] += float(((dec.astype(np.float64) - m.texels.astype(np.float64)) ** 2).sum())
+            e = quality.squared_error(dec, m.texels)
+            psnrs[prec].append(quality.psnr_from_sse(e, m.texels.size))
+            sq_err[prec] += e
     n_values = sum(m.texels.size for m in mat.textures)
 
     def material_psnr(prec):
-        mse = sq_err[prec] / n_values
-        return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+        return quality.psnr_from_sse(sq_err[prec], n_values)
 
     def versus_fp32(prec):
         d = [abs(a - b) for a, b in zip(psnrs[prec], psnrs[ntbc.FP32])]
@@ -419,7 +450,11 @@ def main():
         result["batched_decode"] = batched_decode(torch, ntbc, synth)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(cfg, layers, codes, scale, zero, args.cpu_seconds)
+        result["cpu_baseline"], ids_or, words_or = cpu_baseline(cfg, layers, codes, scale, zero, args.cpu_seconds)
+        log("identity and decoded-PSNR delta of every precision against the FP64 oracle")
+        result["vs_fp64_oracle"] = versus_oracle(
+            cfg, mat, outs, ids_or, words_or,
+            {ntbc.BF16: "bf16", ntbc.FP16: "fp16", ntbc.FP8_E4M3: "fp8_e4m3", ntbc.FP32: "fp32"})
     result["paper_context"] = {
         "hardware": "one Radeon RX 7900 XT, half precision (other GPU, network and material)",
         "inference_ms_six_textures_4096": 27.31, "inference_blocks_per_s": 6291456 / 27.31e-3,

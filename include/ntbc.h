@@ -47,6 +47,8 @@ extern "C" {
 #define NTBC_EINVAL (-1)          /* null pointer, bad size, bad enum, dims not multiples of 4     */
 #define NTBC_EUNSUPPORTED (-2)    /* a valid combination this build does not implement            */
 #define NTBC_EHIP (-3)            /* a HIP runtime error; see ntbc_last_error()                    */
+#define NTBC_ENONFINITE (-4)      /* a training step saw a non-finite loss or gradient and left the
+                                     parameters and moments untouched (ntbc_train_status)             */
 #define NTBC_ENOWORKSPACE (-5)    /* workspace NULL or smaller than ntbc_workspace_size()          */
 
 /* ---- enums ------------------------------------------------------------------------------------- */
@@ -237,6 +239,14 @@ typedef struct {
                                bfloat16 operands on the matrix cores with FP32 accumulation; master
                                parameters, losses, grid scatter and Adam stay FP32                   */
   float loss_weights[4];    /* weights of L_e, L_c, L_cd(endpoint), L_cd(colour) in the gradient; 1 = paper */
+  int32_t deterministic;    /* 0: the grid scatter (and, for shapes outside the fused bfloat16 path, the
+                               split weight products) add with FP32 atomics, so the gradients depend on
+                               their order in the last bits.  1: bitwise repeatable parameters: the grid
+                               gradient is summed as 64-bit fixed-point integers at a per-step power-of-two
+                               scale 2^(61 - ceil(log2(batch * max|dX|))) (order-independent; each term
+                               rounded to that scale, which is far finer than FP32's resolution of the
+                               sums) and every weight product runs unsplit.  The reported losses are
+                               FP32 atomic sums in both modes. */
 } ntbc_hparams;
 
 /* Block ids passed to the training entry points are clamped into [0, blocks_w*blocks_h). */
@@ -252,10 +262,12 @@ int ntbc_forward(const ntbc_model_desc* d, const float* grid, const float* weigh
                  int32_t precision, const int32_t* ids, int32_t n, float* heads_out, void* workspace,
                  size_t workspace_bytes, void* stream);
 
-/* Backward pass: given dL/d(heads) for the same batch, recomputes the forward activations and ADDS the
- * gradients to d_grid ([V][F], scatter through the bilinear weights; with qat = 1 the quantiser's
- * straight-through pass-through: 1 inside the level's range, 0 where clamped) and d_weights (canonical
- * layout).  The caller zeroes them first. */
+/* Backward pass (Sec. 3.2, Fig. NTBC training: the network and the feature grids are learned jointly
+ * by backpropagation; Sec. 2.3 and Sec. 3.3: the quantiser's straight-through estimator under QAT):
+ * given dL/d(heads) for the same batch, recomputes the forward activations and ADDS the gradients to
+ * d_grid ([V][F], scatter through the bilinear weights; with qat = 1 the quantiser's straight-through
+ * pass-through: 1 inside the level's range, 0 where clamped) and d_weights (canonical layout).  The
+ * caller zeroes them first. */
 int ntbc_backward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
                   int32_t precision, const int32_t* ids, int32_t n, const float* d_heads, float* d_grid,
                   float* d_weights, void* workspace, size_t workspace_bytes, void* stream);
@@ -269,13 +281,23 @@ int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float*
                    int32_t n, float temperature, const float* loss_weights, float* losses_out,
                    float* d_heads_out, void* stream);
 
-/* One training iteration: forward, loss, backward, then dense Adam on grid and weights with the
- * learning rates of step `step` (0-based) of the schedule.  losses_out (device float[5]) receives the
+/* One training iteration (Sec. 3.2 training procedure and Eqs. lossNTBC; App. A straight-through
+ * estimator; Sec. 3.3 QAT; Sec. 3.4 Adam, learning rates, warm-up and cosine annealing): forward, loss,
+ * backward, then dense Adam on grid and weights with the learning rates of step `step` (0-based) of the
+ * schedule.  losses_out (device float[5]) receives the
  * four losses and the skip flag: when a non-finite value is seen the parameters and moments are left
  * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions. */
 int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const ntbc_targets* t,
                     const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
                     float* losses_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Outcome of a training step, for callers that want it as a status code: waits for `stream` (the
+ * only synchronising call of the library), reads the skip flag losses_out[4] that ntbc_train_step
+ * wrote on that stream (`losses` = the step's device losses_out) and returns NTBC_ENONFINITE when the
+ * step saw a non-finite loss or gradient (the parameters and Adam moments were left untouched, Sec.
+ * 3.4's update skipped), NTBC_OK otherwise.  The step itself stays asynchronous: a caller may also read
+ * the flag later, or never. */
+int ntbc_train_status(const float* losses, void* stream);
 
 /* Training batch `step`: `batch` block-position ids drawn uniformly with replacement from
  * [0, n_positions) (the paper leaves the sampling unspecified).  Generator: SplitMix64 (Steele, Lea &

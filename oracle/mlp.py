@@ -67,16 +67,27 @@ def forward(layers, x, precision: str = "f64", scales=None):
     return h, (hs, zs)
 
 
-def backward(layers, cache, d_y, y):
-    """Gradients (dW list, db list, dx) of a scalar loss given dL/dY (float64)."""
+def backward(layers, cache, d_y, y, precision: str = "f64"):
+    """Gradients (dW list, db list, dx) of a scalar loss given dL/dY (float64), by the chain rule through
+    the forward of `cache`: dZ_out = dL/dY * Y (1 - Y); dW_k = dZ_k^T h_k, db_k = sum over rows of dZ_k,
+    dh_k = dZ_k W_k, dZ_{k-1} = dh_k * [z_{k-1} > 0].
+
+    ``precision="bf16"`` emulates a backward whose products take bfloat16 operands with float64
+    accumulation: every product operand -- dZ_k (in the weight, bias and input products), W_k and h_k --
+    rounded to bfloat16 (round-to-nearest-even); the bias gradient sums the rounded dZ_k (it is the
+    product of dZ_k with a vector of ones).  The cache is then that of ``forward(..., "bf16")``."""
     hs, zs = cache
+    if precision not in ("f64", "bf16"):
+        raise ValueError(precision)
+    rnd = lowp.round_bf16 if precision == "bf16" else (lambda v: v)
     dz = d_y * y * (1.0 - y)
     dws, dbs = [None] * len(layers), [None] * len(layers)
     for k in range(len(layers) - 1, -1, -1):
-        w = np.asarray(layers[k][0], dtype=np.float64)
-        dws[k] = dz.T @ hs[k]
-        dbs[k] = dz.sum(axis=0)
-        dh = dz @ w
+        w = rnd(np.asarray(layers[k][0], dtype=np.float64))
+        dzr = rnd(dz)
+        dws[k] = dzr.T @ rnd(hs[k])
+        dbs[k] = dzr.sum(axis=0)
+        dh = dzr @ w
         if k > 0:
             dz = dh * (zs[k - 1] > 0)
         else:

@@ -211,9 +211,13 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a) {
 }
 
 // d_grid[corner] += w_corner * dX (times the pass-through mask of the corner value with QAT), for one
-// (position, level, feature).
+// (position, level, feature).  Acc = float: FP32 atomics (the sum depends on their order).  Acc =
+// unsigned long long (deterministic mode): each term is rounded to a fixed-point integer at the step's
+// scale (a power of two, *scale) and added with 64-bit integer atomics, whose sum does not depend on
+// the order.
+template <typename Acc>
 __device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l, int f,
-                                            float* __restrict__ dst) {
+                                            Acc* __restrict__ dst, float scale) {
   const float df = dx[(p * a.n_levels + l) * a.F + f];
   if (df == 0.0f) return;
   const Tap t = grid_tap(a, p, l);
@@ -227,40 +231,86 @@ __device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __re
       fake_quant(a.grid[t.vtx[c] * a.F + f], s, z, &inside);
       if (!inside) continue;
     }
-    atomicAdd(&dst[t.vtx[c] * a.F + f], t.w[c] * df);
+    const float v = t.w[c] * df;
+    if constexpr (sizeof(Acc) == 8)
+      atomicAdd(&dst[t.vtx[c] * a.F + f], (Acc)(long long)rint((double)v * (double)scale));
+    else
+      atomicAdd(&dst[t.vtx[c] * a.F + f], v);
   }
 }
 
 // Levels [first_level, n_levels): one thread per (position, level, feature), feature fastest so that
 // the atomics of a corner land in one cache line.
-__global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid,
-                                                    int first_level) {
+template <typename Acc>
+__global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __restrict__ dx, Acc* __restrict__ dgrid,
+                                                    int first_level, const float* __restrict__ det_scale) {
   const int nl = a.n_levels - first_level;
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (gid >= a.n * nl * a.F) return;
   const int f = (int)(gid % a.F);
   const int64_t pl = gid / a.F;
-  scatter_one(a, dx, pl / nl, first_level + (int)(pl % nl), f, dgrid);
+  scatter_one<Acc>(a, dx, pl / nl, first_level + (int)(pl % nl), f, dgrid, det_scale ? *det_scale : 1.0f);
 }
 
 // Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a strided share of the
 // batch in LDS, then adds its non-zero sums to the grid gradient -- one global atomic per touched
 // value per block instead of one per position.
-__global__ void __launch_bounds__(kBlock) k_scatter_coarse(FeatArgs a, const float* __restrict__ dx, float* __restrict__ dgrid,
-                                                           int n_coarse) {
-  extern __shared__ float acc[];
+template <typename Acc>
+__global__ void __launch_bounds__(kBlock) k_scatter_coarse(FeatArgs a, const float* __restrict__ dx, Acc* __restrict__ dgrid,
+                                                           int n_coarse, const float* __restrict__ det_scale) {
+  extern __shared__ __align__(8) unsigned char acc_raw[];
+  Acc* acc = reinterpret_cast<Acc*>(acc_raw);
+  const float scale = det_scale ? *det_scale : 1.0f;
   const int64_t nv = a.level_offset[n_coarse] * a.F;
-  for (int64_t i = threadIdx.x; i < nv; i += kBlock) acc[i] = 0.0f;
+  for (int64_t i = threadIdx.x; i < nv; i += kBlock) acc[i] = (Acc)0;
   __syncthreads();
   const int64_t per_pos = (int64_t)n_coarse * a.F;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.n * per_pos; e += (int64_t)gridDim.x * kBlock) {
     const int64_t p = e / per_pos;
     const int r = (int)(e - p * per_pos);
-    scatter_one(a, dx, p, r / a.F, r % a.F, acc);
+    scatter_one<Acc>(a, dx, p, r / a.F, r % a.F, acc, scale);
   }
   __syncthreads();
   for (int64_t i = threadIdx.x; i < nv; i += kBlock)
-    if (acc[i] != 0.0f) atomicAdd(&dgrid[i], acc[i]);
+    if (acc[i] != (Acc)0) atomicAdd(&dgrid[i], acc[i]);
+}
+
+// Deterministic mode: the fixed-point scale of a step.  amax = max |dX| over the batch (float bits);
+// each grid value sums at most n terms of magnitude <= amax (a position reaches a vertex at most once,
+// with a bilinear weight <= 1), so scale = 2^(61 - ceil(log2(n amax))) keeps every partial sum below 2^61.
+__global__ void k_absmax_bits(const float* __restrict__ x, int64_t count, unsigned* __restrict__ amax) {
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+}
+
+__global__ void k_det_scale(const unsigned* __restrict__ amax, int64_t n, float* __restrict__ scale) {
+  const double m = (double)__uint_as_float(*amax) * (double)n;
+  int e = 0;
+  if (m > 0.0 && isfinite(m)) {
+    frexp(m, &e);  // m < 2^e
+    e = 61 - e;
+    e = e > 126 ? 126 : (e < -126 ? -126 : e);
+  }
+  *scale = ldexpf(1.0f, e);
+}
+
+// d_grid += fixed-point sums / scale.
+__global__ void k_det_finish(unsigned long long* __restrict__ acc, const float* __restrict__ scale, float* __restrict__ d_grid,
+                             int64_t count) {
+  const double inv = 1.0 / (double)*scale;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const long long v = (long long)acc[i];
+    if (v != 0) d_grid[i] += (float)((double)v * inv);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 // ------------------------------------------------------------------------------------------ GEMM
@@ -612,6 +662,7 @@ struct LossArgs {
   const int32_t* ids;
   int64_t n, n_positions;
   int head_dim, E, C, n_textures, blocks_w;
+  int ld;  // floats between the rows of y and dy (head_dim, or the padded width of the fused path)
   int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
   const uint64_t* ref;
   const uint8_t* tex[NTBC_MAX_TEXTURES];
@@ -708,8 +759,8 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
                              float* lcdc, bool* bad, float de0[3], float de1[3]) {
   constexpr bool bc1 = CH == 3;
   constexpr int N = bc1 ? 4 : 8;
-  const float* yp = a.y + p * a.head_dim;
-  float* dyp = a.dy + p * a.head_dim;
+  const float* yp = a.y + p * a.ld;
+  float* dyp = a.dy + p * a.ld;
   const uint64_t w = a.ref[(int64_t)t * a.n_positions + id];
   float er0[3] = {0, 0, 0}, er1[3] = {0, 0, 0};
   bool eight_ref = true;
@@ -880,8 +931,8 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
     }
     if (active && sub == 0) {
       const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
-      float* dyp = a.dy + p * a.head_dim + a.ep_off[t];
-      const float* yp = a.y + p * a.head_dim + a.ep_off[t];
+      float* dyp = a.dy + p * a.ld + a.ep_off[t];
+      const float* yp = a.y + p * a.ld + a.ep_off[t];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         if (ch < ch_n) {
@@ -969,6 +1020,674 @@ __global__ void k_export_qparams(const int* __restrict__ stats, int n_levels, fl
   }
 }
 
+// ================================================================================== fused bfloat16
+// The bfloat16 training step with the layers chained in registers (the inference kernel's layout):
+//
+//   k_pack_train   FP32 weights -> bfloat16 A operands of the forward products (W_k) and of the
+//                  backward products (W_k^T), biases padded to whole tiles
+//   k_train_fwd    per 128 positions: (fake-quantised) grid features -> hidden layers -> sigmoid heads,
+//                  activations never leave registers between layers; writes the heads, the ReLU
+//                  masks (one bit per activation) and the bfloat16 layer inputs position-contiguous
+//                  ([neuron][position], the K-major operand of the weight gradient)
+//   k_loss_grad    dL/dZ of the head (as for the unfused step)
+//   k_train_bwd    per 128 positions: dZ_head -> dZ_k = (W_{k+1}^T dZ_{k+1}) * mask_k down to
+//                  dX = W_0^T dZ_0, chained in registers like the forward; writes every dZ_k
+//                  position-contiguous in bfloat16 and dX in FP32 for the grid scatter
+//   k_train_dw     dW_k = dZ_k^T H_{k-1} and db_k = sum over positions of dZ_k for every layer in
+//                  one launch: 128 x 128 output tiles, the batch split into K ranges, FP32 partial
+//                  tiles reduced in a fixed order by k_train_dw_reduce (no atomics: deterministic)
+//
+// Lane (j, g) of a wave owns position j of the wave's 32 and row group g, as in the inference kernel:
+// accumulator v of output tile t is neuron 32t + 8(v/4) + 4g + v%4; values 8h..8h+7 of tile t are the
+// B operand of K-step 2t+h of the next product.  The backward products use the same layout with
+// W_k^T as the A operand, so the masks of the forward apply to the backward accumulators lane by lane.
+constexpr int kFW = 4;            // waves per workgroup: 128 positions
+constexpr int kFPos = 32 * kFW;
+constexpr int kFChunkTiles = 2;   // output tiles per weight chunk
+constexpr int kFMaxChunks = 48;
+constexpr int kFMaxLayers = 5;
+constexpr int kFHeadTiles = 6;    // head rows padded to at most 192
+constexpr int kFHeadLd = 32 * kFHeadTiles;
+constexpr int kFPrefetch = 4;
+
+struct FChunks {
+  int n;
+  int cap;                   // u32x4 slots of one chunk buffer
+  int64_t src[kFMaxChunks];  // u32x4 offset into the packed weights
+  int len[kFMaxChunks];
+};
+
+__device__ __forceinline__ uint32_t fbf2(float lo, float hi) { return bf2(lo, hi); }
+
+__device__ __forceinline__ u32x4 fpack8(const float* v) {
+  return u32x4{fbf2(v[0], v[1]), fbf2(v[2], v[3]), fbf2(v[4], v[5]), fbf2(v[6], v[7])};
+}
+
+__device__ __forceinline__ uint16_t fbf1(float x) { return (uint16_t)(fbf2(x, 0.0f) & 0xFFFFu); }
+
+__device__ __forceinline__ f32x16_t fmma(const u32x4& a, const u32x4& b, const f32x16_t& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+
+__device__ __forceinline__ void fwait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Copies chunk c of the packed weights into LDS buffer dst (direct global -> LDS, 16 bytes a lane).
+__device__ __forceinline__ void fchunk_dma(const u32x4* __restrict__ wp, const FChunks& ct, int c, u32x4* dst, int tid) {
+  if (c >= ct.n) return;
+  const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
+  const int len = ct.len[c];
+  const u32x4* src = wp + ct.src[c];
+  for (int r = 0; r * kFPos < len; ++r) {
+    const int e = tid + kFPos * r;
+    if (e < len)
+      __builtin_amdgcn_global_load_lds(src + e, (__attribute__((address_space(3))) void*)(dst + wave_base + kFPos * r), 16,
+                                       0, 0);
+  }
+}
+
+// Products of up to two output tiles over KS K-steps from an LDS chunk (A fragment of tile u, step s,
+// lane l at wb[(u*KS + s)*64 + l]), the fragments read kFPrefetch steps ahead.
+template <int KS, int NB>
+__device__ __forceinline__ void fchunk_mfma(const u32x4* wb, const u32x4 (&b)[NB], int lane, int valid,
+                                            f32x16_t (&acc)[kFChunkTiles]) {
+  static_assert(KS <= NB, "operand count");
+  constexpr int PD = kFPrefetch < KS ? kFPrefetch : KS;
+  u32x4 ring[PD][kFChunkTiles];
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) ring[d][u] = u < valid ? wb[(u * KS + d) * 64 + lane] : u32x4{};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    u32x4 cur[kFChunkTiles];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) cur[u] = ring[s % PD][u];
+    if (s + PD < KS) {
+#pragma unroll
+      for (int u = 0; u < kFChunkTiles; ++u)
+        if (u < valid) ring[s % PD][u] = wb[(u * KS + s + PD) * 64 + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u)
+      if (u < valid) acc[u] = fmma(cur[u], b[s], acc[u]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// ----------------------------------------------------------------------------- weight packing
+struct PackTrainArgs {
+  const float* w;  // canonical FP32 weights
+  int n_layers;
+  int in_dim[kFMaxLayers], out_dim[kFMaxLayers];
+  int64_t w_off[kFMaxLayers], b_off[kFMaxLayers];
+  // forward: A(row = output neuron, K = layer input), rows padded to otiles*32, K to ksteps*16
+  int f_otiles[kFMaxLayers], f_ksteps[kFMaxLayers];
+  int64_t f_off[kFMaxLayers];
+  // backward: A(row = layer input neuron, K = output neuron)
+  int b_otiles[kFMaxLayers], b_ksteps[kFMaxLayers];
+  int64_t b_off2[kFMaxLayers];
+  int bias_off[kFMaxLayers];  // padded biases (floats)
+  u32x4* pack;
+  float* bias;
+};
+
+// K index of element m of K-step s in lane group g: the grid features (forward layer 0) and the head
+// gradient (backward of the head, read from memory) are in natural order; a chained input (the
+// previous product's accumulators) is permuted.
+__device__ __forceinline__ int fk_natural(int s, int g, int m) { return 16 * s + 8 * g + m; }
+__device__ __forceinline__ int fk_chained(int s, int g, int m) {
+  return 32 * (s / 2) + 16 * (s % 2) + 8 * (m / 4) + 4 * g + (m % 4);
+}
+
+__global__ void __launch_bounds__(256) k_pack_train(PackTrainArgs a) {
+  const int layer = blockIdx.y >> 1;
+  const bool bwd = (blockIdx.y & 1) != 0;
+  if (layer >= a.n_layers) return;
+  const int in = a.in_dim[layer], out = a.out_dim[layer];
+  const float* w = a.w + a.w_off[layer];
+  const int ot = bwd ? a.b_otiles[layer] : a.f_otiles[layer];
+  const int ks = bwd ? a.b_ksteps[layer] : a.f_ksteps[layer];
+  const int64_t base = bwd ? a.b_off2[layer] : a.f_off[layer];
+  const bool head = layer == a.n_layers - 1;
+  const int64_t total = (int64_t)ot * ks * 64;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e % 64);
+    const int s = (int)((e / 64) % ks);
+    const int t = (int)(e / (64 * (int64_t)ks));
+    const int row = 32 * t + (l % 32), g = l / 32;
+    float v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      int o, i;  // W[o][i]
+      if (!bwd) {
+        o = row;
+        i = layer == 0 ? fk_natural(s, g, m) : fk_chained(s, g, m);
+      } else {
+        i = row;
+        o = head ? fk_natural(s, g, m) : fk_chained(s, g, m);
+      }
+      v[m] = (o < out && i < in) ? w[(int64_t)o * in + i] : 0.0f;
+    }
+    a.pack[base + e] = fpack8(v);
+  }
+  if (!bwd) {
+    const int nb = ot * 32;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
+      a.bias[a.bias_off[layer] + i] = i < out ? a.w[a.b_off[layer] + i] : 0.0f;
+  }
+}
+
+// ----------------------------------------------------------------------------- forward
+struct FwdArgs {
+  const float* grid;
+  const int* stats;           // QAT (s, z) per level, or null
+  const int32_t* ids;
+  int64_t n, n_positions;
+  int n_levels, base_res, F, blocks_w, blocks_h, in_dim;
+  int64_t level_offset[NTBC_MAX_LEVELS + 1];
+  const u32x4* wpack;
+  const float* bias;
+  int bias_off[kFMaxLayers];
+  int n_layers, head_dim, n_bias;
+  int64_t bpad;               // position stride of the position-contiguous buffers
+  uint16_t* xt;               // [16*KS0][bpad] layer-0 inputs, bfloat16
+  uint16_t* ht;               // [n_hidden][HID][bpad] hidden outputs (after the ReLU), bfloat16
+  uint32_t* masks;            // per wave tile and hidden layer: HID/64 words a lane (ReLU derivative bits)
+  float* y;                   // [n][y_ld] sigmoid heads
+  int y_ld;
+  FChunks ct;
+};
+
+// Features c0 .. c0+7 of a position (the layer-0 B operand values), from the FP32 master grid
+// fake-quantised per level when QAT is on: the arithmetic of k_features.
+__device__ __forceinline__ void ffeatures(const FwdArgs& a, int c0, int bx, int by, float v[8]) {
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[m] = 0.0f;
+  if (a.F == 8) {
+    if (c0 >= a.in_dim) return;
+    const int l = c0 / 8;
+    const int res = a.base_res << l;
+    const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+    const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
+    const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
+    const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
+    float q[4][8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float4 lo = *reinterpret_cast<const float4*>(a.grid + vtx[c] * 8);
+      const float4 hi = *reinterpret_cast<const float4*>(a.grid + vtx[c] * 8 + 4);
+      q[c][0] = lo.x, q[c][1] = lo.y, q[c][2] = lo.z, q[c][3] = lo.w;
+      q[c][4] = hi.x, q[c][5] = hi.y, q[c][6] = hi.z, q[c][7] = hi.w;
+    }
+    if (a.stats) {
+      const float s = reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l];
+      const int z = a.stats[3 * NTBC_MAX_LEVELS + l];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          bool inside;
+          q[c][m] = fake_quant(q[c][m], s, z, &inside);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = fmaf(w[0], q[0][m], fmaf(w[1], q[1][m], fmaf(w[2], q[2][m], w[3] * q[3][m])));
+    return;
+  }
+  for (int m = 0; m < 8; ++m) {
+    const int c = c0 + m;
+    if (c >= a.in_dim) break;
+    const int l = c / a.F, f = c % a.F;
+    const int res = a.base_res << l;
+    const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+    const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
+    const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
+    const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
+    float q[4];
+    for (int k = 0; k < 4; ++k) {
+      q[k] = a.grid[vtx[k] * a.F + f];
+      if (a.stats) {
+        bool inside;
+        q[k] = fake_quant(q[k], reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l],
+                          a.stats[3 * NTBC_MAX_LEVELS + l], &inside);
+      }
+    }
+    v[m] = fmaf(w[0], q[0], fmaf(w[1], q[1], fmaf(w[2], q[2], w[3] * q[3])));
+  }
+}
+
+// Bias-initialised accumulators of output tile t (bias4[q] = neurons 32t + 8q + 4g .. +3).
+__device__ __forceinline__ f32x16_t facc_bias(const float* bt, int g) {
+  f32x16_t r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+    r[4 * q] = b.x, r[4 * q + 1] = b.y, r[4 * q + 2] = b.z, r[4 * q + 3] = b.w;
+  }
+  return r;
+}
+
+// Stores the eight bfloat16 values of operand x (rows r0 .. r0+7) at column p of buf.
+__device__ __forceinline__ void fstore_rows8(uint16_t* __restrict__ buf, int64_t bpad, int r0, int64_t p, const u32x4& x) {
+  int stride = (int)bpad;
+  asm volatile("" : "+s"(stride));
+  const uint32_t base = (uint32_t)r0 * (uint32_t)stride + (uint32_t)p;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) buf[base + (uint32_t)(m * stride)] = (uint16_t)((x[m / 2] >> (16 * (m % 2))) & 0xFFFFu);
+}
+
+// Stores the 16 bfloat16 values of an epilogue tile (words w: value v in the half v%2 of word v/2)
+// position-contiguous: value v belongs to neuron 32t + 8(v/4) + 4g + v%4, stored at element
+// neuron * stride + p of buf (zero for positions past the batch).  The stride passes through an empty
+// asm so that the row offsets are recomputed per tile (scalar multiplies) instead of being hoisted for
+// every tile of the layer into registers.
+__device__ __forceinline__ void fstore_tile(uint16_t* __restrict__ buf, int64_t bpad, int t, int g, int64_t p,
+                                            const uint32_t (&w)[8], bool live) {
+  int stride = (int)bpad;
+  asm volatile("" : "+s"(stride));
+  const uint32_t base = (uint32_t)(32 * t + 4 * g) * (uint32_t)stride + (uint32_t)p;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const uint32_t off = base + (uint32_t)((8 * (v / 4) + v % 4) * stride);
+    buf[off] = live ? (uint16_t)((w[v / 2] >> (16 * (v % 2))) & 0xFFFFu) : (uint16_t)0;
+  }
+}
+
+// Forward epilogue of a hidden tile: ReLU (NaN kept, so a non-finite parameter reaches the gradient
+// check), the next product's two B operands, the derivative bits (z > 0) and the bfloat16 outputs
+// stored position-contiguous (zero for positions past the batch).
+__device__ __forceinline__ uint32_t fhidden_epilogue(const f32x16_t& acc, int t, int g, u32x4* lo, u32x4* hi,
+                                                     uint16_t* __restrict__ ht, int64_t bpad, int64_t p, bool live) {
+  float r[16];
+  uint32_t bits = 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const float z = acc[v];
+    r[v] = z < 0.0f ? 0.0f : z;
+    bits |= (z > 0.0f ? 1u : 0u) << v;
+  }
+  *lo = fpack8(r);
+  *hi = fpack8(r + 8);
+  const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
+  fstore_tile(ht, bpad, t, g, p, w, live);
+  return bits;
+}
+
+template <int S, int T>
+__device__ __forceinline__ void fwd_hidden(const FwdArgs& a, const u32x4 (&in)[S], u32x4 (&out)[S], const float* bl,
+                                           uint16_t* __restrict__ ht, uint32_t* __restrict__ mk, u32x4* smem, int& c,
+                                           int tid, int lane, int g, int64_t p, bool live) {
+#pragma unroll
+  for (int tc = 0; tc < T / kFChunkTiles; ++tc) {
+    fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
+    f32x16_t acc[kFChunkTiles];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) acc[u] = facc_bias(bl + 32 * (kFChunkTiles * tc + u), g);
+    fchunk_mfma<S, S>(smem + (c & 1) * a.ct.cap, in, lane, kFChunkTiles, acc);
+    uint32_t word = 0;
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) {
+      const int t = kFChunkTiles * tc + u;
+      word |= fhidden_epilogue(acc[u], t, g, &out[2 * t], &out[2 * t + 1], ht, a.bpad, p, live) << (16 * u);
+    }
+    mk[tc * 64] = word;
+    fwait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+template <int HID, int KS0, int NH, int HT>
+__global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2))) k_train_fwd(FwdArgs a) {
+  constexpr int S = HID / 16, T = HID / 32;
+  extern __shared__ u32x4 smem[];
+  float* bias_s = reinterpret_cast<float*>(smem + 2 * a.ct.cap);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 31, g = lane >> 5;
+  const int64_t p = (int64_t)blockIdx.x * kFPos + wave * 32 + j;
+  const bool live = p < a.n;
+  const int id = live ? clamp_id(a.ids[p], a.n_positions) : 0;
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int n_hidden = a.n_layers - 1;
+  uint32_t* mbase = a.masks + ((int64_t)(blockIdx.x * kFW + wave) * n_hidden) * (T / 2) * 64 + lane;
+
+  fchunk_dma(a.wpack, a.ct, 0, smem, tid);
+  for (int i = tid; i < a.n_bias; i += 64 * kFW) bias_s[i] = a.bias[i];
+  u32x4 x0[KS0];
+#pragma unroll
+  for (int s = 0; s < KS0; ++s) {
+    float v[8];
+    ffeatures(a, 16 * s + 8 * g, bx, by, v);
+    if (!live) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m] = 0.0f;
+    }
+    x0[s] = fpack8(v);
+    fstore_rows8(a.xt, a.bpad, 16 * s + 8 * g, p, x0[s]);
+  }
+  fwait_dma();
+  __syncthreads();
+
+  int c = 0;
+  u32x4 bin[S], bout[S];
+  {
+    const float* bl = bias_s + a.bias_off[0];
+    uint32_t* mk = mbase;
+#pragma unroll
+    for (int tc = 0; tc < T / kFChunkTiles; ++tc) {
+      fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
+      f32x16_t acc[kFChunkTiles];
+#pragma unroll
+      for (int u = 0; u < kFChunkTiles; ++u) acc[u] = facc_bias(bl + 32 * (kFChunkTiles * tc + u), g);
+      fchunk_mfma<KS0, KS0>(smem + (c & 1) * a.ct.cap, x0, lane, kFChunkTiles, acc);
+      uint32_t word = 0;
+#pragma unroll
+      for (int u = 0; u < kFChunkTiles; ++u) {
+        const int t = kFChunkTiles * tc + u;
+        word |= fhidden_epilogue(acc[u], t, g, &bin[2 * t], &bin[2 * t + 1], a.ht, a.bpad, p, live) << (16 * u);
+      }
+      mk[tc * 64] = word;
+      fwait_dma();
+      __syncthreads();
+      ++c;
+    }
+  }
+  static_assert(NH >= 1 && NH <= 2, "one or two middle hidden layers");
+  fwd_hidden<S, T>(a, bin, bout, bias_s + a.bias_off[1], a.ht + (int64_t)HID * a.bpad, mbase + (T / 2) * 64, smem, c, tid,
+                   lane, g, p, live);
+  if constexpr (NH == 2) {
+    fwd_hidden<S, T>(a, bout, bin, bias_s + a.bias_off[2], a.ht + (int64_t)2 * HID * a.bpad, mbase + 2 * (T / 2) * 64,
+                     smem, c, tid, lane, g, p, live);
+  } else {
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  // head: sigmoid outputs in rows 32t + 8q + 4g .. +3 of position p
+  const float* bl = bias_s + a.bias_off[NH + 1];
+#pragma unroll
+  for (int tc = 0; tc < (HT + 1) / 2; ++tc) {
+    fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
+    const int valid = HT - kFChunkTiles * tc < kFChunkTiles ? HT - kFChunkTiles * tc : kFChunkTiles;
+    f32x16_t acc[kFChunkTiles];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) acc[u] = u < valid ? facc_bias(bl + 32 * (kFChunkTiles * tc + u), g) : f32x16_t{};
+    fchunk_mfma<S, S>(smem + (c & 1) * a.ct.cap, bin, lane, valid, acc);
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) {
+      if (u < valid && live) {
+        const int t = kFChunkTiles * tc + u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r0 = 32 * t + 8 * q + 4 * g;
+          float o[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[r] = 1.0f / (1.0f + expf(-acc[u][4 * q + r]));
+          float* dst = a.y + p * a.y_ld + r0;
+          if ((a.y_ld & 3) == 0) {
+            if (r0 < a.head_dim) *reinterpret_cast<float4*>(dst) = float4{o[0], o[1], o[2], o[3]};
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (r0 + r < a.head_dim) dst[r] = o[r];
+          }
+        }
+      }
+    }
+    fwait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+// ----------------------------------------------------------------------------- backward
+struct BwdArgs {
+  const float* dz;            // [n][dz_ld] dL/dZ of the head pre-activations
+  int dz_ld, head_dim;
+  int64_t n, bpad;
+  const u32x4* wpack;
+  const uint32_t* masks;
+  uint16_t* dzt;              // position-contiguous bfloat16 dZ_k: rows zrow[k] .. of [rows][bpad]
+  int64_t zrow[kFMaxLayers];
+  float* dx;                  // [n][in_dim]
+  int in_dim, n_layers;
+  FChunks ct;
+};
+
+// Backward epilogue of a tile: dZ = dH * (z > 0) (`bits`), the next product's B operands, and the
+// bfloat16 dZ stored position-contiguous.
+__device__ __forceinline__ void fbwd_epilogue(const f32x16_t& acc, uint32_t bits, int t, int g, u32x4* lo, u32x4* hi,
+                                              uint16_t* __restrict__ zt, int64_t bpad, int64_t p, bool live) {
+  float r[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) r[v] = ((bits >> v) & 1u) ? acc[v] : 0.0f;
+  *lo = fpack8(r);
+  *hi = fpack8(r + 8);
+  const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
+  fstore_tile(zt, bpad, t, g, p, w, live);
+}
+
+// One backward product W_k^T dZ_k over a hidden layer's rows (T tiles), K = KS steps of `in`.
+template <int KS, int NB, int S, int T>
+__device__ __forceinline__ void bwd_hidden(const BwdArgs& a, const u32x4 (&in)[NB], u32x4 (&out)[S],
+                                           const uint32_t* __restrict__ mk, uint16_t* __restrict__ zt, u32x4* smem,
+                                           int& c, int tid, int lane, int g, int64_t p, bool live) {
+#pragma unroll
+  for (int tc = 0; tc < T / kFChunkTiles; ++tc) {
+    fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
+    f32x16_t acc[kFChunkTiles];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) acc[u] = f32x16_t{};
+    fchunk_mfma<KS, NB>(smem + (c & 1) * a.ct.cap, in, lane, kFChunkTiles, acc);
+    const uint32_t word = mk[tc * 64];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) {
+      const int t = kFChunkTiles * tc + u;
+      fbwd_epilogue(acc[u], word >> (16 * u), t, g, &out[2 * t], &out[2 * t + 1], zt, a.bpad, p, live);
+    }
+    fwait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+template <int HID, int KS0, int NH, int HT>
+__global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2))) k_train_bwd(BwdArgs a) {
+  constexpr int S = HID / 16, T = HID / 32;
+  constexpr int KH = 2 * HT;        // K-steps of the head gradient
+  constexpr int IT = (KS0 + 1) / 2; // row tiles of dX
+  extern __shared__ u32x4 smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 31, g = lane >> 5;
+  const int64_t p = (int64_t)blockIdx.x * kFPos + wave * 32 + j;
+  const bool live = p < a.n;
+  const int n_hidden = a.n_layers - 1;
+  const uint32_t* mbase = a.masks + ((int64_t)(blockIdx.x * kFW + wave) * n_hidden) * (T / 2) * 64 + lane;
+
+  fchunk_dma(a.wpack, a.ct, 0, smem, tid);
+  // head gradient: B operands in natural row order, also stored position-contiguous for dW
+  u32x4 dzh[KH];
+  uint16_t* zh = a.dzt + a.zrow[a.n_layers - 1] * a.bpad;
+#pragma unroll
+  for (int s = 0; s < KH; ++s) {
+    float v[8];
+    const int r0 = 16 * s + 8 * g;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = (live && r0 + m < a.head_dim) ? a.dz[p * a.dz_ld + r0 + m] : 0.0f;
+    dzh[s] = fpack8(v);
+    fstore_rows8(zh, a.bpad, r0, p, dzh[s]);
+  }
+  fwait_dma();
+  __syncthreads();
+
+  int c = 0;
+  u32x4 bin[S], bout[S];
+  const int top = a.n_layers - 2;  // the last hidden layer
+  // head^T: dZ of the last hidden layer
+  bwd_hidden<KH, KH, S, T>(a, dzh, bin, mbase + top * (T / 2) * 64, a.dzt + a.zrow[top] * a.bpad, smem, c, tid, lane, g,
+                           p, live);
+  // middle layers, from the top down
+  static_assert(NH >= 1 && NH <= 2, "one or two middle hidden layers");
+  bwd_hidden<S, S, S, T>(a, bin, bout, mbase + (top - 1) * (T / 2) * 64, a.dzt + a.zrow[top - 1] * a.bpad, smem, c,
+                         tid, lane, g, p, live);
+  if constexpr (NH == 2) {
+    bwd_hidden<S, S, S, T>(a, bout, bin, mbase + (top - 2) * (T / 2) * 64, a.dzt + a.zrow[top - 2] * a.bpad, smem, c,
+                           tid, lane, g, p, live);
+  } else {
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  // dX = W_0^T dZ_0 in FP32: features 32t + 8q + 4g .. +3 of position p
+#pragma unroll
+  for (int tc = 0; tc < (IT + 1) / 2; ++tc) {
+    fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
+    const int valid = IT - kFChunkTiles * tc < kFChunkTiles ? IT - kFChunkTiles * tc : kFChunkTiles;
+    f32x16_t acc[kFChunkTiles];
+#pragma unroll
+    for (int u = 0; u < kFChunkTiles; ++u) acc[u] = f32x16_t{};
+    fchunk_mfma<S, S>(smem + (c & 1) * a.ct.cap, bin, lane, valid, acc);
+    if (live) {
+#pragma unroll
+      for (int u = 0; u < kFChunkTiles; ++u) {
+        if (u < valid) {
+          const int t = kFChunkTiles * tc + u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int f0 = 32 * t + 8 * q + 4 * g;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (f0 + r < a.in_dim) a.dx[p * a.in_dim + f0 + r] = acc[u][4 * q + r];
+          }
+        }
+      }
+    }
+    fwait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+// ----------------------------------------------------------------------------- weight gradient
+struct DwJob {
+  const uint16_t* a;  // A(m, k) = a[m * bpad + k]: dZ_k rows (output neurons), rows < a_rows
+  const uint16_t* b;  // B(n, k) = b[n * bpad + k]: layer inputs, rows < b_rows
+  int a_rows, b_rows; // rows present in the buffers (padded, zero past the true sizes)
+  int M, N;           // true output sizes
+  int tiles_n, tile0; // 128-wide tiles along N; first global tile of the job
+  float* c;           // dW [M][N] (canonical row-major)
+  float* db;          // bias gradient [M]
+};
+
+struct DwArgs {
+  DwJob job[kFMaxLayers];
+  int n_jobs, n_tiles, splits, k_split;
+  int64_t bpad, K;    // K = positions (a multiple of 32)
+  float* part;        // [n_tiles][splits][128 * 128]
+  float* dbpart;      // [n_tiles][splits][128]
+};
+
+// Block b: tile b % n_tiles, K range b / n_tiles.  Four waves, each a 64 x 64 quadrant as 2 x 2
+// products of 32 x 32; fragments read straight from the position-contiguous buffers (16 bytes a lane:
+// eight consecutive positions of one row).
+__global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
+  const int tile = blockIdx.x % a.n_tiles, split = blockIdx.x / a.n_tiles;
+  int jb = 0;
+  while (jb + 1 < a.n_jobs && tile >= a.job[jb + 1].tile0) ++jb;
+  const DwJob& J = a.job[jb];
+  const int lt = tile - J.tile0;
+  const int tm = lt / J.tiles_n, tn = lt % J.tiles_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, li = lane & 31, g = lane >> 5;
+  const int64_t k0 = (int64_t)split * a.k_split;
+  const int64_t k1 = k0 + a.k_split < a.K ? k0 + a.k_split : a.K;
+  int ar[2], br[2];
+  bool aok[2], bok[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    ar[i] = tm * 128 + wm * 64 + 32 * i + li;
+    br[i] = tn * 128 + wn * 64 + 32 * i + li;
+    aok[i] = ar[i] < J.a_rows;
+    bok[i] = br[i] < J.b_rows;
+  }
+  const bool sums = tn == 0 && wn == 0;  // bias gradient: row sums of A in FP32
+  float rs[2] = {0.0f, 0.0f};
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) acc[i][jj] = f32x16_t{};
+  const u32x4* ap[2];
+  const u32x4* bp[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    ap[i] = reinterpret_cast<const u32x4*>(J.a + (int64_t)(aok[i] ? ar[i] : 0) * a.bpad + 8 * g);
+    bp[i] = reinterpret_cast<const u32x4*>(J.b + (int64_t)(bok[i] ? br[i] : 0) * a.bpad + 8 * g);
+  }
+  for (int64_t k = k0; k < k1; k += 16) {
+    u32x4 af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      af[i] = aok[i] ? ap[i][k / 8] : u32x4{};
+      bf[i] = bok[i] ? bp[i][k / 8] : u32x4{};
+    }
+    if (sums) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          rs[i] += __uint_as_float(af[i][e] << 16) + __uint_as_float(af[i][e] & 0xFFFF0000u);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) acc[i][jj] = fmma(af[i], bf[jj], acc[i][jj]);
+  }
+  float* part = a.part + ((int64_t)tile * a.splits + split) * (128 * 128);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = wm * 64 + 32 * i + 8 * (v / 4) + 4 * g + v % 4;
+        const int col = wn * 64 + 32 * jj + li;
+        part[r * 128 + col] = acc[i][jj][v];
+      }
+  if (sums) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float t = rs[i] + __shfl_xor(rs[i], 32);
+      if (g == 0) a.dbpart[((int64_t)tile * a.splits + split) * 128 + wm * 64 + 32 * i + li] = t;
+    }
+  }
+}
+
+// dW (and db) += the sum of the partial tiles over the K ranges, in K-range order.
+__global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
+  const int tile = blockIdx.y;
+  int jb = 0;
+  while (jb + 1 < a.n_jobs && tile >= a.job[jb + 1].tile0) ++jb;
+  const DwJob& J = a.job[jb];
+  const int lt = tile - J.tile0;
+  const int tm = lt / J.tiles_n, tn = lt % J.tiles_n;
+  const float* part = a.part + (int64_t)tile * a.splits * (128 * 128);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < 128 * 128; e += gridDim.x * 256) {
+    const int r = e / 128, col = e % 128;
+    const int m = tm * 128 + r, nn = tn * 128 + col;
+    if (m >= J.M || nn >= J.N) continue;
+    float s = 0.0f;
+    for (int k = 0; k < a.splits; ++k) s += part[(int64_t)k * (128 * 128) + e];
+    J.c[(int64_t)m * J.N + nn] += s;
+  }
+  if (tn == 0 && blockIdx.x == 0) {
+    for (int r = threadIdx.x; r < 128; r += 256) {
+      const int m = tm * 128 + r;
+      if (m >= J.M) continue;
+      float s = 0.0f;
+      for (int k = 0; k < a.splits; ++k) s += a.dbpart[((int64_t)tile * a.splits + k) * 128 + r];
+      J.db[m] += s;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------ batches
 __host__ __device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -1043,9 +1762,13 @@ struct Ctx {
   int64_t n;
   hipStream_t strm;
   bool bf16;  // bfloat16 matrix-core operands (FP32 accumulation, FP32 master parameters)
+  bool det = false;     // deterministic reductions (grid scatter in fixed point, unsplit weight products)
+  int64_t det_off = 0;  // byte offset of the deterministic scatter's sums in the workspace
   int* stats() { return reinterpret_cast<int*>(ws + lay.stats); }
   float* act_in(int k) { return k == 0 ? ws + lay.x : ws + lay.h[k - 1]; }
 };
+
+int64_t det_offset(const Shape& s, int64_t batch);
 
 int check_common(const ntbc_model_desc* d, int precision, const int32_t* ids, int32_t n, void* workspace,
                  size_t workspace_bytes, Ctx* c) {
@@ -1058,10 +1781,12 @@ int check_common(const ntbc_model_desc* d, int precision, const int32_t* ids, in
   NTBC_REQUIRE(n >= 0, "n %d < 0", n);
   NTBC_REQUIRE(n == 0 || ids != nullptr, "ids is NULL");
   c->lay = train_layout(c->s, n);
-  if (workspace == nullptr || workspace_bytes < (size_t)c->lay.total * sizeof(float))
-    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)(c->lay.total * sizeof(float)));
+  const int64_t need = train_workspace_bytes(c->s, n);
+  if (workspace == nullptr || workspace_bytes < (size_t)need)
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)need);
   c->ws = static_cast<float*>(workspace);
   c->n = n;
+  c->det_off = det_offset(c->s, n);
   return NTBC_OK;
 }
 
@@ -1099,6 +1824,52 @@ int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int
   return NTBC_OK;
 }
 
+// Grid scatter of dX ([n][in_dim]) into d_grid (QAT pass-through mask when qat).  Deterministic mode:
+// 64-bit fixed-point sums at a per-step power-of-two scale (k_det_scale), converted and added at the end.
+int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const float* dx, float* d_grid) {
+  const Shape& s = c.s;
+  const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
+  const int64_t count = s.grid_vertices * s.n_features;
+  char* det = reinterpret_cast<char*>(c.ws) + c.det_off;
+  unsigned* amax = reinterpret_cast<unsigned*>(det);
+  float* scale = reinterpret_cast<float*>(det + 4);
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(det + 256);
+  const size_t vbytes = c.det ? 8 : 4;
+  if (c.det) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c.strm, reinterpret_cast<unsigned long long*>(det), (int64_t)1);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 8192)), dim3(256), 0, c.strm, acc, count);
+    const int64_t nx = c.n * s.in_dim;
+    hipLaunchKernelGGL(k_absmax_bits, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nx, 256), 1024))), dim3(256), 0,
+                       c.strm, dx, nx, amax);
+    hipLaunchKernelGGL(k_det_scale, dim3(1), dim3(1), 0, c.strm, amax, c.n, scale);
+  }
+  // coarse levels whose gradient fits in 48 KB of LDS are pre-aggregated per block
+  int n_coarse = 0;
+  while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * (int64_t)vbytes <= 48 * 1024) ++n_coarse;
+  if (n_coarse > 0) {
+    const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * vbytes;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 512));
+    if (c.det)
+      hipLaunchKernelGGL(k_scatter_coarse<unsigned long long>, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dx, acc, n_coarse,
+                         (const float*)scale);
+    else
+      hipLaunchKernelGGL(k_scatter_coarse<float>, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dx, d_grid, n_coarse,
+                         (const float*)nullptr);
+  }
+  if (n_coarse < s.n_levels) {
+    const dim3 grid_dim((unsigned)ceil_div(c.n * (s.n_levels - n_coarse) * s.n_features, kBlock));
+    if (c.det)
+      hipLaunchKernelGGL(k_scatter<unsigned long long>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, acc, n_coarse,
+                         (const float*)scale);
+    else
+      hipLaunchKernelGGL(k_scatter<float>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, d_grid, n_coarse, (const float*)nullptr);
+  }
+  if (c.det)
+    hipLaunchKernelGGL(k_det_finish, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 8192)), dim3(256), 0, c.strm, acc,
+                       (const float*)scale, d_grid, count);
+  return check_launch("k_scatter");
+}
+
 // Backward of the batch from dZ_out (in lay.dy): accumulates d_weights and d_grid.
 int backward(Ctx& c, const float* grid, const float* weights, bool qat, const int32_t* ids, float* d_grid, float* d_weights) {
   const Shape& s = c.s;
@@ -1123,7 +1894,8 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     gw.K = (int)c.n;
     const int tile = c.bf16 ? kBT : 64;
     const int tiles = (int)(ceil_div(out, tile) * ceil_div(in, tile));
-    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n, 256), ceil_div(c.bf16 ? 512 : 2048, tiles)));
+    // split over the batch with atomic adds, or (deterministic mode) one product per output tile
+    int splits = c.det ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n, 256), ceil_div(c.bf16 ? 512 : 2048, tiles)));
     const int kq = c.bf16 ? kBTK : 16;
     gw.k_split = (int)(ceil_div(ceil_div(c.n, splits), kq) * kq);
     splits = (int)ceil_div(c.n, gw.k_split);
@@ -1133,7 +1905,7 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     st = gemm<EPI_ATOMIC>(gw, splits, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
     if (!fused) {
-      const int rpb = 128;
+      const int rpb = c.det ? (int)c.n : 128;  // deterministic: one block (one atomic add) per column group
       hipLaunchKernelGGL(k_colsum, dim3((unsigned)ceil_div(c.n, rpb), (unsigned)ceil_div(out, 64)), dim3(kBlock), 0,
                          c.strm, dz, c.n, out, rpb, d_weights + s.b_off[k]);
       st = check_launch("k_colsum");
@@ -1164,24 +1936,12 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     dz = bufs[nb];
     nb ^= 1;
   }
-  const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
-  // coarse levels whose gradient fits in 48 KB of LDS are pre-aggregated per block
-  int n_coarse = 0;
-  while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * 4 <= 48 * 1024) ++n_coarse;
-  if (n_coarse > 0) {
-    const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * sizeof(float);
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 512));
-    hipLaunchKernelGGL(k_scatter_coarse, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dz, d_grid, n_coarse);
-  }
-  if (n_coarse < s.n_levels)
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)ceil_div(c.n * (s.n_levels - n_coarse) * s.n_features, kBlock)), dim3(kBlock), 0,
-                       c.strm, fa, dz, d_grid, n_coarse);
-  return check_launch("k_scatter");
+  return scatter_grid(c, grid, qat, ids, dz, d_grid);
 }
 
 // dsigmoid: write dL/dZ of the head pre-activations (dL/dY * Y (1 - Y)) instead of dL/dY.
 int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, float temperature,
-              const float* lw, float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false) {
+              const float* lw, float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0) {
   int st = fill(losses, 5, 0.0f, strm);
   if (st != NTBC_OK) return st;
   LossArgs a{};
@@ -1192,6 +1952,7 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   a.n = n;
   a.n_positions = s.n_positions;
   a.head_dim = s.head_dim;
+  a.ld = ld > 0 ? ld : s.head_dim;
   a.E = s.endpoint_dim;
   a.C = s.channels;
   a.n_textures = s.n_textures;
@@ -1222,10 +1983,277 @@ int check_targets(const Shape& s, const ntbc_targets* t) {
   return NTBC_OK;
 }
 
+// ------------------------------------------------------------------------------------------ fused host
+// Shapes the fused kernels take: hidden width 64 with two hidden layers, or 128 / 256 with three;
+// in_dim <= 64 (four K-steps of features); head_dim <= 192.
+constexpr int kFKS0 = 4, kFHT = kFHeadTiles;
+
+struct FusedPlan {
+  int hid, nh, L, S, T;
+  PackTrainArgs pk;
+  int64_t pack_n;             // u32x4
+  int n_bias;
+  FChunks fct, bct;
+  int out_pad[kFMaxLayers];   // rows of dZ_k (position-contiguous)
+  int64_t zrow[kFMaxLayers];
+  int64_t z_rows;
+};
+
+bool fused_plan(const Shape& s, FusedPlan* fp) {
+  const bool shape_ok = s.in_dim <= 16 * kFKS0 && s.head_dim <= 32 * kFHT &&
+                        ((s.hidden == 64 && s.n_hidden == 2) || (s.hidden == 128 && s.n_hidden == 3) ||
+                         (s.hidden == 256 && s.n_hidden == 3));
+  if (!shape_ok) return false;
+  FusedPlan& f = *fp;
+  f = FusedPlan{};
+  f.hid = s.hidden;
+  f.nh = s.n_hidden - 1;
+  f.L = s.n_layers;
+  f.S = s.hidden / 16;
+  f.T = s.hidden / 32;
+  PackTrainArgs& a = f.pk;
+  a.n_layers = f.L;
+  int64_t off = 0;
+  int boff = 0;
+  for (int k = 0; k < f.L; ++k) {
+    const bool head = k == f.L - 1;
+    a.in_dim[k] = s.layer_in[k];
+    a.out_dim[k] = s.layer_out[k];
+    a.w_off[k] = s.w_off[k];
+    a.b_off[k] = s.b_off[k];
+    a.f_otiles[k] = head ? kFHT : f.T;
+    a.f_ksteps[k] = k == 0 ? kFKS0 : f.S;
+    a.f_off[k] = off;
+    off += (int64_t)a.f_otiles[k] * a.f_ksteps[k] * 64;
+    a.bias_off[k] = boff;
+    boff += a.f_otiles[k] * 32;
+    f.out_pad[k] = head ? 32 * kFHT : f.hid;
+  }
+  for (int k = 0; k < f.L; ++k) {
+    a.b_otiles[k] = k == 0 ? (kFKS0 + 1) / 2 : f.T;
+    a.b_ksteps[k] = f.out_pad[k] / 16;
+    a.b_off2[k] = off;
+    off += (int64_t)a.b_otiles[k] * a.b_ksteps[k] * 64;
+  }
+  f.pack_n = off;
+  f.n_bias = boff;
+  int64_t zr = 0;
+  for (int k = 0; k < f.L; ++k) {
+    f.zrow[k] = zr;
+    zr += f.out_pad[k];
+  }
+  f.z_rows = zr;
+  auto add = [](FChunks& ct, int64_t src, int ot, int ks) {
+    for (int t = 0; t < ot; t += kFChunkTiles) {
+      ct.src[ct.n] = src + (int64_t)t * ks * 64;
+      ct.len[ct.n] = std::min(kFChunkTiles, ot - t) * ks * 64;
+      ct.cap = std::max(ct.cap, ct.len[ct.n]);
+      ++ct.n;
+    }
+  };
+  for (int k = 0; k < f.L; ++k) add(f.fct, a.f_off[k], a.f_otiles[k], a.f_ksteps[k]);
+  for (int k = f.L - 1; k >= 0; --k) add(f.bct, a.b_off2[k], a.b_otiles[k], a.b_ksteps[k]);
+  f.fct.cap = f.bct.cap = std::max(f.fct.cap, f.bct.cap);
+  return f.fct.n <= kFMaxChunks && f.bct.n <= kFMaxChunks;
+}
+
+// Workspace of the fused path for `batch` positions (bytes), laid out by fused_layout.
+struct FusedLayout {
+  int64_t pack, bias, y, dz, xt, ht, dzt, masks, dx, part, dbpart, total;  // byte offsets
+  int64_t bpad;
+  int splits, k_split, n_tiles;
+};
+
+FusedLayout fused_layout(const Shape& s, const FusedPlan& f, int64_t batch) {
+  FusedLayout l{};
+  l.bpad = ceil_div(std::max<int64_t>(batch, 1), kFPos) * kFPos;
+  int64_t o = 1024;  // after the QAT statistics at the start of the workspace
+  auto take = [&](int64_t bytes) {
+    const int64_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  l.pack = take(f.pack_n * 16);
+  l.bias = take((int64_t)f.n_bias * 4);
+  l.y = take(l.bpad * kFHeadLd * 4);
+  l.dz = take(l.bpad * kFHeadLd * 4);
+  l.xt = take((int64_t)16 * kFKS0 * l.bpad * 2);
+  l.ht = take((int64_t)(f.L - 1) * f.hid * l.bpad * 2);
+  l.dzt = take(f.z_rows * l.bpad * 2);
+  l.masks = take((l.bpad / 32) * (f.L - 1) * (f.T / 2) * 64 * 4);
+  l.dx = take(l.bpad * s.in_dim * 4);
+  l.n_tiles = 0;
+  for (int k = 0; k < f.L; ++k) l.n_tiles += (int)(ceil_div(s.layer_out[k], 128) * ceil_div(s.layer_in[k], 128));
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(512 / l.n_tiles, l.bpad / 256));
+  l.k_split = (int)(ceil_div(ceil_div(l.bpad, splits), 16) * 16);
+  l.splits = (int)ceil_div(l.bpad, l.k_split);
+  l.part = take((int64_t)l.n_tiles * l.splits * 128 * 128 * 4);
+  l.dbpart = take((int64_t)l.n_tiles * l.splits * 128 * 4);
+  l.total = o;
+  return l;
+}
+
+typedef void (*FwdKernel)(FwdArgs);
+typedef void (*BwdKernel)(BwdArgs);
+
+void fused_kernels(int hid, FwdKernel* fk, BwdKernel* bk) {
+  if (hid == 64) {
+    *fk = k_train_fwd<64, kFKS0, 1, kFHT>;
+    *bk = k_train_bwd<64, kFKS0, 1, kFHT>;
+  } else if (hid == 128) {
+    *fk = k_train_fwd<128, kFKS0, 2, kFHT>;
+    *bk = k_train_bwd<128, kFKS0, 2, kFHT>;
+  } else {
+    *fk = k_train_fwd<256, kFKS0, 2, kFHT>;
+    *bk = k_train_bwd<256, kFKS0, 2, kFHT>;
+  }
+}
+
+// Forward of the batch: packs the weights, then heads into y ([n][y_ld]); activations, masks and the
+// layer-0 inputs stay in the workspace for fused_backward.
+int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* weights, bool qat, const int32_t* ids,
+                  float* y, int y_ld) {
+  const Shape& s = c.s;
+  const FusedLayout l = fused_layout(s, f, c.n);
+  char* ws = reinterpret_cast<char*>(c.ws);
+  int st;
+  if (qat) {
+    st = qat_range(s, grid, c.stats(), c.strm);
+    if (st != NTBC_OK) return st;
+  }
+  PackTrainArgs pk = f.pk;
+  pk.w = weights;
+  pk.pack = reinterpret_cast<u32x4*>(ws + l.pack);
+  pk.bias = reinterpret_cast<float*>(ws + l.bias);
+  hipLaunchKernelGGL(k_pack_train, dim3(64, 2 * f.L), dim3(256), 0, c.strm, pk);
+  st = check_launch("k_pack_train");
+  if (st != NTBC_OK) return st;
+  FwdArgs a{};
+  a.grid = grid;
+  a.stats = qat ? c.stats() : nullptr;
+  a.ids = ids;
+  a.n = c.n;
+  a.n_positions = s.n_positions;
+  a.n_levels = s.n_levels;
+  a.base_res = s.base_res;
+  a.F = s.n_features;
+  a.blocks_w = s.blocks_w;
+  a.blocks_h = s.blocks_h;
+  a.in_dim = s.in_dim;
+  for (int i = 0; i <= s.n_levels; ++i) a.level_offset[i] = s.level_offset[i];
+  a.wpack = pk.pack;
+  a.bias = pk.bias;
+  for (int k = 0; k < f.L; ++k) a.bias_off[k] = f.pk.bias_off[k];
+  a.n_layers = f.L;
+  a.head_dim = s.head_dim;
+  a.n_bias = f.n_bias;
+  a.bpad = l.bpad;
+  a.xt = reinterpret_cast<uint16_t*>(ws + l.xt);
+  a.ht = reinterpret_cast<uint16_t*>(ws + l.ht);
+  a.masks = reinterpret_cast<uint32_t*>(ws + l.masks);
+  a.y = y;
+  a.y_ld = y_ld;
+  a.ct = f.fct;
+  FwdKernel fk;
+  BwdKernel bk;
+  fused_kernels(f.hid, &fk, &bk);
+  const size_t lds = (size_t)2 * f.fct.cap * 16 + (size_t)f.n_bias * 4;
+  NTBC_HIP(hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(fk, dim3((unsigned)(l.bpad / kFPos)), dim3(64 * kFW), lds, c.strm, a);
+  return check_launch("k_train_fwd");
+}
+
+// Backward of the batch from dZ of the head ([n][dz_ld]); the forward's workspace contents must be
+// current.  ADDS the gradients to d_grid and d_weights.
+int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, const int32_t* ids, const float* dz,
+                   int dz_ld, float* d_grid, float* d_weights) {
+  const Shape& s = c.s;
+  const FusedLayout l = fused_layout(s, f, c.n);
+  char* ws = reinterpret_cast<char*>(c.ws);
+  BwdArgs b{};
+  b.dz = dz;
+  b.dz_ld = dz_ld;
+  b.head_dim = s.head_dim;
+  b.n = c.n;
+  b.bpad = l.bpad;
+  b.wpack = reinterpret_cast<const u32x4*>(ws + l.pack);
+  b.masks = reinterpret_cast<const uint32_t*>(ws + l.masks);
+  b.dzt = reinterpret_cast<uint16_t*>(ws + l.dzt);
+  for (int k = 0; k < f.L; ++k) b.zrow[k] = f.zrow[k];
+  b.dx = reinterpret_cast<float*>(ws + l.dx);
+  b.in_dim = s.in_dim;
+  b.n_layers = f.L;
+  b.ct = f.bct;
+  FwdKernel fk;
+  BwdKernel bk;
+  fused_kernels(f.hid, &fk, &bk);
+  const size_t lds = (size_t)2 * f.bct.cap * 16;
+  NTBC_HIP(hipFuncSetAttribute((const void*)bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(bk, dim3((unsigned)(l.bpad / kFPos)), dim3(64 * kFW), lds, c.strm, b);
+  int st = check_launch("k_train_bwd");
+  if (st != NTBC_OK) return st;
+  st = scatter_grid(c, grid, qat, ids, b.dx, d_grid);
+  if (st != NTBC_OK) return st;
+  DwArgs d{};
+  const uint16_t* xt = reinterpret_cast<const uint16_t*>(ws + l.xt);
+  const uint16_t* ht = reinterpret_cast<const uint16_t*>(ws + l.ht);
+  int tile0 = 0;
+  for (int k = 0; k < f.L; ++k) {
+    DwJob& J = d.job[k];
+    J.a = b.dzt + f.zrow[k] * l.bpad;
+    J.a_rows = f.out_pad[k];
+    J.b = k == 0 ? xt : ht + (int64_t)(k - 1) * f.hid * l.bpad;
+    J.b_rows = k == 0 ? 16 * kFKS0 : f.hid;
+    J.M = s.layer_out[k];
+    J.N = s.layer_in[k];
+    J.tiles_n = (int)ceil_div(J.N, 128);
+    J.tile0 = tile0;
+    tile0 += (int)ceil_div(J.M, 128) * J.tiles_n;
+    J.c = d_weights + s.w_off[k];
+    J.db = d_weights + s.b_off[k];
+  }
+  d.n_jobs = f.L;
+  d.n_tiles = tile0;
+  d.splits = l.splits;
+  d.k_split = l.k_split;
+  d.bpad = l.bpad;
+  d.K = l.bpad;
+  d.part = reinterpret_cast<float*>(ws + l.part);
+  d.dbpart = reinterpret_cast<float*>(ws + l.dbpart);
+  hipLaunchKernelGGL(k_train_dw, dim3((unsigned)(d.n_tiles * d.splits)), dim3(256), 0, c.strm, d);
+  st = check_launch("k_train_dw");
+  if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_train_dw_reduce, dim3(16, (unsigned)d.n_tiles), dim3(256), 0, c.strm, d);
+  return check_launch("k_train_dw_reduce");
+}
+
+// dZ = dY * Y (1 - Y) with row strides (ntbc_backward: d_heads [n][head_dim], heads [n][y_ld]).
+__global__ void k_dsigmoid_ld(const float* __restrict__ dy, int ld_dy, const float* __restrict__ y, int ld_y,
+                              float* __restrict__ dz, int ld_dz, int64_t n, int cols) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * cols; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols;
+    const int k = (int)(i % cols);
+    const float yv = y[r * ld_y + k];
+    dz[r * ld_dz + k] = dy[r * ld_dy + k] * yv * (1.0f - yv);
+  }
+}
+
+
+// Byte offset of the deterministic scatter's region (after the unfused and fused layouts).
+int64_t det_offset(const Shape& s, int64_t batch) {
+  int64_t bytes = train_layout(s, batch).total * (int64_t)sizeof(float);
+  FusedPlan f;
+  if (fused_plan(s, &f)) bytes = std::max(bytes, fused_layout(s, f, batch).total);
+  return (bytes + 255) / 256 * 256;
+}
+
 }  // namespace
 
 namespace ntbc {
-int64_t train_workspace_bytes(const Shape& s, int64_t batch) { return train_layout(s, batch).total * (int64_t)sizeof(float); }
+// The unfused and fused layouts share the workspace; the deterministic scatter's 64-bit sums follow.
+int64_t train_workspace_bytes(const Shape& s, int64_t batch) {
+  return det_offset(s, batch) + 256 + s.grid_vertices * s.n_features * 8;
+}
 }  // namespace ntbc
 
 extern "C" int ntbc_forward(const ntbc_model_desc* d, const float* grid, const float* weights, int32_t qat,
@@ -1238,6 +2266,8 @@ extern "C" int ntbc_forward(const ntbc_model_desc* d, const float* grid, const f
   if (n == 0) return NTBC_OK;
   NTBC_REQUIRE(heads_out != nullptr, "heads_out is NULL");
   c.strm = as_stream(stream);
+  FusedPlan f;
+  if (c.bf16 && fused_plan(c.s, &f)) return fused_forward(c, f, grid, weights, qat != 0, ids, heads_out, c.s.head_dim);
   return forward(c, grid, weights, qat != 0, ids, heads_out);
 }
 
@@ -1251,6 +2281,20 @@ extern "C" int ntbc_backward(const ntbc_model_desc* d, const float* grid, const 
   if (n == 0) return NTBC_OK;
   NTBC_REQUIRE(d_heads != nullptr, "d_heads is NULL");
   c.strm = as_stream(stream);
+  FusedPlan f;
+  if (c.bf16 && fused_plan(c.s, &f)) {
+    const FusedLayout l = fused_layout(c.s, f, c.n);
+    char* ws = reinterpret_cast<char*>(c.ws);
+    float* y = reinterpret_cast<float*>(ws + l.y);
+    float* dz = reinterpret_cast<float*>(ws + l.dz);
+    st = fused_forward(c, f, grid, weights, qat != 0, ids, y, kFHeadLd);
+    if (st != NTBC_OK) return st;
+    hipLaunchKernelGGL(k_dsigmoid_ld, dim3((unsigned)std::min<int64_t>(ceil_div(c.n * c.s.head_dim, 256), 4096)), dim3(256), 0,
+                       c.strm, d_heads, c.s.head_dim, y, kFHeadLd, dz, kFHeadLd, c.n, c.s.head_dim);
+    st = check_launch("k_dsigmoid_ld");
+    if (st != NTBC_OK) return st;
+    return fused_backward(c, f, grid, qat != 0, ids, dz, kFHeadLd, d_grid, d_weights);
+  }
   float* y = c.ws + c.lay.y;
   st = forward(c, grid, weights, qat != 0, ids, y);
   if (st != NTBC_OK) return st;
@@ -1295,20 +2339,39 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   NTBC_REQUIRE(losses_out != nullptr, "losses_out is NULL");
   NTBC_REQUIRE(h->temperature > 0.0f && h->total_steps > 0 && h->warmup >= 0, "bad temperature or schedule");
   c.strm = as_stream(stream);
+  c.det = h->deterministic != 0;
   const Shape& s = c.s;
   const bool qat = h->qat != 0;
-  float* y = c.ws + c.lay.y;
-  st = forward(c, tsd->grid, tsd->weights, qat, batch_ids, y);
-  if (st != NTBC_OK) return st;
-  // dL/dZ of the head pre-activations straight from the loss kernel (the sigmoid derivative fused)
-  st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm, true);
-  if (st != NTBC_OK) return st;
   const int64_t ng = s.grid_vertices * s.n_features;
-  st = fill(tsd->d_grid, ng, 0.0f, c.strm);
-  if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
-  if (st != NTBC_OK) return st;
-  st = backward(c, tsd->grid, tsd->weights, qat, batch_ids, tsd->d_grid, tsd->d_weights);
-  if (st != NTBC_OK) return st;
+  FusedPlan f;
+  if (c.bf16 && fused_plan(s, &f)) {
+    // bfloat16 products with the layers chained in registers
+    const FusedLayout l = fused_layout(s, f, c.n);
+    char* ws = reinterpret_cast<char*>(c.ws);
+    float* y = reinterpret_cast<float*>(ws + l.y);
+    float* dz = reinterpret_cast<float*>(ws + l.dz);
+    st = fused_forward(c, f, tsd->grid, tsd->weights, qat, batch_ids, y, kFHeadLd);
+    if (st != NTBC_OK) return st;
+    st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, dz, c.strm, true, kFHeadLd);
+    if (st != NTBC_OK) return st;
+    st = fill(tsd->d_grid, ng, 0.0f, c.strm);
+    if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
+    if (st != NTBC_OK) return st;
+    st = fused_backward(c, f, tsd->grid, qat, batch_ids, dz, kFHeadLd, tsd->d_grid, tsd->d_weights);
+    if (st != NTBC_OK) return st;
+  } else {
+    float* y = c.ws + c.lay.y;
+    st = forward(c, tsd->grid, tsd->weights, qat, batch_ids, y);
+    if (st != NTBC_OK) return st;
+    // dL/dZ of the head pre-activations straight from the loss kernel (the sigmoid derivative fused)
+    st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm, true);
+    if (st != NTBC_OK) return st;
+    st = fill(tsd->d_grid, ng, 0.0f, c.strm);
+    if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
+    if (st != NTBC_OK) return st;
+    st = backward(c, tsd->grid, tsd->weights, qat, batch_ids, tsd->d_grid, tsd->d_weights);
+    if (st != NTBC_OK) return st;
+  }
   hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 1024)), dim3(256), 0,
                      c.strm, tsd->d_weights, s.n_weights, losses_out + 4);
   // learning rates of this step: linear warm-up, then cosine annealing to 0
@@ -1332,6 +2395,16 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 8192)), dim3(256), 0, c.strm,
                      tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, aa);
   return check_launch("k_adam");
+}
+
+extern "C" int ntbc_train_status(const float* losses, void* stream) {
+  NTBC_REQUIRE(losses != nullptr, "losses is NULL");
+  float flag = 0.0f;
+  NTBC_HIP(hipMemcpyAsync(&flag, losses + 4, sizeof(float), hipMemcpyDeviceToHost, as_stream(stream)));
+  NTBC_HIP(hipStreamSynchronize(as_stream(stream)));
+  if (flag != 0.0f)
+    return fail(NTBC_ENONFINITE, "the training step saw a non-finite loss or gradient; parameters and moments unchanged");
+  return NTBC_OK;
 }
 
 extern "C" int ntbc_quantize_grid(const ntbc_model_desc* d, const float* grid, uint8_t* codes, float* scale,

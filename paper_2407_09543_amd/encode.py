@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from . import ntbc, synth
+from . import ntbc, quality, synth
 
 
 @dataclasses.dataclass
@@ -90,8 +90,7 @@ def psnr_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats
     out = []
     for w, t, f in zip(words, textures, formats):
         dec = ntbc.decode(w.contiguous(), size, size, f)
-        mse = ((dec.float() - t.float()) ** 2).mean().item()
-        out.append(float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse))
+        out.append(quality.psnr(dec, t.reshape(dec.shape)))
     return out
 
 
@@ -99,7 +98,6 @@ def ssim_of_words(words: torch.Tensor, textures: Sequence[torch.Tensor], formats
                   crop: int = 1024) -> List[float]:
     """Decoded SSIM of every texture's blocks against its uncompressed texels, on the central
     crop x crop texels (SSIM on the host; the crop bounds its cost)."""
-    from . import quality
     crop = min(crop, size)
     c0 = (size - crop) // 2
     out = []
@@ -128,6 +126,5 @@ def downsampled_ref_psnr(textures: Sequence[torch.Tensor], formats, size: int) -
         small = torch.floor(small + 0.5).clamp(0, 255).to(torch.uint8).squeeze(-1).contiguous()
         dec = ntbc.decode(ntbc.encode_ref(small, f), half, half, f).reshape(half, half, -1).float()
         up = dec.repeat_interleave(2, dim=0).repeat_interleave(2, dim=1)
-        mse = ((up - x) ** 2).mean().item()
-        out.append(float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse))
+        out.append(quality.psnr(up, x))
     return out

@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libntbc.so")
 
-OK, EINVAL, EUNSUPPORTED, EHIP, ENOWORKSPACE = 0, -1, -2, -3, -5
+OK, EINVAL, EUNSUPPORTED, EHIP, ENONFINITE, ENOWORKSPACE = 0, -1, -2, -3, -4, -5
 BC1, BC4 = 1, 4
 FP32, BF16, FP8_E4M3, FP16 = 0, 1, 2, 3
 GRID_F32, GRID_U8 = 0, 1
@@ -58,7 +58,8 @@ class HParams(ctypes.Structure):
     _fields_ = [("lr_grid", ctypes.c_float), ("lr_mlp", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("temperature", ctypes.c_float),
                 ("warmup", ctypes.c_int32), ("total_steps", ctypes.c_int32), ("qat", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("loss_weights", ctypes.c_float * 4)]
+                ("precision", ctypes.c_int32), ("loss_weights", ctypes.c_float * 4),
+                ("deterministic", ctypes.c_int32)]
 
 
 _lib = None
@@ -93,6 +94,7 @@ _SIGNATURES = {
     "ntbc_train_step": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TrainStateC), ctypes.POINTER(TargetsC), _P,
                          _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P], ctypes.c_int),
     "ntbc_quantize_grid": ([ctypes.POINTER(ModelDesc), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "ntbc_train_status": ([_P, _P], ctypes.c_int),
     "ntbc_batch_ids": ([ctypes.c_uint64, _I64, _I32, _I64, _P, _P], ctypes.c_int),
 }
 
@@ -415,7 +417,8 @@ class Trainer:
 
     def __init__(self, desc: ModelDesc, grid: torch.Tensor, weights: torch.Tensor, targets: Targets, batch: int,
                  total_steps: int, lr_grid: float = 0.01, lr_mlp: float = 0.005, temperature: float = 0.01,
-                 warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0), precision: int = FP32):
+                 warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0), precision: int = FP32,
+                 deterministic: bool = False):
         self.desc = desc
         self.grid = grid.clone().contiguous()
         self.weights = weights.clone().contiguous()
@@ -430,7 +433,7 @@ class Trainer:
         self.state = TrainStateC(*[t.data_ptr() for t in (self.grid, self.weights, self.m_grid, self.v_grid,
                                                           self.m_w, self.v_w, self.d_grid, self.d_w)])
         self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, precision,
-                         (ctypes.c_float * 4)(*loss_weights))
+                         (ctypes.c_float * 4)(*loss_weights), int(deterministic))
 
     def step(self, ids: torch.Tensor, step: int, qat: bool = False) -> torch.Tensor:
         """One step on the batch ids (int32, device); returns the device losses[5] (overwritten)."""
@@ -439,6 +442,11 @@ class Trainer:
                                      _ptr(ids), ids.numel(), step, ctypes.byref(self.h), _ptr(self.losses),
                                      _ptr(self.ws), self.ws.numel(), _stream()))
         return self.losses
+
+    def status(self) -> int:
+        """ntbc_train_status of the last step: OK, or ENONFINITE when it skipped its update (waits for
+        the stream)."""
+        return lib().ntbc_train_status(_ptr(self.losses), _stream())
 
 
 def batch_ids(seed: int, step: int, batch: int, n_positions: int, out: Optional[torch.Tensor] = None,

@@ -95,3 +95,28 @@ class TrainProblem:
         import torch
         ids = synth.batch_ids(seed, 0, n, self.cfg.n_positions)
         return ids, torch.from_numpy(ids).cuda()
+
+
+def near_tie_positions(pb, y, ids, gap=1e-6):
+    """Positions where some texel's two smallest decoded-colour distances (either branch) differ by
+    less than `gap` but are not equal (equal distances to equal palette entries are harmless): there
+    the float32 and float64 argmax may differ."""
+    lay, tg = pb.tg_oracle.lay, pb.tg_oracle
+    n = len(ids)
+    bad = np.zeros(n, dtype=bool)
+    c_hat = y[:, lay.E:].reshape(n, 16, lay.C)
+    for t, f in enumerate(lay.formats):
+        e, ch = lay.ep_off[t], lay.channels(t)
+        sl = slice(lay.ch_off[t], lay.ch_off[t] + ch)
+        c = tg.c[ids][:, :, sl]
+        pr = tg.pal_ref[t][ids]
+        e0, e1 = y[:, e:e + ch], y[:, e + ch:e + 2 * ch]
+        ph, _, _ = ON.palette_real(e0, e1, f, e0[:, 0] > e1[:, 0])
+        for dist in (np.sqrt(((c[:, :, None, :] - ph[:, None]) ** 2).sum(-1)),
+                     np.sqrt(((c_hat[:, :, None, sl] - pr[:, None]) ** 2).sum(-1))):
+            s = np.sort(dist, axis=2)
+            g = s[:, :, 1] - s[:, :, 0]
+            bad |= ((g > 0) & (g < gap)).any(axis=1)
+        if f == 4:
+            bad |= np.abs(e0[:, 0] - e1[:, 0]) < gap          # BC4 mode switch of the prediction
+    return bad

@@ -32,6 +32,11 @@ TOL_FP16 = 2e-3
 TOL_FP16_P99 = 4e-4
 TOL_FP16_MEDIAN = 1e-6
 EMULATION = {ntbc.FP32: "f64", ntbc.BF16: "bf16", ntbc.FP16: "fp16"}
+# Block identity against the emulation of the same format.  Every differing block must be a tie (the
+# assertion below), so identity measures how many decisions sit within the accumulation-order noise of
+# a boundary; on these random O(1) models the lowest measured are 98.1% (BF16) and 99.70% (FP16), on
+# the 1024^2 five-texture uint8 case.  Floors: a regression that widens the noise shows here.
+MIN_IDENTITY = {ntbc.FP32: 0.999, ntbc.BF16: 0.97, ntbc.FP16: 0.995}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -79,6 +84,7 @@ def _check(cfg, layers, g, words, heads, ids, precision):
         assert dy.max() <= tol[0]
         assert np.percentile(dy, 99) <= tol[1]
         assert np.median(dy) <= tol[2]
+        assert ident >= MIN_IDENTITY[precision], ident
     assert res["ties"] == res["differ"], "a differing block is not a boundary tie"
     return ident
 

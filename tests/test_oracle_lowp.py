@@ -90,3 +90,34 @@ def test_fp8_emulation_is_exact_on_representable_operands():
     # and every scaled layer input stays inside the E4M3 range
     for h, (sx, _) in zip(hs, scales):
         assert np.abs(h / sx).max() <= 448.0
+
+
+def test_bf16_backward_emulation():
+    # the bfloat16 backward rounds every product operand (dZ, W, h) and sums the rounded dZ for the
+    # bias: (1) on operands that are bfloat16 values with exact float64 sums it equals the float64
+    # backward; (2) a dZ that is not a bfloat16 value enters every product rounded: moving one dZ entry
+    # by less than half a bfloat16 step changes none of the gradients, while the float64 backward moves
+    from oracle import mlp
+    rng = np.random.default_rng(5)
+    x = rng.integers(-4, 5, (6, 4)) / 4.0
+    layers = [(rng.integers(-3, 4, (5, 4)) / 8.0, rng.integers(-2, 3, 5) / 4.0),
+              (rng.integers(-3, 4, (3, 5)) / 8.0, rng.integers(-2, 3, 3) / 4.0)]
+    y, cache = mlp.forward(layers, x, "bf16")
+    _, cache64 = mlp.forward(layers, x, "f64")
+    assert all(np.array_equal(a, b) for a, b in zip(cache[1], cache64[1]))
+    dy = rng.integers(-8, 9, y.shape) / 64.0
+    # choose dL/dY so that dZ = dy exactly: divide out y (1 - y) in the caller's float64
+    d_y = dy / (y * (1.0 - y))
+    g16 = mlp.backward(layers, cache, d_y, y, "bf16")
+    g64 = mlp.backward(layers, cache64, d_y, y, "f64")
+    dz_exact = d_y * y * (1.0 - y)
+    assert np.allclose(dz_exact, dy, rtol=0, atol=1e-15)
+    for a, b in zip(g16[0] + g16[1] + [g16[2]], g64[0] + g64[1] + [g64[2]]):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-15)
+    # (2): perturb one head dZ by a third of a bfloat16 ulp
+    bump = np.zeros_like(d_y)
+    bump[2, 1] = (abs(dz_exact[2, 1]) * 2.0 ** -8 / 3.0 + 1e-300) / (y[2, 1] * (1.0 - y[2, 1]))
+    h16 = mlp.backward(layers, cache, d_y + bump, y, "bf16")
+    h64 = mlp.backward(layers, cache64, d_y + bump, y, "f64")
+    assert all(np.array_equal(a, b) for a, b in zip(h16[0] + h16[1], g16[0] + g16[1]))
+    assert not np.array_equal(h64[1][1], g64[1][1])

@@ -54,3 +54,23 @@ def test_ssim_closed_forms():
     # symmetric
     b = rng.integers(0, 256, (24, 24, 3))
     assert abs(quality.ssim(a, b) - quality.ssim(b, a)) < 1e-12
+
+
+def test_psnr_closed_forms_and_float64_sums():
+    # reported PSNR (Sec. 4.3): 10 log10(255^2 / MSE), squared error summed in float64
+    import torch
+    a = np.full((64, 64, 3), 100, np.uint8)
+    assert quality.psnr(a, a) == float("inf")
+    b = a + 1                                                   # MSE 1
+    assert abs(quality.psnr(b, a) - 20 * np.log10(255.0)) < 1e-12
+    c = a.copy()
+    c[0, 0, 0] = 0                                              # one error of 100 over 12,288 values
+    assert abs(quality.psnr(c, a) - 10 * np.log10(255.0 ** 2 * a.size / 100 ** 2)) < 1e-12
+    # a large image with a total squared error that float32 sums would round: exact in float64
+    big = np.zeros((4096, 4096), np.uint8)
+    noisy = big.copy()
+    noisy[::2, ::3] = 255
+    n255 = int((noisy == 255).sum())
+    assert quality.squared_error(noisy, big) == n255 * 255.0 ** 2
+    assert quality.squared_error(torch.from_numpy(noisy), torch.from_numpy(big)) == n255 * 255.0 ** 2
+    assert quality.psnr(torch.from_numpy(noisy), torch.from_numpy(big)) == quality.psnr(noisy, big)
