@@ -157,6 +157,22 @@ int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t pr
                       int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* ntbc_infer_blocks for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same computation and the same output, with the
+ * packed weights kept in a static device array of the library (4 MiB per GPU, held by every GPU the
+ * library runs on until the process ends; every model shape the library accepts fits, the largest
+ * needing 1.8 MB) instead of a caller workspace.  The calling thread's current
+ * device must be the device of `stream`; its scratch address is looked up on the first call on that
+ * device.  No hipMalloc, hipFree or other allocating routine is called.  Every call on one GPU shares
+ * that GPU's scratch, which keeps the last call's packed weights: calls that overlap on one GPU (on
+ * different streams, or from several host threads) race and must be serialised by the caller;
+ * p->flags & NTBC_REUSE_PACKED is valid only when the previous call on the device packed the same
+ * weights at the same precision.  Errors: as ntbc_infer_blocks, and NTBC_ENOWORKSPACE when the model's
+ * packed weights (ntbc_workspace_size(d, precision, 0)) exceed the scratch. */
+int ntbc_infer_blocks_noalloc(const ntbc_model_desc* d, const ntbc_params* p, int32_t precision,
+                              int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
+                              void* stream);
+
 /* FP8 E4M3 scales for ntbc_infer_blocks at NTBC_FP8_E4M3 (the paper has no FP8 path; per-layer,
  * per-tensor scaling as this library defines it): for every layer, s_w = the smallest power of two
  * with max|W| / s_w <= 448 (the largest finite E4M3 value; biases stay FP32) and s_x = the same for

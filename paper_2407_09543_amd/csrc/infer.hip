@@ -22,6 +22,7 @@
 // contiguous 16-byte (16-bit formats) or 4-byte (FP32) load; the copy is made by k_pack_lp / k_pack_f32
 // unless the caller says it is current.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1387,12 +1388,14 @@ extern "C" int ntbc_workspace_size(const ntbc_model_desc* d, int32_t precision, 
   return NTBC_OK;
 }
 
-extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* prm, int32_t precision,
-                                 int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
-                                 void* workspace, size_t workspace_bytes, void* stream) {
-  Plan p;
-  int st = make_plan(d, precision, &p);
-  if (st != NTBC_OK) return st;
+namespace {
+
+// ntbc_infer_blocks with the workspace already chosen (the caller's buffer, or the device's static
+// scratch array for ntbc_infer_blocks_noalloc); `p` is the plan of (d, precision).
+int infer_blocks(const Plan& p, const ntbc_model_desc* d, const ntbc_params* prm, int32_t precision,
+                 int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out, void* workspace,
+                 size_t workspace_bytes, void* stream) {
+  int st = NTBC_OK;
   const Shape& s = p.s;
   NTBC_REQUIRE(prm != nullptr && prm->grid != nullptr && prm->weights != nullptr, "params, grid or weights is NULL");
   if (d->grid_dtype == NTBC_GRID_U8)
@@ -1505,6 +1508,60 @@ extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* pr
     else hipLaunchKernelGGL((k_infer_f32<256, false>), grid, block, lds, strm, a);
   }
   return check_launch("ntbc_infer_blocks");
+}
+
+// Per-device scratch of ntbc_infer_blocks_noalloc: the packed weights and biases live here instead of
+// in a caller workspace.  Each GPU holds its own copy of the array until the process ends.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device id, set on first use
+
+// The device address of the current device's copy of `scratch` (the array's name is only a host-side
+// stand-in); looked up once per device.
+int scratch_address(void** out) {
+  int dev = -1;
+  NTBC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NTBC_EUNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(NTBC_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NTBC_OK;
+}
+
+}  // namespace
+
+extern "C" int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* prm, int32_t precision,
+                                 int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  Plan p;
+  int st = make_plan(d, precision, &p);
+  if (st != NTBC_OK) return st;
+  return infer_blocks(p, d, prm, precision, first_block, n_blocks, blocks_out, heads_out, workspace,
+                      workspace_bytes, stream);
+}
+
+extern "C" int ntbc_infer_blocks_noalloc(const ntbc_model_desc* d, const ntbc_params* prm, int32_t precision,
+                                         int64_t first_block, int64_t n_blocks, uint64_t* blocks_out,
+                                         float* heads_out, void* stream) {
+  Plan p;
+  int st = make_plan(d, precision, &p);
+  if (st != NTBC_OK) return st;
+  if ((size_t)p.total_bytes > kScratchBytes)
+    return fail(NTBC_ENOWORKSPACE, "model needs %lld bytes of packed weights, beyond the %zu-byte static scratch",
+                (long long)p.total_bytes, kScratchBytes);
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != NTBC_OK) return st;
+  return infer_blocks(p, d, prm, precision, first_block, n_blocks, blocks_out, heads_out, ws, kScratchBytes, stream);
 }
 
 extern "C" int ntbc_fp8_calibrate(const ntbc_model_desc* d, const ntbc_params* prm, int64_t n_sample, float* scales_out,

@@ -86,6 +86,8 @@ _SIGNATURES = {
     "ntbc_infer_batch": ([_P, _P, _P, _SZ, _P, _P], _I32),
     "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
                            _P, _SZ, _P], ctypes.c_int),
+    "ntbc_infer_blocks_noalloc": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
+                                   _P], ctypes.c_int),
     "ntbc_forward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _SZ, _P], ctypes.c_int),
     "ntbc_backward": ([ctypes.POINTER(ModelDesc), _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _SZ, _P],
                       ctypes.c_int),
@@ -274,6 +276,24 @@ class Model:
         p.flags = REUSE_PACKED if reuse_packed else 0
         _check(lib().ntbc_infer_blocks(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
                                        n_blocks, _ptr(out), _ptr(h), _ptr(ws), ws.numel(), _stream()))
+        return (out, h) if heads else out
+
+
+    def infer_noalloc(self, precision: int = BF16, first_block: int = 0, n_blocks: Optional[int] = None,
+                      heads: bool = False, out: Optional[torch.Tensor] = None, reuse_packed: bool = False):
+        """As infer(), through ntbc_infer_blocks_noalloc: the library's static per-device scratch holds the
+        packed weights, so the call allocates nothing on the device (pass `out` to allocate nothing here
+        either)."""
+        if n_blocks is None:
+            n_blocks = self.desc.blocks_w * self.desc.blocks_h - first_block
+        dev = self.weights.device
+        if out is None:
+            out = torch.empty((self.desc.n_textures, n_blocks), dtype=torch.int64, device=dev)
+        h = torch.empty((n_blocks, self.head_dim), dtype=torch.float32, device=dev) if heads else None
+        p = self.params()
+        p.flags = REUSE_PACKED if reuse_packed else 0
+        _check(lib().ntbc_infer_blocks_noalloc(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
+                                               n_blocks, _ptr(out), _ptr(h), _stream()))
         return (out, h) if heads else out
 
 
