@@ -158,30 +158,12 @@ def batched_decode(torch, ntbc, synth, reps=10):
     3-5 textures, random parameters of those shapes): one batched BF16 launch per kernel instance,
     replayed from a HIP graph, against per-material FP32 launches of the same block grids (and, for
     context, per-material BF16 launches)."""
+    from paper_2407_09543_amd import autotune
     dev = torch.device("cuda:0")
-    entries, mat_of, per_mat = [], [], []
-    for m in range(16):
-        size, width, nt = 512 << (m % 4), 64 * (1 + m // 4), 3 + (m % 3)
-        n_bc1 = min(2, nt - 1)
-        cfg = synth.ModelConfig(8, 8, 8, True, width, 3, tuple([synth.BC1] * n_bc1 + [synth.BC4] * (nt - n_bc1)),
-                                size // 4, size // 4)
-        layers = synth.init_weights(cfg, 100 + m)
-        codes, _, _ = synth.random_u8_grid(cfg, 100 + m)
-        model = ntbc.Model(ntbc.desc_from_config(cfg), torch.from_numpy(synth.flatten_weights(layers)).to(dev),
-                           torch.from_numpy(codes).to(dev),
-                           torch.from_numpy(np.full(cfg.n_levels, 0.7 / 128, np.float32)).to(dev),
-                           torch.from_numpy(np.full(cfg.n_levels, 128, np.int32)).to(dev))
-        mips = []
-        level = 0
-        while (cfg.blocks_w >> level) >= 1:
-            d = ntbc.mip_desc(model.desc, level)
-            entries.append((model, d, 0, d.blocks_w * d.blocks_h))
-            mat_of.append(m)
-            mips.append(ntbc.Model(d, model.weights, model.grid, model.grid_scale, model.grid_zero))
-            level += 1
-        per_mat.append(mips)
+    entries, mat_of, per_mat = autotune.batched_decode_workload()
     n_blocks = sum(e[1].n_textures * e[3] for e in entries)
-    batch = ntbc.Batch(entries, ntbc.BF16)
+    batch = ntbc.Batch(entries, ntbc.BF16)  # tile shapes from the committed autotuner table
+    tile_shapes = {autotune.key(g): g["waves"] for g in batch.groups()}
     stamps = torch.zeros(len(entries) + 1, dtype=torch.int64, device=dev)
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
@@ -229,6 +211,7 @@ def batched_decode(torch, ntbc, synth, reps=10):
                                    "latency_us_p50": float(np.percentile(lat_us, 50)),
                                    "latency_us_p99": float(np.percentile(lat_us, 99)),
                                    "stamp_span_us": float(0.01 * ticks.max())},
+            "tile_waves": tile_shapes, "tile_table": autotune.TABLE_PATH if os.path.exists(autotune.TABLE_PATH) else None,
             "per_material_fp32": per_fp32, "per_material_bf16": per_bf16,
             "latency_note": "batched: completion of a material's last mip since the batch start (100 MHz "
                             "real-time counter); per-material: completion since the first launch of the "
@@ -336,8 +319,14 @@ def main():
             "ssim_central_1024": {"ntbc": encode.ssim_of_words(res.ntbc_words, tex, cfg.formats, args.size),
                                   "after_judge": encode.ssim_of_words(res.words, tex, cfg.formats, args.size),
                                   "ref_encoder": encode.ssim_of_words(torch.stack(ref), tex, cfg.formats, args.size)},
-            "judge": {"kappa": args.kappa, "delta": 0.0, "fallback_blocks": res.fallback_blocks},
+            "judge": {"kappa": args.kappa, "delta": 0.0, "fallback_blocks": res.fallback_blocks,
+                      "exception_list_bytes": sum(encode.exception_list_bytes(c, cfg.n_positions)
+                                                  for c in res.fallback_blocks)},
             "model_bytes_bf16_weights": encode.model_bytes(cfg, 2), "bc_bytes": bc_bytes,
+            "total_bytes_after_judge": encode.model_bytes(cfg, 2) + sum(
+                encode.exception_list_bytes(c, cfg.n_positions) for c in res.fallback_blocks),
+            "judge_sweep": encode.judge_sweep(res.ntbc_words, res.ref_words, tex, cfg.formats, args.size,
+                                              encode.model_bytes(cfg, 2)),
             "storage_matched_baseline": {"what": "reference BC of the 2x2-averaged texture, nearest upsampled",
                                          "bytes": bc_bytes // 4,
                                          "psnr_db": encode.downsampled_ref_psnr(tex, cfg.formats, args.size)},

@@ -57,8 +57,9 @@ extern "C" {
 
 #define NTBC_FP32 0               /* MLP in FP32 (FP32 matrix cores), FP32 accumulation             */
 #define NTBC_BF16 1               /* MLP weights and layer inputs in BF16, FP32 accumulation         */
-#define NTBC_FP8_E4M3 2           /* MLP weights and layer inputs in FP8 E4M3 (OCP) with per-layer
-                                     power-of-two scales, FP32 accumulation (ntbc_fp8_calibrate)     */
+#define NTBC_FP8_E4M3 2           /* middle hidden layers in FP8 E4M3 (OCP) with per-layer power-of-two
+                                     scales (ntbc_fp8_calibrate); the first layer and the head in
+                                     BF16; FP32 accumulation                                         */
 #define NTBC_FP16 3               /* MLP weights and layer inputs in IEEE half, FP32 accumulation    */
 
 #define NTBC_GRID_F32 0
@@ -115,7 +116,8 @@ int ntbc_workspace_size(const ntbc_model_desc* d, int32_t precision, int64_t bat
 /* Reference encoder (Sec. 3.2 and Sec. 4.1: the reference blocks that are the training targets;
  * also the fallback).  The encoding is the project's integer REF-BC1 / REF-BC4 algorithm (two
  * candidates, exact nearest-code selection, two least-squares refinement steps in exact integer
- * arithmetic), bit-reproducible.  texels: uint8 texture (3 channels for BC1, 1 for BC4), `row_pitch`
+ * arithmetic; BC1 blocks of one colour also try the optimal single-colour endpoints, whose 2/3 point
+ * is the nearest value any BC1 palette entry can take in each channel), bit-reproducible.  texels: uint8 texture (3 channels for BC1, 1 for BC4), `row_pitch`
  * bytes per row.  blocks_out: uint64[(height/4)*(width/4)].  Optional sse_out (may be NULL): int32
  * per block, integer squared error of the decoded block against the texels. */
 int ntbc_bc_encode_ref(const uint8_t* texels, int32_t width, int32_t height, int32_t row_pitch,
@@ -151,8 +153,8 @@ int ntbc_fallback(const uint64_t* ntbc, const uint64_t* ref, const int32_t* sse_
  * blocks_out: uint64[n_textures][n_blocks].  heads_out (optional, may be NULL): float
  * [n_blocks][head_dim] sigmoid outputs.  workspace: >= ntbc_workspace_size(d, precision, 0).
  * Precisions: NTBC_FP32, NTBC_BF16, NTBC_FP16, and NTBC_FP8_E4M3 with p->fp8_scales set (from
- * ntbc_fp8_calibrate; FP8 needs head_dim <= 192, in_dim <= 64 and a hidden layer, else
- * NTBC_EUNSUPPORTED). */
+ * ntbc_fp8_calibrate; FP8 needs head_dim <= 192, in_dim <= 64 and two hidden layers, else
+ * NTBC_EUNSUPPORTED; its first layer and head take BF16 operands, the layers between them E4M3). */
 int ntbc_infer_blocks(const ntbc_model_desc* d, const ntbc_params* p, int32_t precision,
                       int64_t first_block, int64_t n_blocks, uint64_t* blocks_out, float* heads_out,
                       void* workspace, size_t workspace_bytes, void* stream);
@@ -211,6 +213,19 @@ int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, int32_t preci
 
 /* Packs every distinct model's weights into the workspace (once; again after the weights change). */
 int ntbc_batch_pack(const void* table, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The kernel instances of a plan (one launch each): n_groups receives their count and, when groups_out
+ * is not NULL, groups_out[8 g .. 8 g + 7] = precision, hidden width, first-layer K-steps, unrolled
+ * middle layers (-1: a run-time count), BC1 and BC4 textures of the register epilogue (-1: heads staged
+ * in LDS), tile waves, items, for g < min(*n_groups, max_groups).  Host only. */
+int ntbc_batch_groups(const void* table, int32_t* groups_out, int32_t max_groups, int32_t* n_groups);
+
+/* Tile shape of one kernel instance of a plan: `waves` (2, 4 or 8) waves of 32 block positions per
+ * workgroup (4 after ntbc_batch_plan; 2 and 8 exist for BF16 only, else NTBC_EUNSUPPORTED; a shape
+ * whose LDS does not fit returns NTBC_EINVAL).  Rewrites the host table; the caller copies it to its
+ * device copy again before ntbc_infer_batch.  The blocks do not depend on the shape.  Host only.  This
+ * is what the tile autotuner (paper_2407_09543_amd.autotune) times. */
+int ntbc_batch_set_waves(void* table, int32_t group, int32_t waves);
 
 /* Decodes every item of a plan: `table` is the host image, `table_device` the caller's device copy of
  * it.  stamps (optional, device uint64[n_items + 1]): [0] = the real-time counter (100 MHz) when the
@@ -302,7 +317,7 @@ int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float*
  * backward, then dense Adam on grid and weights with the learning rates of step `step` (0-based) of the
  * schedule.  losses_out (device float[5]) receives the
  * four losses and the skip flag: when a non-finite value is seen the parameters and moments are left
- * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions. */
+ * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions.  */
 int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const ntbc_targets* t,
                     const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
                     float* losses_out, void* workspace, size_t workspace_bytes, void* stream);

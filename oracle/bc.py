@@ -40,6 +40,12 @@ REF-BC1, per block of texels p_i (i = 0..15, 8-bit RGB):
      rounded to 5/6 bits as round-half-up of (num/D)*31/255 (resp. 63/255) after clamping num to
      [0, 255 D]; steps 4-5 are redone, and the result is kept only if the block SSE strictly falls.
      D = 0 skips the step.
+  8. A block whose 16 texels are one colour (r, g, b) also tries the optimal single-colour endpoints:
+     per channel, from a table over the 256 values, the code pair (a, b) (5 bits for R and B, 6 for G)
+     whose four-colour 2/3 point (2 E(a) + E(b) + 1) // 3 (E = bit replication) is nearest to the
+     value, ties to the smallest a, then the smallest b; every palette entry of every BC1 block is such
+     a point, so the per-channel error is the least any block can reach.  Steps 4-5 are redone with
+     q0 = (a_r, a_g, a_b), q1 = (b_r, b_g, b_b), and the result is kept if the block SSE strictly falls.
 REF-BC4, per block of 8-bit values v_i:
   1. Candidate 8: e0 = max, e1 = min (e0 == e1 makes it the six-value mode with every texel on e0).
   2. Candidate 6: e0 = min, e1 = max over texels other than 0 and 255 (none: e0 = e1 = 0).
@@ -260,6 +266,24 @@ def _select(mask, new, old):
                  for nv, o in zip(new, old))
 
 
+def single_colour_table(bits: int):
+    """[256, 2] code pairs (a, b) of `bits`-bit endpoints: for value v, the pair whose four-colour 2/3
+    point (2 E(a) + E(b) + 1) // 3 is nearest to v; ties to the smallest a, then the smallest b (step 8
+    of REF-BC1)."""
+    n = 1 << bits
+    e = expand5(np.arange(n)) if bits == 5 else expand6(np.arange(n))
+    pts = (2 * e[:, None] + e[None, :] + 1) // 3                 # [a, b]
+    table = np.zeros((256, 2), dtype=np.int64)
+    for v in range(256):
+        k = int(np.argmin(np.abs(pts - v)))                      # first in (a, b) order
+        table[v] = (k // n, k % n)
+    return table
+
+
+_SINGLE5 = None
+_SINGLE6 = None
+
+
 def bc1_encode_ref(blocks, return_sse: bool = False):
     """REF-BC1 on texel blocks uint8 [nb, 16, 3] -> BC1 words uint64 [nb] (and block SSE)."""
     p = np.asarray(blocks, dtype=np.int64)
@@ -287,6 +311,17 @@ def bc1_encode_ref(blocks, return_sse: bool = False):
         ok, qa, qb = _bc1_refine(st[3], p)
         new = _bc1_finish(qa, qb, p)
         st = _select(ok & (new[4] < st[4]), new, st)
+    # step 8: single-colour blocks
+    global _SINGLE5, _SINGLE6
+    if _SINGLE5 is None:
+        _SINGLE5, _SINGLE6 = single_colour_table(5), single_colour_table(6)
+    uniform = (p == p[:, :1, :]).all(axis=(1, 2))
+    if uniform.any():
+        v = p[:, 0, :]
+        q0 = np.stack([_SINGLE5[v[:, 0], 0], _SINGLE6[v[:, 1], 0], _SINGLE5[v[:, 2], 0]], axis=-1)
+        q1 = np.stack([_SINGLE5[v[:, 0], 1], _SINGLE6[v[:, 1], 1], _SINGLE5[v[:, 2], 1]], axis=-1)
+        new = _bc1_finish(q0, q1, p)
+        st = _select(uniform & (new[4] < st[4]), new, st)
     words = bc1_pack(st[0], st[1], st[2])
     return (words, st[4]) if return_sse else words
 

@@ -11,9 +11,11 @@ emulates a reduced-precision matrix path with float64 accumulation:
 
   * ``"bf16"``: every layer input and every weight rounded to bfloat16 (round-to-nearest-even);
   * ``"fp16"``: the same with IEEE half precision (the paper's network precision);
-  * ``"fp8"``: per-layer scales (s_x, s_w); the layer input is rounded to E4M3 as x / s_x, the weight
-    as W * (1/s_w) evaluated in float32 (the GPU path's precision for this integer decision), and the
-    product is rescaled by s_x * s_w before the bias is added.
+  * ``"fp8"``: the middle hidden layers (every layer but the first and the head) take E4M3 operands
+    with per-layer scales (s_x, s_w): the layer input is rounded to E4M3 as x / s_x, the weight as
+    W * (1/s_w) evaluated in float32 (the GPU path's precision for this integer decision), and the
+    product is rescaled by s_x * s_w before the bias is added.  The first layer (the grid features)
+    and the head (whose outputs decide 8-bit endpoints) take bfloat16 operands as in ``"bf16"``.
 
 FP8 scales (the paper has no FP8 path; this is the reading used here): per layer and per tensor, the
 smallest power of two s with max|v| / s <= 448 (the largest finite E4M3 value), so that v / s is exact
@@ -55,6 +57,8 @@ def forward(layers, x, precision: str = "f64", scales=None):
             z = lowp.round_bf16(h) @ lowp.round_bf16(w).T + b
         elif precision == "fp16":
             z = lowp.round_fp16(h) @ lowp.round_fp16(w).T + b
+        elif precision == "fp8" and (k == 0 or k == n_layers - 1):
+            z = lowp.round_bf16(h) @ lowp.round_bf16(w).T + b
         elif precision == "fp8":
             s_x, s_w = float(scales[k][0]), float(scales[k][1])
             xq = lowp.round_e4m3(h / s_x)

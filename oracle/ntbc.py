@@ -359,8 +359,10 @@ class TrainState:
 
 
 def gradients(cfg, grid, layers, tg: Targets, ids, qat: bool, temp: float = 0.01,
-              terms=(1.0, 1.0, 1.0, 1.0)):
-    """Losses and gradients (d grid, [(dW, db)]) at the given parameters for batch ids."""
+              terms=(1.0, 1.0, 1.0, 1.0), precision: str = "f64"):
+    """Losses and gradients (d grid, [(dW, db)]) at the given parameters for batch ids.  precision
+    "bf16" evaluates the MLP forward and backward with bfloat16 product operands (mlp.forward and
+    mlp.backward); the losses, the grid and its scatter stay float64."""
     ids = np.asarray(ids, dtype=np.int64)
     if qat:
         gvals, mask = G.fake_quant_grid(grid, cfg.n_levels, cfg.base_res)
@@ -369,9 +371,9 @@ def gradients(cfg, grid, layers, tg: Targets, ids, qat: bool, temp: float = 0.01
     levels = G.split_levels(gvals, cfg.n_levels, cfg.base_res)
     bx, by = ids % cfg.blocks_w, ids // cfg.blocks_w
     x = G.features(levels, bx, by, cfg.blocks_w, cfg.blocks_h)
-    y, cache = mlp.forward(layers, x)
+    y, cache = mlp.forward(layers, x, precision)
     losses, dy = loss_and_grad(y, tg, ids, temp, terms)
-    dws, dbs, dx = mlp.backward(layers, cache, dy, y)
+    dws, dbs, dx = mlp.backward(layers, cache, dy, y, precision)
     dgrid = G.features_backward(dx, bx, by, cfg.blocks_w, cfg.blocks_h, cfg.n_levels, cfg.base_res,
                                 cfg.n_features, mask)
     return losses, dgrid, list(zip(dws, dbs)), y

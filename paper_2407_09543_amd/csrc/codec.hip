@@ -23,6 +23,8 @@
 //   BC4: candidates (max, min) and (min, max) of the texels other than 0/255; two least-squares steps
 //   each in its own mode (sevenths, or fifths without the 0/255 texels), dropped if they leave the mode
 //   or do not lower the SSE; the smaller SSE wins (ties: the first).
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -146,6 +148,40 @@ __device__ void bc1_refine(Bc1Enc& st, const int p[16][3]) {
   if (nw.sse < st.sse) st = nw;
 }
 
+// Optimal single-colour endpoints (step 8 of REF-BC1): for every value v, the code pair (a, b) of 5-bit
+// (g_single5) or 6-bit (g_single6) endpoints whose four-colour 2/3 point (2 E(a) + E(b) + 1) / 3 is
+// nearest to v, ties to the smallest a, then the smallest b; entry = a | b << 8.  Filled on the device
+// by k_single_colour_init before each encode (the same values every time): one workgroup per (value,
+// table), its threads taking every 256th candidate pair and the minimum of (error, a, b) reduced in
+// that order.
+__device__ uint16_t g_single5[256];
+__device__ uint16_t g_single6[256];
+
+__global__ void __launch_bounds__(256) k_single_colour_init() {
+  __shared__ unsigned best_s[4];
+  const int v = blockIdx.x;
+  const int bits = blockIdx.y == 0 ? 5 : 6;
+  const int n = 1 << bits;
+  unsigned best = 0xFFFFFFFFu;  // error << 16 | a << 8 | b: the smallest error, then a, then b
+  for (int k = threadIdx.x; k < n * n; k += 256) {
+    const int a = k / n, b = k % n;
+    const int ea = bits == 5 ? expand5(a) : expand6(a), eb = bits == 5 ? expand5(b) : expand6(b);
+    const unsigned key = ((unsigned)abs((2 * ea + eb + 1) / 3 - v) << 16) | ((unsigned)a << 8) | (unsigned)b;
+    best = key < best ? key : best;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned o = (unsigned)__shfl_xor((int)best, off);
+    best = o < best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0) best_s[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) best = best_s[w] < best ? best_s[w] : best;
+    (bits == 5 ? g_single5 : g_single6)[v] = (uint16_t)(((best >> 8) & 255u) | ((best & 255u) << 8));
+  }
+}
+
 __device__ Bc1Enc bc1_encode_block(const int p[16][3]) {
   // candidate A: farthest pair
   int best = -1, bi = 0, bj = 1;
@@ -197,6 +233,17 @@ __device__ Bc1Enc bc1_encode_block(const int p[16][3]) {
   if (stb.sse < st.sse) st = stb;
   bc1_refine(st, p);
   bc1_refine(st, p);
+  // step 8: a one-colour block also tries the optimal single-colour endpoints
+  bool uniform = true;
+#pragma unroll
+  for (int i = 1; i < 16; ++i) uniform &= p[i][0] == p[0][0] && p[i][1] == p[0][1] && p[i][2] == p[0][2];
+  if (uniform) {
+    const uint32_t r = g_single5[p[0][0]], g = g_single6[p[0][1]], b = g_single5[p[0][2]];
+    const int q0[3] = {(int)(r & 255u), (int)(g & 255u), (int)(b & 255u)};
+    const int q1[3] = {(int)(r >> 8), (int)(g >> 8), (int)(b >> 8)};
+    const Bc1Enc sc = bc1_finish(q0, q1, p);
+    if (sc.sse < st.sse) st = sc;
+  }
   return st;
 }
 
@@ -463,16 +510,26 @@ __global__ void __launch_bounds__(kThreads) k_fallback(const uint64_t* __restric
                                                  const int32_t* __restrict__ sse_r, int64_t n, float kappa,
                                                  float delta, uint64_t* __restrict__ out,
                                                  int32_t* __restrict__ count) {
-  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  bool replaced = false;
-  if (b < n) {
-    const float limit = kappa * (float)sse_r[b] + delta;
-    replaced = (float)sse_n[b] > limit;
-    out[b] = replaced ? ref_words[b] : ntbc_words[b];
+  // grid-stride over the blocks; the replaced count is summed per wavefront (ballot), then per
+  // workgroup in LDS, and added with one atomic per workgroup (same-address atomics serialise)
+  __shared__ int part[kThreads / 64];
+  int mine = 0;
+  for (int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x; b - threadIdx.x < n; b += (int64_t)gridDim.x * kThreads) {
+    bool replaced = false;
+    if (b < n) {
+      const float limit = kappa * (float)sse_r[b] + delta;
+      replaced = (float)sse_n[b] > limit;
+      out[b] = replaced ? ref_words[b] : ntbc_words[b];
+    }
+    mine += (int)__popcll(__ballot(replaced));
   }
-  // one atomic per wavefront
-  const unsigned long long ballot = __ballot(replaced);
-  if ((threadIdx.x & 63) == 0 && ballot != 0ull) atomicAdd(count, (int32_t)__popcll(ballot));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < kThreads / 64; ++w) tot += part[w];
+    if (tot != 0) atomicAdd(count, tot);
+  }
 }
 
 int check_texture(const void* tex, int32_t width, int32_t height, int32_t pitch, int32_t format) {
@@ -495,9 +552,11 @@ extern "C" int ntbc_bc_encode_ref(const uint8_t* texels, int32_t width, int32_t 
   const int bw = width / 4, bh = height / 4;
   const int64_t n = (int64_t)bw * bh;
   const dim3 grid((unsigned)ntbc::ceil_div(n, kThreads));
-  if (format == NTBC_BC1)
+  if (format == NTBC_BC1) {
+    hipLaunchKernelGGL(k_single_colour_init, dim3(256, 2), dim3(256), 0, ntbc::as_stream(stream));
     hipLaunchKernelGGL(k_encode_ref_bc1, grid, dim3(kThreads), 0, ntbc::as_stream(stream), texels, bw, bh,
                        row_pitch, blocks_out, sse_out);
+  }
   else
     hipLaunchKernelGGL(k_encode_ref_bc4, grid, dim3(kThreads), 0, ntbc::as_stream(stream), texels, bw, bh,
                        row_pitch, blocks_out, sse_out);
@@ -539,7 +598,7 @@ extern "C" int ntbc_fallback(const uint64_t* ntbc_words, const uint64_t* ref, co
   NTBC_REQUIRE(ntbc_words && ref && sse_ntbc && sse_ref && out && n_fallback, "NULL pointer argument");
   NTBC_REQUIRE(n_blocks >= 0, "n_blocks %lld < 0", (long long)n_blocks);
   if (n_blocks == 0) return NTBC_OK;
-  hipLaunchKernelGGL(k_fallback, dim3((unsigned)ntbc::ceil_div(n_blocks, kThreads)), dim3(kThreads), 0,
+  hipLaunchKernelGGL(k_fallback, dim3((unsigned)std::min<int64_t>(ntbc::ceil_div(n_blocks, kThreads), 1024)), dim3(kThreads), 0,
                      ntbc::as_stream(stream), ntbc_words, ref, sse_ntbc, sse_ref, n_blocks, kappa, delta, out,
                      n_fallback);
   return ntbc::check_launch("ntbc_fallback");

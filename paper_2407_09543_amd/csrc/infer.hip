@@ -30,8 +30,9 @@
 
 // The build compiles this file once per part so that the many kernel instances compile in parallel:
 // NTBC_INFER_PART = 0 holds the host code, the FP32 kernels and the weight packing, 1-3 the
-// single-range 16-bit/FP8 instances (BF16, FP16, FP8), 4-6 the batched ones.  Without the macro one
-// translation unit holds everything.
+// single-range 16-bit/FP8 instances (BF16, FP16, FP8), 4-6 the batched ones (BF16 with 4-wave tiles,
+// FP16, FP8), 7-8 the BF16 batched ones with 2- and 8-wave tiles.  Without the macro one translation
+// unit holds everything.
 #ifndef NTBC_INFER_PART
 #define NTBC_INFER_PART -1
 #endif
@@ -166,8 +167,10 @@ template <Lp L>
 __global__ void k_pack_lp(PackArgs a, typename LpOp<L>::type* __restrict__ pack, float* __restrict__ bias) {
   const int layer = blockIdx.y;
   if (layer >= a.n_layers) return;
-  // FP8: W * (1/s_w) in float32 (exact for the power-of-two scales), then E4M3
-  const float inv_w = L == Lp::FP8 ? 1.0f / a.fp8_scales[2 * layer + 1] : 1.0f;
+  // FP8 mode: the middle layers as E4M3 of W * (1/s_w) in float32 (exact for the power-of-two scales);
+  // the first layer and the head as bfloat16 operands, each filling two 8-byte units
+  const bool wide = L == Lp::FP8 && (layer == 0 || layer == a.n_layers - 1);
+  const float inv_w = L == Lp::FP8 && !wide ? 1.0f / a.fp8_scales[2 * layer + 1] : 1.0f;
   const int64_t total = (int64_t)a.otiles[layer] * a.ksteps[layer] * 64;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int l = (int)(e % 64);
@@ -184,6 +187,12 @@ __global__ void k_pack_lp(PackArgs a, typename LpOp<L>::type* __restrict__ pack,
                  : 0.0f;
     }
     if constexpr (L == Lp::FP8) {
+      if (wide) {
+        const u32x4 w16 = x8_of<Lp::BF16>(v);
+        pack[a.pack_off[layer] + 2 * e] = u32x2{w16[0], w16[1]};
+        pack[a.pack_off[layer] + 2 * e + 1] = u32x2{w16[2], w16[3]};
+        continue;
+      }
 #pragma unroll
       for (int m = 0; m < 8; ++m) v[m] *= inv_w;
     }
@@ -500,6 +509,39 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16_t& acc, const float
   }
 }
 
+// FP8 E4M3 mode takes bfloat16 operands in the first layer and the head and E4M3 operands in the
+// middle hidden layers.  First layer -> middle: the bias-initialised accumulators, ReLU, divided by the
+// next layer's s_x (an exact power of two), rounded to E4M3.
+__device__ __forceinline__ void epi_bf16_to_fp8(const f32x16_t& acc, u32x2* lo, u32x2* hi, float inv_next) {
+  float r[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const float z = acc[v];
+    r[v] = (z < 0.0f ? 0.0f : z) * inv_next;
+  }
+  *lo = x8_of<Lp::FP8>(r);
+  *hi = x8_of<Lp::FP8>(r + 8);
+}
+
+// Last middle layer -> head: z = acc * (s_x s_w) + b, ReLU, rounded to bfloat16 (bias4[q] = the four
+// consecutive neurons 32t + 8q + 4g .. +3).
+__device__ __forceinline__ void epi_fp8_to_bf16(const f32x16_t& acc, const float* bt, int g, u32x4* lo, u32x4* hi,
+                                                float mul) {
+  float r[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 b = *reinterpret_cast<const float4*>(bt + 8 * q + 4 * g);
+    const float bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float z = acc[4 * q + k] * mul + bv[k];
+      r[4 * q + k] = z < 0.0f ? 0.0f : z;
+    }
+  }
+  *lo = x8_of<Lp::BF16>(r);
+  *hi = x8_of<Lp::BF16>(r + 8);
+}
+
 // One chunk of a layer: output tiles tc*CT .. tc*CT+CT-1 (those below `valid`) over KS K-steps, the
 // A fragments read from LDS kPrefetch K-steps ahead of their product.
 constexpr int kPrefetch = 4;
@@ -569,6 +611,29 @@ __device__ __forceinline__ void hidden_layer(const typename LpOp<L>::type (&in)[
     for (int u = 0; u < CT; ++u) {
       const int t = CT * tc + u;
       hidden_epilogue<L>(acc[u], bl + 32 * t, g, &out[2 * t], &out[2 * t + 1], mul, inv_next);
+    }
+    wait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+// The last middle hidden layer of FP8 mode: E4M3 products, outputs rounded to bfloat16 for the head.
+template <int S, int T, int CT, int PR, int NT, int CH>
+__device__ __forceinline__ void last_middle_fp8(const u32x2 (&in)[S], u32x4 (&out)[S], const float* bl, float mul,
+                                                const u32x4* __restrict__ wp, const ChunkTable& ct, u32x4* smem, int& c,
+                                                int tid, int lane, int g) {
+#pragma unroll
+  for (int tc = 0; tc < T / CT; ++tc) {
+    if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+    f32x16_t acc[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) acc[u] = f32x16_t{};
+    chunk_mfma<Lp::FP8, S, CT, S>(reinterpret_cast<const u32x2*>(smem + (c & 1) * CH), S, in, lane, CT, acc);
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const int t = CT * tc + u;
+      epi_fp8_to_bf16(acc[u], bl + 32 * t, g, &out[2 * t], &out[2 * t + 1], mul);
     }
     wait_dma();
     __syncthreads();
@@ -656,19 +721,33 @@ __device__ __forceinline__ void reg_epilogue(ArgsT a, const f32x16_t (&h)[kHeadT
 #undef NTBC_SLOT
 }
 
-// The fused network of one tile of kLdsWaves * 32 block positions (tile index `tile` of the range
+// The head's input: the last hidden layer's operands, which FP8 mode rounds to bfloat16 separately.
+template <bool MIX, typename A, typename B>
+__device__ __forceinline__ const B& pick_head_input(const A& bin, const B& hb) {
+  if constexpr (MIX)
+    return hb;
+  else
+    return bin;
+}
+
+// The fused network of one tile of W * 32 block positions (W waves; tile index `tile` of the range
 // a.first .. a.first + a.n).
 // ArgsT/ChunksT: by value for the single-range kernel (its by-value parameters are then read in place
 // from the kernel-argument segment), references for work items in device memory.
 template <Lp L, int HID, int KS0, int NH, int NB1 = -1, int NB4 = 0, typename ArgsT = const InferArgs,
-          typename ChunksT = const ChunkTable>
+          typename ChunksT = const ChunkTable, int W = kLdsWaves>
 __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
+  // FP8 mode (MIX): E4M3 operands in the middle hidden layers (Op), bfloat16 in the first layer and the
+  // head (OpE); the other formats use one operand type throughout (OpE = Op)
+  constexpr bool MIX = L == Lp::FP8;
+  constexpr Lp LE = MIX ? Lp::BF16 : L;
   typedef typename LpOp<L>::type Op;
+  typedef typename LpOp<LE>::type OpE;
   constexpr int S = HID / 16;
   constexpr int T = HID / 32;
   constexpr int CT = kChunkTiles;
-  constexpr int CH = CT * S * 64 * (int)sizeof(Op) / 16;  // u32x4 per chunk buffer
-  constexpr int NT = 64 * kLdsWaves;                    // threads
+  constexpr int CH = CT * S * 64 * (int)sizeof(OpE) / 16;  // u32x4 per chunk buffer (the wider operand)
+  constexpr int NT = 64 * W;                            // threads
   constexpr int PR = (CH + NT - 1) / NT;                // DMA slots per thread
   static_assert(T % CT == 0 && kHeadTiles % CT == 0, "chunk tiles must divide the tile counts");
   extern __shared__ u32x4 smem[];
@@ -678,7 +757,7 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int j = lane & 31, g = lane >> 5;
-  const int64_t pos0 = a.first + (tile * kLdsWaves + wave) * 32;
+  const int64_t pos0 = a.first + (tile * W + wave) * 32;
   const int64_t last = a.first + a.n - 1;
   const int64_t id = pos0 + j <= last ? pos0 + j : last;
   const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
@@ -690,16 +769,12 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
   for (int i = tid; i < ct.n_bias; i += NT) bias_s[i] = a.bias[i];
 
   // grid features: the first layer's B operands
-  Op x0[KS0];
+  OpE x0[KS0];
 #pragma unroll
   for (int s = 0; s < KS0; ++s) {
     float v[8];
     dev::features<8>(a.grid, 16 * s + 8 * g, bx, by, v);
-    if constexpr (L == Lp::FP8) {
-#pragma unroll
-      for (int m = 0; m < 8; ++m) v[m] *= f8.inv[0];
-    }
-    x0[s] = x8_of<L>(v);
+    x0[s] = x8_of<LE>(v);
   }
   wait_dma();
   __syncthreads();
@@ -713,12 +788,15 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
       if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
       f32x16_t acc[CT];
 #pragma unroll
-      for (int u = 0; u < CT; ++u) acc[u] = acc_init<L>(bl + 32 * (CT * tc + u), g);
-      chunk_mfma<L, KS0, CT, KS0>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), KS0, x0, lane, CT, acc);
+      for (int u = 0; u < CT; ++u) acc[u] = acc_init<LE>(bl + 32 * (CT * tc + u), g);
+      chunk_mfma<LE, KS0, CT, KS0>(reinterpret_cast<const OpE*>(smem + (c & 1) * CH), KS0, x0, lane, CT, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) {
         const int t = CT * tc + u;
-        hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bin[2 * t], &bin[2 * t + 1], f8.mul[0], f8.inv[1]);
+        if constexpr (MIX)
+          epi_bf16_to_fp8(acc[u], &bin[2 * t], &bin[2 * t + 1], f8.inv[1]);
+        else
+          hidden_epilogue<L>(acc[u], bl + 32 * t, g, &bin[2 * t], &bin[2 * t + 1], f8.mul[0], f8.inv[1]);
       }
       wait_dma();
       __syncthreads();
@@ -726,8 +804,34 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
     }
   }
   // middle hidden layers: NH of them unrolled at compile time (the two register arrays alternate, so
-  // nothing is copied), or NH < 0: a run-time count
-  if constexpr (NH >= 0) {
+  // nothing is copied), or NH < 0: a run-time count.  FP8 mode: the last one rounds its outputs to
+  // bfloat16 for the head (hb); FP8 needs at least one middle layer (the host checks).
+  OpE hb[S];  // FP8 mode only (unused, and removed by the compiler, otherwise)
+  if constexpr (MIX) {
+    if constexpr (NH >= 0) {
+      static_assert(NH >= 1 && NH <= 2, "one or two unrolled middle layers");
+      if constexpr (NH == 2) {
+        hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[1], f8.mul[1], f8.inv[2], wp, ct, smem, c,
+                                              tid, lane, g);
+        last_middle_fp8<S, T, CT, PR, NT, CH>(bout, hb, bias_s + a.bias_off[2], f8.mul[2], wp, ct, smem, c, tid, lane, g);
+      } else {
+        last_middle_fp8<S, T, CT, PR, NT, CH>(bin, hb, bias_s + a.bias_off[1], f8.mul[1], wp, ct, smem, c, tid, lane, g);
+      }
+    } else {
+      for (int layer = 1; layer < a.n_layers - 2; ++layer) {
+        const float mul = a.fp8_scales[2 * layer] * a.fp8_scales[2 * layer + 1];
+        const float inv_next = 1.0f / a.fp8_scales[2 * layer + 2];
+        hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], mul, inv_next, wp, ct, smem, c, tid,
+                                              lane, g);
+#pragma unroll
+        for (int s = 0; s < S; ++s) bin[s] = bout[s];
+      }
+      const int layer = a.n_layers - 2;
+      last_middle_fp8<S, T, CT, PR, NT, CH>(bin, hb, bias_s + a.bias_off[layer],
+                                            a.fp8_scales[2 * layer] * a.fp8_scales[2 * layer + 1], wp, ct, smem, c, tid,
+                                            lane, g);
+    }
+  } else if constexpr (NH >= 0) {
     static_assert(NH <= 2, "at most two unrolled middle layers");
     if constexpr (NH >= 1)
       hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[1], f8.mul[1], f8.inv[2], wp, ct, smem, c,
@@ -741,23 +845,17 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
     }
   } else {
     for (int layer = 1; layer < a.n_layers - 1; ++layer) {
-      float mul = 1.0f, inv_next = 1.0f;
-      if constexpr (L == Lp::FP8) {
-        mul = a.fp8_scales[2 * layer] * a.fp8_scales[2 * layer + 1];
-        inv_next = 1.0f / a.fp8_scales[2 * layer + 2];
-      }
-      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], mul, inv_next, wp, ct, smem, c, tid,
+      hidden_layer<L, S, T, CT, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], 1.0f, 1.0f, wp, ct, smem, c, tid,
                                             lane, g);
 #pragma unroll
       for (int s = 0; s < S; ++s) bin[s] = bout[s];
     }
   }
+  const OpE (&hin)[S] = pick_head_input<MIX>(bin, hb);
   // head layer, accumulators kept for the BC epilogue
   const int head = a.n_layers - 1;
   const int nht = a.otiles[head];
   const float* bl = bias_s + a.bias_off[head];
-  float head_mul = 1.0f;
-  if constexpr (L == Lp::FP8) head_mul = a.fp8_scales[2 * head] * a.fp8_scales[2 * head + 1];
   f32x16_t hacc[kHeadTiles];
 #pragma unroll
   for (int t = 0; t < kHeadTiles; ++t) hacc[t] = f32x16_t{};
@@ -767,8 +865,8 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
       if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
       f32x16_t acc[CT];
 #pragma unroll
-      for (int u = 0; u < CT; ++u) acc[u] = CT * tc + u < nht ? acc_init<L>(bl + 32 * (CT * tc + u), g) : f32x16_t{};
-      chunk_mfma<L, S, CT, S>(reinterpret_cast<const Op*>(smem + (c & 1) * CH), S, bin, lane, nht - CT * tc, acc);
+      for (int u = 0; u < CT; ++u) acc[u] = CT * tc + u < nht ? acc_init<LE>(bl + 32 * (CT * tc + u), g) : f32x16_t{};
+      chunk_mfma<LE, S, CT, S>(reinterpret_cast<const OpE*>(smem + (c & 1) * CH), S, hin, lane, nht - CT * tc, acc);
 #pragma unroll
       for (int u = 0; u < CT; ++u) hacc[CT * tc + u] = acc[u];
       wait_dma();
@@ -784,16 +882,10 @@ __device__ __forceinline__ void infer_tile(ArgsT a, ChunksT ct, int64_t tile) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (16 * t + 4 * q >= used) continue;
-        float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // 16-bit formats: the bias is in the accumulators
-        if constexpr (L == Lp::FP8) {
-          const float4 b = *reinterpret_cast<const float4*>(bl + 32 * t + 8 * q + 4 * g);
-          bv[0] = b.x, bv[1] = b.y, bv[2] = b.z, bv[3] = b.w;
-        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           if (16 * t + 4 * q + r >= used) continue;
-          const float z = L == Lp::FP8 ? hacc[t][4 * q + r] * head_mul + bv[r] : hacc[t][4 * q + r];
-          hacc[t][4 * q + r] = sigmoid_fast(z);
+          hacc[t][4 * q + r] = sigmoid_fast(hacc[t][4 * q + r]);  // the bias is in the accumulators
         }
       }
     }
@@ -848,8 +940,8 @@ struct BatchItem {
   int32_t index;  // position of the item in the caller's list (stamps)
 };
 
-template <Lp L, int HID, int KS0, int NH, int NB1, int NB4>
-__global__ void __launch_bounds__(64 * kLdsWaves) __attribute__((amdgpu_waves_per_eu(2)))
+template <Lp L, int HID, int KS0, int NH, int NB1, int NB4, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2)))
 k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __restrict__ done,
                   uint64_t* __restrict__ stamps) {
   // the items are read-only for the whole launch: reading them through the constant address space
@@ -864,7 +956,7 @@ k_infer_lds_batch(const BatchItem* __restrict__ items, int n_items, unsigned* __
     else hi = mid - 1;
   }
   const BatchItem& it = *(const BatchItem*)(citems + lo);
-  infer_tile<L, HID, KS0, NH, NB1, NB4, const InferArgs&, const ChunkTable&>(it.a, it.ct, b - it.tile_begin);
+  infer_tile<L, HID, KS0, NH, NB1, NB4, const InferArgs&, const ChunkTable&, W>(it.a, it.ct, b - it.tile_begin);
   if (stamps != nullptr) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1026,7 +1118,9 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
     p->ksteps[k] = (int)ceil_div(in, p->kstep);
     p->otiles[k] = (int)ceil_div(out, p->rows);
     p->pack_off[k] = off;
-    off += (int64_t)p->otiles[k] * p->ksteps[k] * 64;
+    // FP8 mode: offsets in 8-byte units; the first layer and the head hold bfloat16 operands (two units)
+    const bool wide = precision == NTBC_FP8_E4M3 && (k == 0 || k == p->s.n_layers - 1);
+    off += (int64_t)p->otiles[k] * p->ksteps[k] * 64 * (wide ? 2 : 1);
     p->bias_off[k] = boff;
     boff += (int64_t)p->otiles[k] * p->rows;
   }
@@ -1089,15 +1183,27 @@ __global__ void k_fp8_finalize(const unsigned* __restrict__ amax, int n_layers, 
 // The weight-chunk table of the LDS kernel (offsets and lengths in 16-byte units: an FP8 operand is 8
 // bytes, a 16-bit one 16, and every chunk holds a multiple of 64 operands) and its LDS size.
 // staged: the LDS-staged BC epilogue (the heads reuse the chunk buffers, which must hold them).
-int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTable* ct, size_t* lds_out) {
+// Bytes of the staging area at the start of the LDS: the two weight-chunk buffers, or the heads of
+// the workgroup's waves (16 positions each) for the LDS-staged epilogue, whichever is larger.
+size_t stage_bytes(int hid_inst, bool fp8, int head_stride, bool staged, int waves) {
+  (void)fp8;  // FP8 mode's widest chunks are its bfloat16 layers: 16-byte operands like the 16-bit formats
+  const size_t chunk = (size_t)kChunkTiles * (hid_inst / 16) * 64 * 16;
+  const size_t ybytes = staged ? (size_t)waves * 16 * head_stride * sizeof(float) : 0;
+  return std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
+}
+
+int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTable* ct, size_t* lds_out,
+                int waves = kLdsWaves) {
   const Shape& s = p.s;
-  const int64_t op_bytes = fp8 ? 8 : 16;
+  const int64_t unit = fp8 ? 8 : 16;  // bytes of a pack_off unit
   *ct = ChunkTable{};
   for (int k = 0; k < s.n_layers; ++k) {
+    // FP8 mode: E4M3 operands (8 bytes) in the middle layers, bfloat16 (16 bytes) in the first and the head
+    const int64_t op_bytes = fp8 && k > 0 && k < s.n_layers - 1 ? 8 : 16;
     for (int t0 = 0; t0 < p.otiles[k]; t0 += kChunkTiles) {
       NTBC_REQUIRE(ct->n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
       const int nt = std::min(kChunkTiles, p.otiles[k] - t0);
-      ct->src[ct->n] = (p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64) * op_bytes / 16;
+      ct->src[ct->n] = (p.pack_off[k] * unit + (int64_t)t0 * p.ksteps[k] * 64 * op_bytes) / 16;
       ct->len[ct->n] = (int)((int64_t)nt * p.ksteps[k] * 64 * op_bytes / 16);
       ++ct->n;
     }
@@ -1105,9 +1211,7 @@ int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTabl
   int64_t nb = 0;
   for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 32);
   ct->n_bias = (int)((nb + 3) / 4 * 4);
-  const size_t chunk = (size_t)kChunkTiles * (p.hid_inst / 16) * 64 * op_bytes;
-  const size_t ybytes = staged ? (size_t)kLdsWaves * 16 * head_stride * sizeof(float) : 0;
-  const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
+  const size_t stage = stage_bytes(p.hid_inst, fp8, head_stride, staged, waves);
   ct->stage = (int)(stage / sizeof(u32x4));
   *lds_out = stage + (256 + (size_t)ct->n_bias) * sizeof(float);
   NTBC_REQUIRE(*lds_out <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, *lds_out);
@@ -1127,9 +1231,9 @@ typedef void (*BatchLaunch)(dim3, dim3, size_t, hipStream_t, const void* items, 
 bool lds_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
 bool lds_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
 bool lds_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, LdsLaunch* launch);
-bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
-bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
-bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch);
+bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
+bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
+bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
 }  // namespace ntbc
 
 // Single-range instances: every precision at widths 64/128/256 with one to four input K-steps and a
@@ -1158,10 +1262,10 @@ bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void**
 // register epilogue for two BC1 + one to three BC4 textures at widths 64, 128 (run-time layer count)
 // and 256 (two middle layers unrolled).
 #define NTBC_BATCH_INSTANCE_L(LP, H, K, NH, NB1, NB4)                                                         \
-  if (hid == H && ks0 == K && nh == NH && nb1 == NB1 && (NB1 < 0 || nb4 == NB4)) {                         \
-    *fn = (const void*)k_infer_lds_batch<LP, H, K, NH, NB1, NB4>;                                            \
+  if (hid == H && ks0 == K && nh == NH && nb1 == NB1 && (NB1 < 0 || nb4 == NB4) && waves == NTBC_BATCH_W) {   \
+    *fn = (const void*)k_infer_lds_batch<LP, H, K, NH, NB1, NB4, NTBC_BATCH_W>;                              \
     *launch = [](dim3 g, dim3 b, size_t sh, hipStream_t st, const void* it, int n, unsigned* d, uint64_t* s) { \
-      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH, NB1, NB4>), g, b, sh, st,                         \
+      hipLaunchKernelGGL((k_infer_lds_batch<LP, H, K, NH, NB1, NB4, NTBC_BATCH_W>), g, b, sh, st,           \
                          static_cast<const BatchItem*>(it), n, d, s);                                        \
     };                                                                                                       \
     return true;                                                                                             \
@@ -1197,25 +1301,53 @@ bool lds_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** f
   return false;
 }
 #endif
+// BF16 batched instances come in three tile shapes (2, 4 or 8 waves of 32 positions per workgroup),
+// one per part, for the tile autotuner; FP16 and FP8 in the default shape (4 waves).
+#define NTBC_BATCH_BF16_W(WV)                                                                                   \
+  bool batch_instance_bf16_w##WV(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn,         \
+                                 BatchLaunch* launch) {                                                         \
+    NTBC_BATCH_INSTANCES(Lp::BF16)                                                                              \
+    NTBC_BATCH_REG(64, 4, -1) NTBC_BATCH_REG(128, 4, -1) NTBC_BATCH_REG(256, 4, 2)                              \
+    return false;                                                                                               \
+  }
+bool batch_instance_bf16_w2(int, int, int, int, int, int, const void**, BatchLaunch*);
+bool batch_instance_bf16_w4(int, int, int, int, int, int, const void**, BatchLaunch*);
+bool batch_instance_bf16_w8(int, int, int, int, int, int, const void**, BatchLaunch*);
 #if NTBC_PART(4)
-bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
-  NTBC_BATCH_INSTANCES(Lp::BF16)
-  NTBC_BATCH_REG(64, 4, -1) NTBC_BATCH_REG(128, 4, -1) NTBC_BATCH_REG(256, 4, 2)
-  return false;
+#define NTBC_BATCH_W 4
+NTBC_BATCH_BF16_W(4)
+#undef NTBC_BATCH_W
+bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch) {
+  if (waves == 2) return batch_instance_bf16_w2(hid, ks0, nh, nb1, nb4, waves, fn, launch);
+  if (waves == 8) return batch_instance_bf16_w8(hid, ks0, nh, nb1, nb4, waves, fn, launch);
+  return batch_instance_bf16_w4(hid, ks0, nh, nb1, nb4, waves, fn, launch);
 }
 #endif
+#if NTBC_PART(7)
+#define NTBC_BATCH_W 2
+NTBC_BATCH_BF16_W(2)
+#undef NTBC_BATCH_W
+#endif
+#if NTBC_PART(8)
+#define NTBC_BATCH_W 8
+NTBC_BATCH_BF16_W(8)
+#undef NTBC_BATCH_W
+#endif
+#define NTBC_BATCH_W 4
 #if NTBC_PART(5)
-bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
+bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch) {
   NTBC_BATCH_INSTANCES(Lp::FP16)
   return false;
 }
 #endif
 #if NTBC_PART(6)
-bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** fn, BatchLaunch* launch) {
+bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch) {
   NTBC_BATCH_INSTANCES(Lp::FP8)
   return false;
 }
 #endif
+#undef NTBC_BATCH_W
+#undef NTBC_BATCH_BF16_W
 }  // namespace ntbc
 #undef NTBC_LDS_INSTANCE_L
 #undef NTBC_LDS_INSTANCES
@@ -1231,7 +1363,13 @@ struct BatchGroup {
   int32_t lp, hid, ks0, nh, nb1, nb4;
   int32_t item_begin, item_end;
   int64_t tiles, lds;
+  int32_t waves;       // tile shape: waves (of 32 block positions) per workgroup
+  int32_t pad;
+  int64_t lds_w[3];    // LDS bytes at 2, 4 and 8 waves
 };
+
+constexpr int kTileWaves[3] = {2, 4, 8};
+int waves_index(int w) { return w == 2 ? 0 : (w == 8 ? 2 : 1); }
 
 // Kernel instance of an item: the unrolled two-middle-layer instances where they exist, else the
 // generic one (same selection as ntbc_infer_blocks).
@@ -1245,13 +1383,14 @@ int launch_batch_group(const BatchGroup& gr, const BatchItem* items, unsigned* d
   const void* fn = nullptr;
   BatchLaunch launch = nullptr;
   const bool found =
-      gr.lp == NTBC_FP8_E4M3 ? batch_instance_fp8(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch)
-      : gr.lp == NTBC_FP16   ? batch_instance_fp16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch)
-                             : batch_instance_bf16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, &fn, &launch);
+      gr.lp == NTBC_FP8_E4M3 ? batch_instance_fp8(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, gr.waves, &fn, &launch)
+      : gr.lp == NTBC_FP16   ? batch_instance_fp16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, gr.waves, &fn, &launch)
+                             : batch_instance_bf16(gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, gr.waves, &fn, &launch);
   if (!found) fn = nullptr;
-  NTBC_REQUIRE(fn != nullptr, "no batch kernel instance for width %d, %d input K-steps", gr.hid, gr.ks0);
+  NTBC_REQUIRE(fn != nullptr, "no batch kernel instance for width %d, %d input K-steps, %d-wave tiles", gr.hid, gr.ks0,
+               gr.waves);
   NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gr.lds));
-  launch(dim3((unsigned)gr.tiles), dim3(64 * kLdsWaves), (size_t)gr.lds, strm, items + gr.item_begin,
+  launch(dim3((unsigned)gr.tiles), dim3(64 * gr.waves), (size_t)gr.lds, strm, items + gr.item_begin,
          gr.item_end - gr.item_begin, done, stamps);
   return check_launch("ntbc_infer_batch");
 }
@@ -1408,7 +1547,8 @@ int infer_blocks(const Plan& p, const ntbc_model_desc* d, const ntbc_params* prm
   const bool lds_shape = p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2;
   if (fp8) {
     NTBC_REQUIRE(prm->fp8_scales != nullptr, "FP8 needs fp8_scales (see ntbc_fp8_calibrate)");
-    if (!lds_shape) return fail(NTBC_EUNSUPPORTED, "FP8 needs head_dim <= %d, in_dim <= 64 and a hidden layer", 32 * kHeadTiles);
+    if (!lds_shape || s.n_layers < 3)
+      return fail(NTBC_EUNSUPPORTED, "FP8 needs head_dim <= %d, in_dim <= 64 and two hidden layers", 32 * kHeadTiles);
   }
   if (n_blocks == 0) return NTBC_OK;
   NTBC_REQUIRE(blocks_out != nullptr, "blocks_out is NULL");
@@ -1696,6 +1836,8 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
     if (!(p.otiles[s.n_layers - 1] <= kHeadTiles && p.ksteps[0] <= 4 && s.n_layers >= 2))
       return fail(NTBC_EUNSUPPORTED, "item %d: batched decode needs head_dim <= %d, in_dim <= 64 and a hidden layer", i,
                   32 * kHeadTiles);
+    if (precision == NTBC_FP8_E4M3 && s.n_layers < 3)
+      return fail(NTBC_EUNSUPPORTED, "item %d: FP8 needs two hidden layers", i);
     int m = -1;
     for (size_t q = 0; q < model_ids.size(); ++q)
       if (model_ids[q] == it.model_id) m = (int)q;
@@ -1715,7 +1857,7 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
     }
     model_of[i] = m;
     const RegPlan rp = reg_plan(p, true);
-    const BatchGroup want{precision, p.hid_inst, p.ksteps[0], batch_nh(p), rp.nb1, rp.nb4, 0, 0, 0, 0};
+    const BatchGroup want{precision, p.hid_inst, p.ksteps[0], batch_nh(p), rp.nb1, rp.nb4, 0, 0, 0, 0, kLdsWaves, 0, {0, 0, 0}};
     int gi = -1;
     for (size_t q = 0; q < groups.size(); ++q)
       if (groups[q].hid == want.hid && groups[q].ks0 == want.ks0 && groups[q].nh == want.nh &&
@@ -1786,12 +1928,19 @@ extern "C" int ntbc_batch_plan(const ntbc_batch_item* items, int32_t n_items, in
       bi.a.n = items[i].n_blocks;
       bi.a.out = items[i].blocks_out;
       bi.a.heads = nullptr;
+      const bool fp8 = precision == NTBC_FP8_E4M3, staged = reg_plan(p, true).nb1 < 0;
       size_t lds = 0;
-      int st = make_chunks(p, precision == NTBC_FP8_E4M3, bi.a.head_stride, reg_plan(p, true).nb1 < 0, &bi.ct, &lds);
+      int st = make_chunks(p, fp8, bi.a.head_stride, staged, &bi.ct, &lds, gr.waves);
       if (st != NTBC_OK) return st;
-      gr.lds = std::max<int64_t>(gr.lds, (int64_t)lds);
+      // LDS of every tile shape (the staging area grows with the waves of the staged epilogue)
+      for (int w = 0; w < 3; ++w) {
+        const int64_t lw = (int64_t)stage_bytes(p.hid_inst, fp8, bi.a.head_stride, staged, kTileWaves[w]) +
+                           (256 + (int64_t)bi.ct.n_bias) * (int64_t)sizeof(float);
+        gr.lds_w[w] = std::max<int64_t>(gr.lds_w[w], lw);
+      }
+      gr.lds = gr.lds_w[waves_index(gr.waves)];
       bi.tile_begin = tiles;
-      bi.tiles = ceil_div(items[i].n_blocks, (int64_t)32 * kLdsWaves);
+      bi.tiles = ceil_div(items[i].n_blocks, (int64_t)32 * gr.waves);
       bi.index = i;
       tiles += bi.tiles;
       out[n_out++] = bi;
@@ -1824,6 +1973,45 @@ extern "C" int ntbc_batch_pack(const void* table, void* workspace, size_t worksp
     int st = check_launch("ntbc_batch_pack");
     if (st != NTBC_OK) return st;
   }
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_batch_groups(const void* table, int32_t* groups_out, int32_t max_groups, int32_t* n_groups) {
+  const BatchHeader* h = batch_header(table);
+  NTBC_REQUIRE(h != nullptr, "table is not a batch plan");
+  NTBC_REQUIRE(n_groups != nullptr, "n_groups is NULL");
+  *n_groups = h->n_groups;
+  for (int g = 0; g < h->n_groups && g < max_groups && groups_out != nullptr; ++g) {
+    const BatchGroup& gr = h->groups[g];
+    const int32_t row[8] = {gr.lp, gr.hid, gr.ks0, gr.nh, gr.nb1, gr.nb4, gr.waves, gr.item_end - gr.item_begin};
+    for (int k = 0; k < 8; ++k) groups_out[8 * g + k] = row[k];
+  }
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_batch_set_waves(void* table, int32_t group, int32_t waves) {
+  BatchHeader* h = const_cast<BatchHeader*>(batch_header(table));
+  NTBC_REQUIRE(h != nullptr, "table is not a batch plan");
+  NTBC_REQUIRE(group >= 0 && group < h->n_groups, "group %d outside 0..%d", group, h->n_groups - 1);
+  NTBC_REQUIRE(waves == 2 || waves == 4 || waves == 8, "waves %d is not 2, 4 or 8", waves);
+  BatchGroup& gr = h->groups[group];
+  if (gr.lp != NTBC_BF16 && waves != kLdsWaves)
+    return fail(NTBC_EUNSUPPORTED, "only the BF16 batch has %d-wave tiles", waves);
+  const int64_t lds = gr.lds_w[waves_index(waves)];
+  NTBC_REQUIRE(lds <= 160 * 1024, "%d-wave tiles of group %d need %lld bytes of LDS", waves, group, (long long)lds);
+  gr.waves = waves;
+  gr.lds = lds;
+  BatchItem* items = reinterpret_cast<BatchItem*>(static_cast<char*>(table) + h->items_offset);
+  int64_t tiles = 0;
+  for (int i = gr.item_begin; i < gr.item_end; ++i) {
+    // the staging area (and with it the /255 table and biases behind it) moves with the shape
+    items[i].ct.stage = (int)(stage_bytes(gr.hid, gr.lp == NTBC_FP8_E4M3, items[i].a.head_stride, gr.nb1 < 0, waves) /
+                              sizeof(u32x4));
+    items[i].tile_begin = tiles;
+    items[i].tiles = ceil_div(items[i].a.n, (int64_t)32 * waves);
+    tiles += items[i].tiles;
+  }
+  gr.tiles = tiles;
   return NTBC_OK;
 }
 

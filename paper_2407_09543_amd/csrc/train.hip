@@ -1585,9 +1585,18 @@ struct DwArgs {
 };
 
 // Block b: tile b % n_tiles, K range b / n_tiles.  Four waves, each a 64 x 64 quadrant as 2 x 2
-// products of 32 x 32; fragments read straight from the position-contiguous buffers (16 bytes a lane:
-// eight consecutive positions of one row).
+// products of 32 x 32.  The K range advances in slices of kDwK positions: each thread loads kDwK/16
+// x 16 bytes of A rows and of B rows (row tid/2, positions (kDwK/2)(tid%2) .. +kDwK/2-1 of the slice)
+// into registers while the previous slice is multiplied from LDS, then stores them to the other LDS
+// buffer (one barrier per slice); a lane's fragment (row l%32, positions 8(l/32) .. +7 of a K-step) is
+// one 16-byte LDS read.
+constexpr int kDwK = 64;          // positions per slice
+constexpr int kDwRow = kDwK + 8;  // LDS row stride in bfloat16 (144 bytes)
+constexpr int kDwLd = kDwK / 16;  // 16-byte loads per thread and operand
+
 __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
+  __shared__ __align__(16) uint16_t As[2][128][kDwRow];
+  __shared__ __align__(16) uint16_t Bs[2][128][kDwRow];
   const int tile = blockIdx.x % a.n_tiles, split = blockIdx.x / a.n_tiles;
   int jb = 0;
   while (jb + 1 < a.n_jobs && tile >= a.job[jb + 1].tile0) ++jb;
@@ -1598,47 +1607,65 @@ __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
   const int wm = wave >> 1, wn = wave & 1, li = lane & 31, g = lane >> 5;
   const int64_t k0 = (int64_t)split * a.k_split;
   const int64_t k1 = k0 + a.k_split < a.K ? k0 + a.k_split : a.K;
-  int ar[2], br[2];
-  bool aok[2], bok[2];
+  // the thread's staging row and half slice
+  const int sr = tid >> 1, sh = (tid & 1) * (kDwK / 2);
+  const int arow = tm * 128 + sr, brow = tn * 128 + sr;
+  const bool aok = arow < J.a_rows, bok = brow < J.b_rows;
+  const u32x4* ag = reinterpret_cast<const u32x4*>(J.a + (int64_t)(aok ? arow : 0) * a.bpad + sh);
+  const u32x4* bg = reinterpret_cast<const u32x4*>(J.b + (int64_t)(bok ? brow : 0) * a.bpad + sh);
+  const bool sums = tn == 0;  // bias gradient: row sums of A in FP32
+  float rs = 0.0f;
+  u32x4 ra[kDwLd], rb[kDwLd];
+  auto load = [&](int64_t k) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    ar[i] = tm * 128 + wm * 64 + 32 * i + li;
-    br[i] = tn * 128 + wn * 64 + 32 * i + li;
-    aok[i] = ar[i] < J.a_rows;
-    bok[i] = br[i] < J.b_rows;
-  }
-  const bool sums = tn == 0 && wn == 0;  // bias gradient: row sums of A in FP32
-  float rs[2] = {0.0f, 0.0f};
+    for (int h = 0; h < kDwLd; ++h) {
+      ra[h] = aok ? ag[k / 8 + h] : u32x4{};
+      rb[h] = bok ? bg[k / 8 + h] : u32x4{};
+    }
+    if (sums) {
+#pragma unroll
+      for (int h = 0; h < kDwLd; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rs += __uint_as_float(ra[h][e] << 16) + __uint_as_float(ra[h][e] & 0xFFFF0000u);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < kDwLd; ++h) {
+      *reinterpret_cast<u32x4*>(&As[buf][sr][sh + 8 * h]) = ra[h];
+      *reinterpret_cast<u32x4*>(&Bs[buf][sr][sh + 8 * h]) = rb[h];
+    }
+  };
   f32x16_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) acc[i][jj] = f32x16_t{};
-  const u32x4* ap[2];
-  const u32x4* bp[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    ap[i] = reinterpret_cast<const u32x4*>(J.a + (int64_t)(aok[i] ? ar[i] : 0) * a.bpad + 8 * g);
-    bp[i] = reinterpret_cast<const u32x4*>(J.b + (int64_t)(bok[i] ? br[i] : 0) * a.bpad + 8 * g);
+  if (k0 < k1) {
+    load(k0);
+    store(0);
   }
-  for (int64_t k = k0; k < k1; k += 16) {
-    u32x4 af[2], bf[2];
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k = k0; k < k1; k += kDwK) {
+    const bool more = k + kDwK < k1;
+    if (more) load(k + kDwK);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      af[i] = aok[i] ? ap[i][k / 8] : u32x4{};
-      bf[i] = bok[i] ? bp[i][k / 8] : u32x4{};
-    }
-    if (sums) {
+    for (int ks = 0; ks < kDwK / 16; ++ks) {
+      u32x4 af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        af[i] = *reinterpret_cast<const u32x4*>(&As[buf][wm * 64 + 32 * i + li][16 * ks + 8 * g]);
+        bf[i] = *reinterpret_cast<const u32x4*>(&Bs[buf][wn * 64 + 32 * i + li][16 * ks + 8 * g]);
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          rs[i] += __uint_as_float(af[i][e] << 16) + __uint_as_float(af[i][e] & 0xFFFF0000u);
+        for (int jj = 0; jj < 2; ++jj) acc[i][jj] = fmma(af[i], bf[jj], acc[i][jj]);
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) acc[i][jj] = fmma(af[i], bf[jj], acc[i][jj]);
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   float* part = a.part + ((int64_t)tile * a.splits + split) * (128 * 128);
 #pragma unroll
@@ -1652,15 +1679,13 @@ __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
         part[r * 128 + col] = acc[i][jj][v];
       }
   if (sums) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float t = rs[i] + __shfl_xor(rs[i], 32);
-      if (g == 0) a.dbpart[((int64_t)tile * a.splits + split) * 128 + wm * 64 + 32 * i + li] = t;
-    }
+    const float t = rs + __shfl_xor(rs, 1);  // the two threads of a staging row
+    if ((tid & 1) == 0) a.dbpart[((int64_t)tile * a.splits + split) * 128 + sr] = t;
   }
 }
 
-// dW (and db) += the sum of the partial tiles over the K ranges, in K-range order.
+// dW (and db) += the sum of the partial tiles over the K ranges, in K-range order; one thread per
+// element of a tile.
 __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
   const int tile = blockIdx.y;
   int jb = 0;
@@ -1669,21 +1694,20 @@ __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
   const int lt = tile - J.tile0;
   const int tm = lt / J.tiles_n, tn = lt % J.tiles_n;
   const float* part = a.part + (int64_t)tile * a.splits * (128 * 128);
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < 128 * 128; e += gridDim.x * 256) {
-    const int r = e / 128, col = e % 128;
-    const int m = tm * 128 + r, nn = tn * 128 + col;
-    if (m >= J.M || nn >= J.N) continue;
+  const int e = blockIdx.x * 256 + threadIdx.x;  // gridDim.x = 64
+  const int r = e / 128, col = e % 128;
+  const int m = tm * 128 + r, nn = tn * 128 + col;
+  if (m < J.M && nn < J.N) {
     float s = 0.0f;
     for (int k = 0; k < a.splits; ++k) s += part[(int64_t)k * (128 * 128) + e];
     J.c[(int64_t)m * J.N + nn] += s;
   }
-  if (tn == 0 && blockIdx.x == 0) {
-    for (int r = threadIdx.x; r < 128; r += 256) {
-      const int m = tm * 128 + r;
-      if (m >= J.M) continue;
+  if (tn == 0 && blockIdx.x == 0 && threadIdx.x < 128) {
+    const int mr = tm * 128 + threadIdx.x;
+    if (mr < J.M) {
       float s = 0.0f;
-      for (int k = 0; k < a.splits; ++k) s += a.dbpart[((int64_t)tile * a.splits + k) * 128 + r];
-      J.db[m] += s;
+      for (int k = 0; k < a.splits; ++k) s += a.dbpart[((int64_t)tile * a.splits + k) * 128 + threadIdx.x];
+      J.db[mr] += s;
     }
   }
 }
@@ -2085,7 +2109,7 @@ FusedLayout fused_layout(const Shape& s, const FusedPlan& f, int64_t batch) {
   l.n_tiles = 0;
   for (int k = 0; k < f.L; ++k) l.n_tiles += (int)(ceil_div(s.layer_out[k], 128) * ceil_div(s.layer_in[k], 128));
   int splits = (int)std::max<int64_t>(1, std::min<int64_t>(512 / l.n_tiles, l.bpad / 256));
-  l.k_split = (int)(ceil_div(ceil_div(l.bpad, splits), 16) * 16);
+  l.k_split = (int)(ceil_div(ceil_div(l.bpad, splits), kDwK) * kDwK);
   l.splits = (int)ceil_div(l.bpad, l.k_split);
   l.part = take((int64_t)l.n_tiles * l.splits * 128 * 128 * 4);
   l.dbpart = take((int64_t)l.n_tiles * l.splits * 128 * 4);
@@ -2223,7 +2247,7 @@ int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, cons
   hipLaunchKernelGGL(k_train_dw, dim3((unsigned)(d.n_tiles * d.splits)), dim3(256), 0, c.strm, d);
   st = check_launch("k_train_dw");
   if (st != NTBC_OK) return st;
-  hipLaunchKernelGGL(k_train_dw_reduce, dim3(16, (unsigned)d.n_tiles), dim3(256), 0, c.strm, d);
+  hipLaunchKernelGGL(k_train_dw_reduce, dim3(64, (unsigned)d.n_tiles), dim3(256), 0, c.strm, d);
   return check_launch("k_train_dw_reduce");
 }
 

@@ -114,6 +114,42 @@ def model_bytes(cfg, weight_bytes: int = 2) -> int:
     return cfg.grid_vertices * cfg.n_features + 8 * cfg.n_levels + cfg.n_weights * weight_bytes
 
 
+def exception_list_bytes(n_fallback: int, n_blocks: int) -> int:
+    """Bytes of one texture's exception list: the replaced blocks (8 bytes each) and where they go, as
+    a bitmask over the texture's blocks or as 32-bit block indices, whichever is smaller."""
+    if n_fallback == 0:
+        return 0
+    return 8 * n_fallback + min((n_blocks + 7) // 8, 4 * n_fallback)
+
+
+def judge_sweep(ntbc_words: torch.Tensor, ref_words: torch.Tensor, textures: Sequence[torch.Tensor], formats,
+                size: int, model_bytes_: int, kappas=(1.0, 2.0, 4.0, 8.0), deltas=(0.0, 16.0, 64.0, 256.0)):
+    """The per-block judge (Sec. 4.3: standard BC where NTBC compresses badly) swept over its threshold
+    SSE_ntbc > kappa * SSE_ref + delta: for every (kappa, delta) the decoded PSNR of each texture and of
+    the material after the judge, the replaced blocks, and the total stored bytes (model + every
+    texture's exception list).  Per-block SSEs come from ntbc_block_sse; the judge is ntbc_fallback."""
+    n_blocks = ntbc_words.shape[1]
+    sse_n = [ntbc.block_sse(ntbc_words[t].contiguous(), tex, f) for t, (tex, f) in enumerate(zip(textures, formats))]
+    sse_r = [ntbc.block_sse(ref_words[t].contiguous(), tex, f) for t, (tex, f) in enumerate(zip(textures, formats))]
+    n_values = [tex.numel() for tex in textures]
+    rows = []
+    for kappa in kappas:
+        for delta in deltas:
+            counts, sse_tot = [], []
+            for t in range(len(formats)):
+                out, cnt = ntbc.fallback(ntbc_words[t].contiguous(), ref_words[t].contiguous(), sse_n[t], sse_r[t],
+                                         kappa, delta)
+                counts.append(int(cnt.item()))
+                # the judged texture's squared error is the sum of its blocks' SSEs
+                chosen = torch.where(out == ref_words[t], sse_r[t], sse_n[t])
+                sse_tot.append(float(chosen.double().sum().item()))
+            total = model_bytes_ + sum(exception_list_bytes(c, n_blocks) for c in counts)
+            rows.append({"kappa": kappa, "delta": delta, "fallback_blocks": counts, "total_bytes": total,
+                         "psnr_db": [quality.psnr_from_sse(e, n) for e, n in zip(sse_tot, n_values)],
+                         "psnr_db_material": quality.psnr_from_sse(sum(sse_tot), sum(n_values))})
+    return rows
+
+
 def downsampled_ref_psnr(textures: Sequence[torch.Tensor], formats, size: int) -> List[float]:
     """A storage-matched non-learned baseline: each texture averaged over 2x2 texels (rounded), encoded
     by the reference encoder at half resolution (a quarter of the BC bytes), decoded and upsampled by

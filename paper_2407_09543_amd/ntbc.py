@@ -84,6 +84,8 @@ _SIGNATURES = {
     "ntbc_batch_plan": ([ctypes.c_void_p, _I32, _I32, _P, _P, _SZ, ctypes.POINTER(_SZ)], _I32),
     "ntbc_batch_pack": ([_P, _P, _SZ, _P], _I32),
     "ntbc_infer_batch": ([_P, _P, _P, _SZ, _P, _P], _I32),
+    "ntbc_batch_groups": ([_P, _P, _I32, ctypes.POINTER(_I32)], _I32),
+    "ntbc_batch_set_waves": ([_P, _I32, _I32], _I32),
     "ntbc_infer_blocks": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
                            _P, _SZ, _P], ctypes.c_int),
     "ntbc_infer_blocks_noalloc": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(Params), _I32, _I64, _I64, _P, _P,
@@ -278,7 +280,6 @@ class Model:
                                        n_blocks, _ptr(out), _ptr(h), _ptr(ws), ws.numel(), _stream()))
         return (out, h) if heads else out
 
-
     def infer_noalloc(self, precision: int = BF16, first_block: int = 0, n_blocks: Optional[int] = None,
                       heads: bool = False, out: Optional[torch.Tensor] = None, reuse_packed: bool = False):
         """As infer(), through ntbc_infer_blocks_noalloc: the library's static per-device scratch holds the
@@ -314,7 +315,9 @@ class Batch:
     """A planned batched decode: items (model, desc, first_block, n_blocks) -> one output tensor per
     item; run() issues one launch per kernel instance (capturable in a HIP graph)."""
 
-    def __init__(self, entries, precision: int = BF16):
+    def __init__(self, entries, precision: int = BF16, tiles=None):
+        """tiles: {instance key: waves} tile shapes (autotune.key); None = the committed autotuner table,
+        {} = the default shape everywhere."""
         self.models = [e[0] for e in entries]
         n = len(entries)
         dev = self.models[0].weights.device
@@ -342,7 +345,24 @@ class Batch:
                                      ctypes.addressof(self.table), tb.value, ctypes.byref(wsb)))
         self.table_dev = torch.frombuffer(bytearray(bytes(self.table)), dtype=torch.uint8).to(dev)
         self.n = n
+        from . import autotune
+        autotune.apply(self, autotune.load_table() if tiles is None else tiles)
         _check(lib().ntbc_batch_pack(ctypes.addressof(self.table), _ptr(self.ws), self.ws.numel(), _stream()))
+
+    def groups(self):
+        """Kernel instances of the plan: dicts of precision, hidden, ks0, nh, nb1, nb4, waves, items."""
+        n = _I32()
+        _check(lib().ntbc_batch_groups(ctypes.addressof(self.table), None, 0, ctypes.byref(n)))
+        buf = (_I32 * (8 * max(n.value, 1)))()
+        _check(lib().ntbc_batch_groups(ctypes.addressof(self.table), buf, n.value, ctypes.byref(n)))
+        keys = ("precision", "hidden", "ks0", "nh", "nb1", "nb4", "waves", "items")
+        return [dict(zip(keys, buf[8 * g:8 * g + 8])) for g in range(n.value)]
+
+    def set_waves(self, group: int, waves: int):
+        """Tile shape (waves of 32 positions per workgroup) of one kernel instance; the device copy of
+        the plan is refreshed."""
+        _check(lib().ntbc_batch_set_waves(ctypes.addressof(self.table), group, waves))
+        self.table_dev.copy_(torch.frombuffer(bytearray(bytes(self.table)), dtype=torch.uint8))
 
     def run(self, stamps: Optional[torch.Tensor] = None):
         """Decodes every item into self.outputs; stamps (uint64 as int64 [n + 1]) receive the start and

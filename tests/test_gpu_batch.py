@@ -142,3 +142,44 @@ def test_fp8_batch_equals_single_launches():
         single = ntbc.Model(d, model.weights, model.grid, model.grid_scale, model.grid_zero)
         single.fp8_scales = model.fp8_scales
         assert torch.equal(out, single.infer(ntbc.FP8_E4M3, first_block=first, n_blocks=n)), f"material {k} level {level}"
+
+
+def test_tile_shapes_give_the_same_blocks():
+    # every BF16 kernel instance of the batch at 2, 4 and 8 waves per workgroup (the tile shapes the
+    # autotuner chooses from): the blocks are those of the default shape, bit for bit
+    mats = _materials()
+    entries, meta = _entries(mats)
+    batch = ntbc.Batch(entries, ntbc.BF16, tiles={})
+    ref = [o.clone() for o in batch.run()]
+    torch.cuda.synchronize()
+    groups = batch.groups()
+    assert len(groups) >= 3 and all(g["waves"] == 4 for g in groups)
+    for w in (2, 8):
+        for gi in range(len(groups)):
+            batch.set_waves(gi, w)
+        assert all(g["waves"] == w for g in batch.groups())
+        for o in batch.outputs:
+            o.zero_()
+        outs = batch.run()
+        torch.cuda.synchronize()
+        for o, r, (k, level) in zip(outs, ref, meta):
+            assert torch.equal(o, r), f"{w}-wave tiles: material {k} level {level}"
+        log(f"{w}-wave tiles: {len(outs)} items equal")
+    with pytest.raises(ntbc.NtbcError):
+        batch.set_waves(0, 3)
+
+
+def test_autotuner_picks_a_timed_shape():
+    from paper_2407_09543_amd import autotune
+    mats = _materials()
+    entries, meta = _entries(mats)
+    batch = ntbc.Batch(entries, ntbc.BF16, tiles={})
+    table = autotune.tune(batch, reps=3)
+    groups = batch.groups()
+    assert len(table) == len(groups)
+    for g in groups:
+        t = table[autotune.key(g)]
+        assert g["waves"] == t["waves"] == min(t["ms"], key=t["ms"].get)
+    # a plan made with the table applies it
+    again = ntbc.Batch(entries, ntbc.BF16, tiles={k: v["waves"] for k, v in table.items()})
+    assert [g["waves"] for g in again.groups()] == [g["waves"] for g in groups]

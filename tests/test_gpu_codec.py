@@ -52,6 +52,25 @@ def test_encode_adversarial_blocks(fmt):
     assert np.array_equal(gs, osse)
 
 
+def test_encode_single_colour_blocks():
+    # one-colour blocks take REF-BC1's optimal single-colour step: every grey level, every value of
+    # each channel alone, and random colours; mixed with non-uniform blocks in the same texture
+    rng = np.random.default_rng(31)
+    cols = [np.repeat(np.arange(256)[:, None], 3, axis=1)]
+    for c in range(3):
+        one = np.full((256, 3), 128)
+        one[:, c] = np.arange(256)
+        cols.append(one)
+    cols.append(rng.integers(0, 256, (256, 3)))
+    col = np.concatenate(cols)
+    blocks = np.repeat(col[:, None, :], 16, axis=1).astype(np.uint8)
+    blocks[1::7, 5] ^= 1  # some blocks one texel off uniform
+    tex = bc.blocks_to_image(blocks, 4 * 40, 4 * 32)
+    gw, gs, ow, osse = _encode_both(tex, 1)
+    assert np.array_equal(gw, ow)
+    assert np.array_equal(gs, osse)
+
+
 @pytest.mark.parametrize("h,w", [(4, 4), (8, 12), (36, 20)])
 def test_encode_ragged_sizes(h, w):
     rng = np.random.default_rng(h * 100 + w)

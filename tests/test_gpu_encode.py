@@ -101,3 +101,39 @@ def test_storage_matched_baseline_report():
         f"{sum(256 * 256 // 16 // 4 * 8 for _ in cfg.formats)} B psnr {np.round(base, 2)}")
     ref = encode.psnr_of_words(res.ref_words, tex, cfg.formats, 256)
     assert all(b <= r + 1e-9 for b, r in zip(base, ref))
+
+
+def test_judge_sweep_accounting():
+    # the judge swept over (kappa, delta): a threshold nobody exceeds keeps every NTBC block (no
+    # exception list, NTBC's PSNR), one everybody exceeds replaces every block (the reference
+    # encoder's PSNR and a full exception list); PSNR after the judge equals the PSNR of the judged
+    # words decoded by the library; a larger delta never replaces more blocks
+    cfg = synth.config_mid(256)
+    mat = synth.material_five(256, 4)
+    tex = [torch.from_numpy(t.texels).cuda() for t in mat.textures]
+    res = encode.encode_material(tex, cfg, steps=300, batch=2048, seed=4)
+    mb = encode.model_bytes(cfg, 2)
+    n = cfg.n_positions
+    rows = encode.judge_sweep(res.ntbc_words, res.ref_words, tex, cfg.formats, 256, mb,
+                              kappas=(0.0, 1.0, 4.0, 1e30), deltas=(-1.0, 0.0, 64.0, 1e30))
+    by = {(r["kappa"], r["delta"]): r for r in rows}
+    keep_all, replace_all = by[(1e30, 1e30)], by[(0.0, -1.0)]  # limits above / below every block SSE
+    assert keep_all["fallback_blocks"] == [0] * 5 and keep_all["total_bytes"] == mb
+    assert np.allclose(keep_all["psnr_db"], encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, 256))
+    assert replace_all["fallback_blocks"] == [n] * 5
+    assert replace_all["total_bytes"] == mb + 5 * (8 * n + n // 8)
+    ref = encode.psnr_of_words(res.ref_words, tex, cfg.formats, 256)
+    assert all((a == b) or np.isclose(a, b) for a, b in zip(replace_all["psnr_db"], ref))
+    for kappa in (1.0, 4.0):
+        counts = [sum(by[(kappa, d)]["fallback_blocks"]) for d in (-1.0, 0.0, 64.0, 1e30)]
+        assert counts == sorted(counts, reverse=True)
+    # PSNR after the judge against the library's decode of the judged words (kappa 4, delta 0)
+    words = []
+    for t, (tx, f) in enumerate(zip(tex, cfg.formats)):
+        s_n = ntbc.block_sse(res.ntbc_words[t].contiguous(), tx, f)
+        s_r = ntbc.block_sse(res.ref_words[t].contiguous(), tx, f)
+        words.append(ntbc.fallback(res.ntbc_words[t].contiguous(), res.ref_words[t].contiguous(), s_n, s_r, 4.0, 0.0)[0])
+    judged = encode.psnr_of_words(torch.stack(words), tex, cfg.formats, 256)
+    log(f"judge sweep: kappa 4 delta 0 psnr {np.round(by[(4.0, 0.0)]['psnr_db'], 3)} decoded {np.round(judged, 3)} "
+        f"bytes {by[(4.0, 0.0)]['total_bytes']}")
+    assert all((a == b) or np.isclose(a, b, rtol=0, atol=1e-9) for a, b in zip(by[(4.0, 0.0)]["psnr_db"], judged))

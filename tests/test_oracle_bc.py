@@ -239,18 +239,50 @@ def test_bc1_against_coarse_lattice():
     assert worse == 0
 
 
+def _reachable(bits):
+    """Every value a BC1 palette entry can take in one channel of `bits` bits: the endpoints E(a), and
+    the four-colour points (2 E(a) + E(b) + 1) // 3 and (E(a) + 2 E(b) + 1) // 3 of every pair."""
+    e = [(a << 3) | (a >> 2) if bits == 5 else (a << 2) | (a >> 4) for a in range(1 << bits)]
+    vals = set(e)
+    for x in e:
+        for y in e:
+            vals.add((2 * x + y + 1) // 3)
+            vals.add((x + 2 * y + 1) // 3)
+    return sorted(vals)
+
+
+def test_single_colour_table_is_optimal():
+    # step 8 of REF-BC1: the table's 2/3 point is as near to every value as any value a four-colour
+    # palette entry can take (enumerated as a set, independently of the table's argmin and tie rule)
+    for bits in (5, 6):
+        reach = np.array(_reachable(bits))
+        t = bc.single_colour_table(bits)
+        e = bc.expand5(np.arange(1 << bits)) if bits == 5 else bc.expand6(np.arange(1 << bits))
+        pt = (2 * e[t[:, 0]] + e[t[:, 1]] + 1) // 3
+        best = np.abs(reach[None, :] - np.arange(256)[:, None]).min(axis=1)
+        assert np.array_equal(np.abs(pt - np.arange(256)), best)
+        # every value is within one of a reachable one (136 values reachable with 5 bits, 246 with 6)
+        assert best.max() == 1
+    assert len(_reachable(5)) == 136 and len(_reachable(6)) == 246
+
+
 def test_single_colour_blocks():
+    # a one-colour block: its SSE is 16 times the sum over channels of the least squared error any
+    # palette entry can reach (a lower bound for every BC1 block that REF-BC1 must meet)
     rng = np.random.default_rng(8)
-    col = rng.integers(0, 256, (200, 3))
+    col = np.concatenate([rng.integers(0, 256, (300, 3)), np.repeat(np.arange(256)[:, None], 3, axis=1)])
     tex = np.repeat(col[:, None, :], 16, axis=1).astype(np.uint8)
     w, sse = bc.bc1_encode_ref(tex, return_sse=True)
-    c0, c1, codes = bc.bc1_fields(w)
-    assert (c0 == c1).all() and (codes == 0).all()
-    q = np.stack([(col[:, 0] * 31 + 127) // 255, (col[:, 1] * 63 + 127) // 255,
-                  (col[:, 2] * 31 + 127) // 255], -1)
-    e = np.stack([(q[:, 0] << 3) | (q[:, 0] >> 2), (q[:, 1] << 2) | (q[:, 1] >> 4),
-                  (q[:, 2] << 3) | (q[:, 2] >> 2)], -1)
-    assert (sse == 16 * ((e - col) ** 2).sum(-1)).all()
+    r5, r6 = np.array(_reachable(5)), np.array(_reachable(6))
+    err = [np.abs(r[None, :] - col[:, c][:, None]).min(axis=1) for c, r in ((0, r5), (1, r6), (2, r5))]
+    assert np.array_equal(sse, 16 * sum(e_ * e_ for e_ in err))
+    assert np.array_equal(bc.block_sse(w, tex, 1), sse)
+    # blocks of two colours are not one-colour blocks: step 8 leaves them alone (their words come from
+    # steps 1-7 only, which put a grey step 0/1 on the two endpoints exactly)
+    two = np.zeros((1, 16, 3), np.uint8)
+    two[0, 8:] = 8
+    w2, s2 = bc.bc1_encode_ref(two, return_sse=True)
+    assert s2[0] == 0
     v = rng.integers(0, 256, 100)
     w4, sse4 = bc.bc4_encode_ref(np.repeat(v[:, None], 16, axis=1).astype(np.uint8), return_sse=True)
     assert (sse4 == 0).all() and (bc.bc4_decode(w4) == v[:, None]).all()

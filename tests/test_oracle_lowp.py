@@ -70,26 +70,35 @@ def test_pow2_scale_closed_form():
 
 
 def test_fp8_emulation_is_exact_on_representable_operands():
-    # operands that are E4M3 values times the power-of-two scales pass through unrounded, so the fp8
-    # emulation equals the float64 forward; a dropped or doubled rescale would not
+    # operands that are E4M3 values times the power-of-two scales pass through unrounded, so the middle
+    # layer's fp8 product equals the float64 one; a dropped or doubled rescale would not.  The first
+    # layer and the head take bfloat16 operands: inputs that bfloat16 holds but E4M3 does not pass
+    # through the first layer unrounded.
     from oracle import mlp
     rng = np.random.default_rng(4)
     vals = lowp.e4m3_values()
     small = vals[np.abs(vals) <= 8]
     x = rng.choice(small[small >= 0], (16, 8)) * 0.25
-    layers = [(rng.choice(small, (12, 8)) * 2.0 ** -5, rng.standard_normal(12) * 0.1),
+    ident = (np.eye(8), np.zeros(8))                      # h_1 = relu(x) = x: E4M3 values again
+    layers = [ident,
+              (rng.choice(small, (12, 8)) * 2.0 ** -5, rng.standard_normal(12) * 0.1),
               (rng.choice(small, (5, 12)) * 2.0 ** -4, rng.standard_normal(5) * 0.1)]
     scales = mlp.fp8_scales(layers, x)
     for (sx, sw) in scales:
         assert np.frexp(sx)[0] == 0.5 and np.frexp(sw)[0] == 0.5
-    y64, (hs, _) = mlp.forward(layers, x, "f64")
-    # the first layer's operands are representable by construction: its pre-activations match exactly
-    z64 = x @ layers[0][0].T.astype(np.float64) + layers[0][1]
+    y64, (hs, z64) = mlp.forward(layers, x, "f64")
     _, (_, z8) = mlp.forward(layers, x, "fp8", scales)
-    assert np.array_equal(z8[0], z64)
+    assert np.array_equal(z8[0], z64[0]) and np.array_equal(z8[1], z64[1])
     # and every scaled layer input stays inside the E4M3 range
     for h, (sx, _) in zip(hs, scales):
         assert np.abs(h / sx).max() <= 448.0
+    # bfloat16-exact inputs with more than four significant bits: exact through the first layer and the
+    # head, rounded by the E4M3 middle layer
+    xb = np.full((2, 8), 1.0 + 2.0 ** -6)
+    _, (_, zb) = mlp.forward(layers, xb, "fp8", mlp.fp8_scales(layers, xb))
+    assert np.array_equal(zb[0], xb @ np.eye(8))
+    _, (_, zf) = mlp.forward(layers, xb, "f64")
+    assert not np.array_equal(zb[1], zf[1])
 
 
 def test_bf16_backward_emulation():
