@@ -236,6 +236,29 @@ def _plain(x):
     raise TypeError(f"not JSON serializable: {type(x).__name__}")
 
 
+def naive_ablation(args, cfg, tex, ntbc_psnr):
+    """The naive approach (Sec. 3.1: weight head, two-stage 80/20 training) encoded with the same
+    steps, batch, seed and training precision as NTBC, its blocks inferred in BF16: PSNR per texture
+    beside NTBC's, its model size, and its train step and inference times."""
+    import dataclasses
+    import torch
+    from paper_2407_09543_amd import encode, ntbc
+    ncfg = dataclasses.replace(cfg, variant="naive")
+    log(f"naive ablation: {args.encode_steps} steps + 10% QAT")
+    res = encode.encode_material(tex, ncfg, steps=args.encode_steps, batch=args.batch, seed=3,
+                                 precision=ntbc.BF16, train_precision=ntbc.PRECISIONS[args.train_precision])
+    p = encode.psnr_of_words(res.ntbc_words, tex, cfg.formats, args.size)
+    out = torch.empty_like(res.ntbc_words)
+    ms = time_call(lambda: res.model.infer(ntbc.BF16, out=out, reuse_packed=True), 10, 2, torch)
+    return {"psnr_db_naive": p, "psnr_db_ntbc": ntbc_psnr,
+            "ntbc_minus_naive_db": [None if a is None or b is None else a - b for a, b in zip(ntbc_psnr, p)],
+            "model_bytes_bf16_weights": encode.model_bytes(ncfg, 2), "head_dim": ncfg.head_dim,
+            "stage2_from_step": (4 * res.steps) // 5, "steps": res.steps,
+            "ms_per_train_step": res.train_seconds * 1e3 / res.steps,
+            "inference_ms_bf16": ms, "inference_blocks_per_s": res.ntbc_words.numel() / (ms * 1e-3),
+            "note": "the naive model's inference takes the LDS-staged epilogue (no register-resident instance)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +276,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-material decode")
+    ap.add_argument("--no-naive", action="store_true", help="skip the naive-approach ablation encode")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -332,6 +356,8 @@ def main():
                                          "psnr_db": encode.downsampled_ref_psnr(tex, cfg.formats, args.size)},
         }
         model_note = "parameters trained by the encode above"
+        if not args.no_naive:
+            encode_info["naive_ablation"] = naive_ablation(args, cfg, tex, ntbc_psnr)
     n_blocks = cfg.n_positions * len(cfg.formats)
     # FP8 E4M3 scales from a 65,536-block calibration sample (not part of the timed inference)
     torch.cuda.synchronize()

@@ -27,7 +27,9 @@
  *              times, ReLU) -> head_dim (sigmoid).
  *   Heads      head_dim floats per block position: the endpoint head (per texture in order: BC1 ->
  *              R0 G0 B0 R1 G1 B1, BC4 -> e0 e1) followed by the colour head, texel-major
- *              [texel 0..15][channels of every texture in order].
+ *              [texel 0..15][channels of every texture in order].  Naive variant (NTBC_NAIVE): the
+ *              endpoint head followed by the weight head, texel-major [texel 0..15][one weight per
+ *              texture in order].
  *
  * Paper: S. Fujieda and T. Harada, "Neural Texture Block Compression" (arXiv 2407.09543).  Section
  * numbers below refer to it.
@@ -68,6 +70,16 @@ extern "C" {
 #define NTBC_MAX_TEXTURES 8
 #define NTBC_MAX_LEVELS 12
 
+/* Model variants (ntbc_model_desc.variant). */
+#define NTBC_NTBC 0               /* Sec. 3.2: endpoint head + colour head; each texel takes the palette
+                                     entry nearest to its predicted colour (Eq. dist)                 */
+#define NTBC_NAIVE 1              /* Sec. 3.1, the naive approach: endpoint head + weight head; each
+                                     texel takes the quantised weight w_n nearest to its predicted
+                                     weight (float32 decision, ties to the smaller n): BC1 n/3, with
+                                     1 - w when the endpoints are swapped into four-colour order; BC4
+                                     n/7 (e0 > e1) or (n-1)/5 for n = 1..6 (the interpolated entries).
+                                     Trained in two stages (ntbc_hparams.stage2_from)                 */
+
 /* One material's model shape (host struct; sizes only). */
 typedef struct {
   int32_t n_levels;       /* grid levels L, 1..NTBC_MAX_LEVELS                                      */
@@ -80,6 +92,7 @@ typedef struct {
   int32_t formats[NTBC_MAX_TEXTURES]; /* NTBC_BC1 or NTBC_BC4 per texture, in head order            */
   int32_t blocks_w;       /* block grid = texture size / 4                                           */
   int32_t blocks_h;
+  int32_t variant;        /* NTBC_NTBC (0) or NTBC_NAIVE: head_dim = 6*nBC1 + 2*nBC4 + 16*n_textures */
 } ntbc_model_desc;
 
 /* Model parameters for inference (host struct of device pointers). */
@@ -103,7 +116,8 @@ const char* ntbc_last_error(void);
 /* ---- sizes -------------------------------------------------------------------------------------- */
 
 /* Number of FP32 values in the canonical weight layout of `d`; head_dim = 6*nBC1 + 2*nBC4 +
- * 16*(3*nBC1 + nBC4); grid vertex count sum_l res_l^2.  Host only.  Returns NTBC_EINVAL on a bad desc. */
+ * 16*(3*nBC1 + nBC4) (NTBC_NAIVE: 6*nBC1 + 2*nBC4 + 16*n_textures); grid vertex count sum_l res_l^2.
+ * Host only.  Returns NTBC_EINVAL on a bad desc. */
 int ntbc_model_sizes(const ntbc_model_desc* d, int64_t* n_weights, int32_t* head_dim,
                      int64_t* grid_vertices);
 
@@ -278,6 +292,11 @@ typedef struct {
                                rounded to that scale, which is far finer than FP32's resolution of the
                                sums) and every weight product runs unsplit.  The reported losses are
                                FP32 atomic sums in both modes. */
+  int32_t stage2_from;      /* NTBC_NAIVE only (Sec. 3.1): steps >= stage2_from are the second stage, which
+                               decodes with the quantised weights w_n (the gradient reaches the endpoints
+                               only) and updates only the endpoint head's rows of the last layer's weights
+                               and biases; the grid, the hidden layers and the weight head keep their
+                               values and moments.  The paper's split is the first 80% of the steps. */
 } ntbc_hparams;
 
 /* Block ids passed to the training entry points are clamped into [0, blocks_w*blocks_h). */
@@ -312,12 +331,23 @@ int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float*
                    int32_t n, float temperature, const float* loss_weights, float* losses_out,
                    float* d_heads_out, void* stream);
 
+/* Naive-approach loss (Sec. 3.1; d->variant = NTBC_NAIVE): decoded colours x = (1 - w) e0^ + w e1^ per
+ * texel and channel from the predicted endpoints and weights of heads ([n][head_dim]); stage 1 takes
+ * the continuous weight w, stage 2 the nearest quantised weight w_n of the block's mode (BC4: eight
+ * values when e0^ > e1^; the endpoints stay continuous and unswapped).  losses_out[0] = L = the mean of
+ * (x - c)^2 over n * 16 texels * the channels of every texture, losses_out[1..3] = 0, losses_out[4] = 1
+ * if a head or gradient was not finite (device float[5], overwritten).  d_heads_out = dL/d(heads)
+ * (stage 2: zero on the weight head).  Errors: NTBC_EINVAL (stage not 1 or 2, d->variant not naive). */
+int ntbc_naive_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float* heads, const int32_t* ids,
+                         int32_t n, int32_t stage, float* losses_out, float* d_heads_out, void* stream);
+
 /* One training iteration (Sec. 3.2 training procedure and Eqs. lossNTBC; App. A straight-through
  * estimator; Sec. 3.3 QAT; Sec. 3.4 Adam, learning rates, warm-up and cosine annealing): forward, loss,
  * backward, then dense Adam on grid and weights with the learning rates of step `step` (0-based) of the
  * schedule.  losses_out (device float[5]) receives the
  * four losses and the skip flag: when a non-finite value is seen the parameters and moments are left
- * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions.  */
+ * untouched and losses_out[4] = 1.  batch_ids: device int32[batch] block positions.  NTBC_NAIVE models
+ * train with ntbc_naive_loss_grad's loss instead (Sec. 3.1), stage 2 from step h->stage2_from on. */
 int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const ntbc_targets* t,
                     const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
                     float* losses_out, void* workspace, size_t workspace_bytes, void* stream);

@@ -36,6 +36,8 @@ int make_shape(const ntbc_model_desc* d, Shape* s) {
   NTBC_REQUIRE(d->n_hidden >= 1 && d->n_hidden <= 4, "n_hidden %d out of 1..4", d->n_hidden);
   NTBC_REQUIRE(d->n_textures >= 1 && d->n_textures <= NTBC_MAX_TEXTURES, "n_textures %d out of 1..%d",
                d->n_textures, NTBC_MAX_TEXTURES);
+  NTBC_REQUIRE(d->variant == NTBC_NTBC || d->variant == NTBC_NAIVE, "variant %d is not NTBC_NTBC or NTBC_NAIVE",
+               d->variant);
   NTBC_REQUIRE(d->blocks_w >= 1 && d->blocks_h >= 1, "block grid %dx%d must be positive", d->blocks_w,
                d->blocks_h);
   const int64_t top = (int64_t)d->base_res << (d->n_levels - 1);
@@ -62,7 +64,8 @@ int make_shape(const ntbc_model_desc* d, Shape* s) {
   }
   s->endpoint_dim = e;
   s->channels = c;
-  s->head_dim = e + 16 * c;
+  s->naive = d->variant == NTBC_NAIVE;
+  s->head_dim = e + 16 * (s->naive ? d->n_textures : c);
   s->blocks_w = d->blocks_w;
   s->blocks_h = d->blocks_h;
   s->n_positions = (int64_t)d->blocks_w * d->blocks_h;

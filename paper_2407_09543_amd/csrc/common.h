@@ -38,6 +38,7 @@ struct Shape {
   int n_textures, formats[NTBC_MAX_TEXTURES];
   int ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
   int endpoint_dim, channels, head_dim;
+  int naive;  // NTBC_NAIVE: the weight head (16 * n_textures values) replaces the colour head
   int blocks_w, blocks_h;
   int64_t n_positions, grid_vertices, n_weights;
   int64_t level_offset[NTBC_MAX_LEVELS + 1];

@@ -346,5 +346,44 @@ __device__ __forceinline__ uint32_t bc4_code(const Bc4Pal& p, float x) {
   return (p.map >> sh) & 7u;
 }
 
+// Naive approach (Sec. 3.1): the weight index n of the quantised weight nearest to a predicted weight
+// w, |w - w_n| in float32 with the first minimum taken (ties to the smaller n); *wn receives w_n.
+// BC1: w_n = n/3; BC4: n/7 in eight-value mode, (n-1)/5 for n = 1..6 in six-value mode (the entries 0
+// and 7 are the constants 0 and 1, which carry no weight).  The table values are float32 quotients.
+__device__ __forceinline__ int naive_index_bc1(float w, float* wn) {
+  constexpr float kW[4] = {0.0f, 1.0f / 3.0f, 2.0f / 3.0f, 1.0f};
+  float best = fabsf(__fsub_rn(w, kW[0])), v = kW[0];
+  int n_best = 0;
+#pragma unroll
+  for (int n = 1; n < 4; ++n) {
+    const float d = fabsf(__fsub_rn(w, kW[n]));
+    const bool take = d < best;
+    n_best = take ? n : n_best;
+    v = take ? kW[n] : v;
+    best = take ? d : best;
+  }
+  *wn = v;
+  return n_best;
+}
+
+__device__ __forceinline__ int naive_index_bc4(float w, bool eight, float* wn) {
+  constexpr float kW8[8] = {0.0f, 1.0f / 7.0f, 2.0f / 7.0f, 3.0f / 7.0f, 4.0f / 7.0f, 5.0f / 7.0f, 6.0f / 7.0f, 1.0f};
+  constexpr float kW6[8] = {0.0f, 1.0f / 5.0f, 2.0f / 5.0f, 3.0f / 5.0f, 4.0f / 5.0f, 1.0f, 0.0f, 0.0f};
+  const int count = eight ? 8 : 6, first = eight ? 0 : 1;
+  float best = 0.0f, v = 0.0f;
+  int n_best = first;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float wk = eight ? kW8[k] : kW6[k];
+    const float d = fabsf(__fsub_rn(w, wk));
+    const bool take = k == 0 || (k < count && d < best);
+    n_best = take ? first + k : n_best;
+    v = take ? wk : v;
+    best = take ? d : best;
+  }
+  *wn = v;
+  return n_best;
+}
+
 }  // namespace dev
 }  // namespace ntbc

@@ -140,6 +140,7 @@ struct InferArgs {
   int head_dim, head_stride;
   int n_textures, formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
   int endpoint_dim, channels;
+  int naive;                    // weight head (Sec. 3.1): texel i's weight of texture t at endpoint_dim + i*n_textures + t
   int64_t first, n;
   uint64_t* out;                // [n_textures][n]
   float* heads;                 // optional [n][head_dim]
@@ -255,15 +256,29 @@ __device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int
   for (int t = 0; t < a.n_textures; ++t) {
     const float* ep = yj + a.ep_off[t];
     const float* col = yj + a.endpoint_dim + a.ch_off[t];
+    const float* wt = yj + a.endpoint_dim + t;  // naive: texel tx's weight at wt[tx * n_textures]
     uint64_t bits;
     if (a.formats[t] == NTBC_BC1) {
       const dev::Bc1Pal p = dev::bc1_from_heads(ep, tab);
       uint32_t codes = 0;
+      if (a.naive) {
+        // stored c0 is the predicted endpoint 1 when the endpoints were swapped: the weight turns round
+        const bool swap = dev::rgb565(ep[0], ep[1], ep[2]) < dev::rgb565(ep[3], ep[4], ep[5]);
 #pragma unroll
-      for (int i = 0; i < TPL; ++i) {
-        const int tx = q * TPL + i;
-        const float* c = col + tx * a.channels;
-        codes |= dev::bc1_code(p, c[0], c[1], c[2]) << (2 * tx);
+        for (int i = 0; i < TPL; ++i) {
+          const int tx = q * TPL + i;
+          const float w = wt[tx * a.n_textures];
+          float wn;
+          const int n = dev::naive_index_bc1(swap ? __fsub_rn(1.0f, w) : w, &wn);
+          codes |= ((p.map >> (2 * n)) & 3u) << (2 * tx);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+          const int tx = q * TPL + i;
+          const float* c = col + tx * a.channels;
+          codes |= dev::bc1_code(p, c[0], c[1], c[2]) << (2 * tx);
+        }
       }
 #pragma unroll
       for (int o = P; o < 64; o <<= 1) codes |= __shfl_xor(codes, o);
@@ -274,7 +289,14 @@ __device__ void pack_blocks(const InferArgs& a, const float* __restrict__ y, int
 #pragma unroll
       for (int i = 0; i < TPL; ++i) {
         const int tx = q * TPL + i;
-        codes |= (uint64_t)dev::bc4_code(p, col[tx * a.channels]) << (3 * tx);
+        uint32_t code;
+        if (a.naive) {
+          float wn;
+          code = (p.map >> (3 * dev::naive_index_bc4(wt[tx * a.n_textures], p.eight, &wn))) & 7u;
+        } else {
+          code = dev::bc4_code(p, col[tx * a.channels]);
+        }
+        codes |= (uint64_t)code << (3 * tx);
       }
 #pragma unroll
       for (int o = P; o < 64; o <<= 1) {
@@ -1423,7 +1445,7 @@ RegPlan reg_plan(const Plan& p, bool batch = false) {
     if (s.formats[t] == NTBC_BC1) r.tex[nb1++] = t;
   for (int t = 0; t < s.n_textures; ++t)
     if (s.formats[t] == NTBC_BC4) r.tex[nb1 + nb4++] = t;
-  if (reg_instance(p, nb1, nb4, batch) && 27 * nb1 + 9 * nb4 <= 16 * p.otiles[s.n_layers - 1]) {
+  if (!s.naive && reg_instance(p, nb1, nb4, batch) && 27 * nb1 + 9 * nb4 <= 16 * p.otiles[s.n_layers - 1]) {
     r.nb1 = nb1;
     r.nb4 = nb4;
   }
@@ -1500,6 +1522,7 @@ InferArgs infer_args(const Plan& p, const ntbc_model_desc* d, const ntbc_params*
   }
   a.endpoint_dim = s.endpoint_dim;
   a.channels = s.channels;
+  a.naive = s.naive;
   a.fp8_scales = prm->fp8_scales;
   a.stride = 1;
   return a;

@@ -972,6 +972,137 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
   }
 }
 
+// ------------------------------------------------------------------------------------------ naive loss
+// Naive approach (Sec. 3.1): the weight head holds texel i's weight of texture t at E + i*T + t.
+struct NaiveLossArgs {
+  const float* y;
+  float* dy;
+  const int32_t* ids;
+  int64_t n, n_positions;
+  int ld, E, T, blocks_w;
+  int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES];
+  const uint8_t* tex[NTBC_MAX_TEXTURES];
+  float inv_n;     // 1 / (n 16 C)
+  float* losses;   // [5]
+  int dsigmoid;    // write dL/dZ through the sigmoid instead of dL/dY
+  int stage;       // 1: continuous weights; 2: the quantised weights w_n, no weight gradient
+};
+
+// One texture of one position, texel row `sub`: decoded colours x = (1 - w) e0^ + w e1^, the squared
+// error against the texels, the weight gradients (stage 1) and the partial endpoint gradients.
+template <int CH>
+__device__ __forceinline__ void naive_texture_loss(const NaiveLossArgs& a, int64_t p, int t, int id, int sub, float* loss,
+                                                   bool* bad, float de0[3], float de1[3]) {
+  const float* yp = a.y + p * a.ld;
+  float* dyp = a.dy + p * a.ld;
+  const int e = a.ep_off[t];
+  float eh0[3] = {0, 0, 0}, eh1[3] = {0, 0, 0};
+#pragma unroll
+  for (int ch = 0; ch < CH; ++ch) {
+    eh0[ch] = yp[e + ch];
+    eh1[ch] = yp[e + CH + ch];
+  }
+  const bool eight = CH == 3 ? true : eh0[0] > eh1[0];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) de0[ch] = de1[ch] = 0.0f;
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
+  const uint8_t* row = a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+  constexpr float k255 = 1.0f / 255.0f;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = 4 * sub + x;
+    const int wi = a.E + i * a.T + t;
+    const float w = yp[wi];
+    float wq = w;
+    if (a.stage == 2) {
+      if (CH == 3)
+        dev::naive_index_bc1(w, &wq);
+      else
+        dev::naive_index_bc4(w, eight, &wq);
+    }
+    float dw = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+      const float c = (float)row[x * CH + ch] * k255;
+      const float r = (1.0f - wq) * eh0[ch] + wq * eh1[ch] - c;
+      *loss += r * r;
+      const float g = 2.0f * r * a.inv_n;
+      de0[ch] += g * (1.0f - wq);
+      de1[ch] += g * wq;
+      dw += g * (eh1[ch] - eh0[ch]);
+    }
+    const float gw = a.stage == 1 ? dw : 0.0f;
+    dyp[wi] = a.dsigmoid ? gw * w * (1.0f - w) : gw;
+    *bad |= !isfinite(dw);
+  }
+}
+
+// Four lanes per (texture, position), one wave per texture, as k_loss_grad.
+__global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_naive(NaiveLossArgs a) {
+  __shared__ float part[NTBC_MAX_TEXTURES];
+  __shared__ int part_bad[NTBC_MAX_TEXTURES];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = wave;
+  const int64_t groups = (a.n + 15) / 16;
+  float loss = 0.0f;
+  bool bad = false;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
+    const int64_t p = grp * 16 + (lane >> 2);
+    const int sub = lane & 3;
+    const bool active = p < a.n;
+    if (active) {
+      const int id = clamp_id(a.ids[p], a.n_positions);
+      if (a.formats[t] == NTBC_BC1)
+        naive_texture_loss<3>(a, p, t, id, sub, &loss, &bad, de0, de1);
+      else
+        naive_texture_loss<1>(a, p, t, id, sub, &loss, &bad, de0, de1);
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+      for (int off = 1; off < 4; off <<= 1) {
+        de0[ch] += __shfl_xor(de0[ch], off);
+        de1[ch] += __shfl_xor(de1[ch], off);
+      }
+    }
+    if (active && sub == 0) {
+      const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
+      float* dyp = a.dy + p * a.ld + a.ep_off[t];
+      const float* yp = a.y + p * a.ld + a.ep_off[t];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        if (ch < ch_n) {
+          const float y0 = yp[ch], y1 = yp[ch_n + ch];
+          dyp[ch] = a.dsigmoid ? de0[ch] * y0 * (1.0f - y0) : de0[ch];
+          dyp[ch_n + ch] = a.dsigmoid ? de1[ch] * y1 * (1.0f - y1) : de1[ch];
+          bad |= !isfinite(de0[ch]) || !isfinite(de1[ch]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off);
+  const unsigned long long anybad = __ballot(bad);
+  if (lane == 0) {
+    part[wave] = loss;
+    part_bad[wave] = anybad != 0;
+  }
+  __syncthreads();
+  const int n_waves = (int)(blockDim.x / 64);
+  if (threadIdx.x == 0) {
+    float sum = 0.0f;
+    int any = 0;
+    for (int w = 0; w < n_waves; ++w) {
+      sum += part[w];
+      any |= part_bad[w];
+    }
+    atomicAdd(&a.losses[0], sum * a.inv_n);
+    if (any) atomicExch(&a.losses[4], 1.0f);
+  }
+}
+
 // Sets flag[0] = 1 if any of x[0..n) is not finite.
 __global__ void k_check_finite(const float* __restrict__ x, int64_t n, float* __restrict__ flag) {
   bool bad = false;
@@ -2001,6 +2132,35 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   return check_launch("k_loss_grad");
 }
 
+// Naive-approach loss (stage 1 or 2) of heads [n][ld]; dsigmoid as loss_grad.
+int naive_loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, int stage,
+                    float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0) {
+  int st = fill(losses, 5, 0.0f, strm);
+  if (st != NTBC_OK) return st;
+  NaiveLossArgs a{};
+  a.y = heads;
+  a.dy = dheads;
+  a.ids = ids;
+  a.n = n;
+  a.n_positions = s.n_positions;
+  a.ld = ld > 0 ? ld : s.head_dim;
+  a.E = s.endpoint_dim;
+  a.T = s.n_textures;
+  a.blocks_w = s.blocks_w;
+  for (int i = 0; i < s.n_textures; ++i) {
+    a.formats[i] = s.formats[i];
+    a.ep_off[i] = s.ep_off[i];
+    a.tex[i] = t->texels[i];
+  }
+  a.inv_n = (float)(1.0 / ((double)n * 16.0 * s.channels));
+  a.losses = losses;
+  a.dsigmoid = dsigmoid ? 1 : 0;
+  a.stage = stage;
+  hipLaunchKernelGGL(k_loss_naive, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks))),
+                     dim3(64 * s.n_textures), 0, strm, a);
+  return check_launch("k_loss_naive");
+}
+
 int check_targets(const Shape& s, const ntbc_targets* t) {
   NTBC_REQUIRE(t != nullptr && t->ref_blocks != nullptr, "targets or ref_blocks is NULL");
   for (int i = 0; i < s.n_textures; ++i) NTBC_REQUIRE(t->texels[i] != nullptr, "targets texels[%d] is NULL", i);
@@ -2346,6 +2506,23 @@ extern "C" int ntbc_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, c
   return loss_grad(s, t, heads, ids, n, temperature, loss_weights, losses_out, d_heads_out, as_stream(stream));
 }
 
+extern "C" int ntbc_naive_loss_grad(const ntbc_model_desc* d, const ntbc_targets* t, const float* heads,
+                                    const int32_t* ids, int32_t n, int32_t stage, float* losses_out, float* d_heads_out,
+                                    void* stream) {
+  Shape s;
+  int st = make_shape(d, &s);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(s.naive, "ntbc_naive_loss_grad needs variant NTBC_NAIVE");
+  NTBC_REQUIRE(stage == 1 || stage == 2, "stage %d is not 1 or 2", stage);
+  st = check_targets(s, t);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(n >= 0, "n %d < 0", n);
+  NTBC_REQUIRE(losses_out != nullptr, "losses_out is NULL");
+  if (n == 0) return fill(losses_out, 5, 0.0f, as_stream(stream));
+  NTBC_REQUIRE(heads && ids && d_heads_out, "heads, ids or d_heads_out is NULL");
+  return naive_loss_grad(s, t, heads, ids, n, stage, losses_out, d_heads_out, as_stream(stream));
+}
+
 extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* tsd, const ntbc_targets* t,
                                const int32_t* batch_ids, int32_t batch, int64_t step, const ntbc_hparams* h,
                                float* losses_out, void* workspace, size_t workspace_bytes, void* stream) {
@@ -2367,6 +2544,8 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   const Shape& s = c.s;
   const bool qat = h->qat != 0;
   const int64_t ng = s.grid_vertices * s.n_features;
+  // naive approach: stage 2 (quantised weights, endpoint head only) from step stage2_from on
+  const int stage = s.naive && step >= h->stage2_from ? 2 : 1;
   FusedPlan f;
   if (c.bf16 && fused_plan(s, &f)) {
     // bfloat16 products with the layers chained in registers
@@ -2376,7 +2555,9 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
     float* dz = reinterpret_cast<float*>(ws + l.dz);
     st = fused_forward(c, f, tsd->grid, tsd->weights, qat, batch_ids, y, kFHeadLd);
     if (st != NTBC_OK) return st;
-    st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, dz, c.strm, true, kFHeadLd);
+    st = s.naive ? naive_loss_grad(s, t, y, batch_ids, c.n, stage, losses_out, dz, c.strm, true, kFHeadLd)
+                 : loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, dz, c.strm, true,
+                             kFHeadLd);
     if (st != NTBC_OK) return st;
     st = fill(tsd->d_grid, ng, 0.0f, c.strm);
     if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
@@ -2388,7 +2569,9 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
     st = forward(c, tsd->grid, tsd->weights, qat, batch_ids, y);
     if (st != NTBC_OK) return st;
     // dL/dZ of the head pre-activations straight from the loss kernel (the sigmoid derivative fused)
-    st = loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy, c.strm, true);
+    st = s.naive ? naive_loss_grad(s, t, y, batch_ids, c.n, stage, losses_out, c.ws + c.lay.dy, c.strm, true)
+                 : loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, c.ws + c.lay.dy,
+                             c.strm, true);
     if (st != NTBC_OK) return st;
     st = fill(tsd->d_grid, ng, 0.0f, c.strm);
     if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
@@ -2412,12 +2595,23 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   aa.bc1 = (float)(1.0 / (1.0 - std::pow((double)h->beta1, tt)));
   aa.bc2 = (float)(1.0 / (1.0 - std::pow((double)h->beta2, tt)));
   aa.flag = losses_out + 4;
+  aa.lr = (float)lr_at(h->lr_mlp);
+  if (stage == 2) {
+    // only the endpoint head's rows of the last layer: W rows 0..E-1 and b[0..E-1], each contiguous
+    const int last = s.n_layers - 1;
+    const int64_t nw = (int64_t)s.endpoint_dim * s.layer_in[last];
+    const int64_t ranges[2][2] = {{s.w_off[last], nw}, {s.b_off[last], s.endpoint_dim}};
+    for (const auto& r : ranges)
+      hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(r[1], 256), 8192)), dim3(256), 0, c.strm,
+                         tsd->weights + r[0], tsd->d_weights + r[0], tsd->m_weights + r[0], tsd->v_weights + r[0], r[1],
+                         aa);
+    return check_launch("k_adam");
+  }
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 8192)), dim3(256), 0, c.strm,
+                     tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, aa);
   aa.lr = (float)lr_at(h->lr_grid);
   hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(ng, 256), 8192)), dim3(256), 0, c.strm, tsd->grid,
                      tsd->d_grid, tsd->m_grid, tsd->v_grid, ng, aa);
-  aa.lr = (float)lr_at(h->lr_mlp);
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 8192)), dim3(256), 0, c.strm,
-                     tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, aa);
   return check_launch("k_adam");
 }
 

@@ -20,6 +20,7 @@ BC1, BC4 = 1, 4
 FP32, BF16, FP8_E4M3, FP16 = 0, 1, 2, 3
 GRID_F32, GRID_U8 = 0, 1
 MAX_TEXTURES = 8
+NTBC, NAIVE = 0, 1  # model variants: NTBC (Sec. 3.2) and the naive approach (Sec. 3.1)
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3}
 
 
@@ -34,7 +35,7 @@ class ModelDesc(ctypes.Structure):
                 ("n_features", ctypes.c_int32), ("grid_dtype", ctypes.c_int32),
                 ("hidden_width", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
                 ("n_textures", ctypes.c_int32), ("formats", ctypes.c_int32 * MAX_TEXTURES),
-                ("blocks_w", ctypes.c_int32), ("blocks_h", ctypes.c_int32)]
+                ("blocks_w", ctypes.c_int32), ("blocks_h", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -59,7 +60,7 @@ class HParams(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("temperature", ctypes.c_float),
                 ("warmup", ctypes.c_int32), ("total_steps", ctypes.c_int32), ("qat", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("loss_weights", ctypes.c_float * 4),
-                ("deterministic", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("stage2_from", ctypes.c_int32)]
 
 
 _lib = None
@@ -95,6 +96,8 @@ _SIGNATURES = {
                       ctypes.c_int),
     "ntbc_loss_grad": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TargetsC), _P, _P, _I32, _F, _P, _P, _P, _P],
                        ctypes.c_int),
+    "ntbc_naive_loss_grad": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TargetsC), _P, _P, _I32, _I32, _P, _P, _P],
+                             ctypes.c_int),
     "ntbc_train_step": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TrainStateC), ctypes.POINTER(TargetsC), _P,
                          _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P], ctypes.c_int),
     "ntbc_quantize_grid": ([ctypes.POINTER(ModelDesc), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
@@ -140,7 +143,7 @@ def _stream():
 
 
 def make_desc(n_levels, base_res, n_features, grid_u8, hidden, n_hidden, formats: Sequence[int],
-              blocks_w, blocks_h) -> ModelDesc:
+              blocks_w, blocks_h, variant: int = 0) -> ModelDesc:
     d = ModelDesc()
     d.n_levels, d.base_res, d.n_features = n_levels, base_res, n_features
     d.grid_dtype = GRID_U8 if grid_u8 else GRID_F32
@@ -149,13 +152,14 @@ def make_desc(n_levels, base_res, n_features, grid_u8, hidden, n_hidden, formats
     for i, f in enumerate(formats):
         d.formats[i] = int(f)
     d.blocks_w, d.blocks_h = blocks_w, blocks_h
+    d.variant = int(variant)
     return d
 
 
 def desc_from_config(cfg) -> ModelDesc:
     """ModelDesc of a config object with the fields of synth.ModelConfig."""
     return make_desc(cfg.n_levels, cfg.base_res, cfg.n_features, cfg.grid_u8, cfg.hidden, cfg.n_hidden,
-                     cfg.formats, cfg.blocks_w, cfg.blocks_h)
+                     cfg.formats, cfg.blocks_w, cfg.blocks_h, NAIVE if getattr(cfg, "variant", "ntbc") == "naive" else NTBC)
 
 
 def model_sizes(desc: ModelDesc):
@@ -441,6 +445,15 @@ def loss_grad(desc: ModelDesc, targets: Targets, heads: torch.Tensor, ids: torch
     return losses, dh
 
 
+def naive_loss_grad(desc: ModelDesc, targets: Targets, heads: torch.Tensor, ids: torch.Tensor, stage: int):
+    """Naive-approach loss (losses float32[5] = L, 0, 0, 0, nonfinite flag; dL/dheads) of stage 1 or 2."""
+    losses = torch.empty(5, dtype=torch.float32, device=heads.device)
+    dh = torch.empty_like(heads)
+    _check(lib().ntbc_naive_loss_grad(ctypes.byref(desc), ctypes.byref(targets.c), _ptr(heads.contiguous()),
+                                      _ptr(ids), ids.numel(), stage, _ptr(losses), _ptr(dh), _stream()))
+    return losses, dh
+
+
 def quantize_grid(desc: ModelDesc, grid: torch.Tensor):
     """(codes uint8 [V, F], scale float32 [L], zero int32 [L]) of an FP32 grid."""
     codes = torch.empty(grid.shape, dtype=torch.uint8, device=grid.device)
@@ -458,7 +471,7 @@ class Trainer:
     def __init__(self, desc: ModelDesc, grid: torch.Tensor, weights: torch.Tensor, targets: Targets, batch: int,
                  total_steps: int, lr_grid: float = 0.01, lr_mlp: float = 0.005, temperature: float = 0.01,
                  warmup: int = 10, loss_weights=(1.0, 1.0, 1.0, 1.0), precision: int = FP32,
-                 deterministic: bool = False):
+                 deterministic: bool = False, stage2_from: Optional[int] = None):
         self.desc = desc
         self.grid = grid.clone().contiguous()
         self.weights = weights.clone().contiguous()
@@ -472,8 +485,11 @@ class Trainer:
         self.losses = torch.zeros(5, dtype=torch.float32, device=dev)
         self.state = TrainStateC(*[t.data_ptr() for t in (self.grid, self.weights, self.m_grid, self.v_grid,
                                                           self.m_w, self.v_w, self.d_grid, self.d_w)])
+        # naive variant: the paper's two stages split the steps 80/20 (Sec. 3.1)
+        if stage2_from is None:
+            stage2_from = (4 * total_steps) // 5
         self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, precision,
-                         (ctypes.c_float * 4)(*loss_weights), int(deterministic))
+                         (ctypes.c_float * 4)(*loss_weights), int(deterministic), int(stage2_from))
 
     def step(self, ids: torch.Tensor, step: int, qat: bool = False) -> torch.Tensor:
         """One step on the batch ids (int32, device); returns the device losses[5] (overwritten)."""

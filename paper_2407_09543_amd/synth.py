@@ -229,6 +229,7 @@ class ModelConfig:
     formats: Tuple[int, ...]
     blocks_w: int
     blocks_h: int
+    variant: str = "ntbc"    # "ntbc" (colour head) or "naive" (weight head, Sec. 3.1)
 
     @property
     def in_dim(self) -> int:
@@ -244,6 +245,8 @@ class ModelConfig:
 
     @property
     def head_dim(self) -> int:
+        if self.variant == "naive":
+            return self.endpoint_dim + 16 * len(self.formats)
         return self.endpoint_dim + 16 * self.colour_channels
 
     @property
