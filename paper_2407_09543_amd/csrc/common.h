@@ -51,6 +51,18 @@ int make_shape(const ntbc_model_desc* d, Shape* s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// log2(2 * blocks) when that is a power of two and every numerator of the grid-corner arithmetic
+// ((2b + 1) res - blocks, and the clamp bound (res - 1) 2 blocks) fits in 31 bits at the finest level,
+// else -1: the corner computation then takes shifts instead of divisions.
+inline int pow2_shift(const Shape& s, int blocks) {
+  const int64_t den = 2 * (int64_t)blocks;
+  const int64_t top = (int64_t)s.base_res << (s.n_levels - 1);
+  if ((den & (den - 1)) != 0 || (2 * (int64_t)blocks + 1) * top >= (1ll << 31) || top * den >= (1ll << 31)) return -1;
+  int sh = 0;
+  while ((1ll << sh) < den) ++sh;
+  return sh;
+}
+
 // Workspace bytes of the training / forward / backward entry points for `batch` positions.
 int64_t train_workspace_bytes(const Shape& s, int64_t batch);
 

@@ -1493,16 +1493,8 @@ InferArgs infer_args(const Plan& p, const ntbc_model_desc* d, const ntbc_params*
   a.grid.blocks_w = s.blocks_w;
   a.grid.blocks_h = s.blocks_h;
   for (int l = 0; l <= s.n_levels; ++l) a.grid.level_offset[l] = s.level_offset[l];
-  auto pow2_shift = [&](int blocks) {
-    const int64_t den = 2 * (int64_t)blocks;
-    const int64_t top = (int64_t)s.base_res << (s.n_levels - 1);
-    if ((den & (den - 1)) != 0 || (2 * (int64_t)blocks + 1) * top >= (1ll << 31) || top * den >= (1ll << 31)) return -1;
-    int sh = 0;
-    while ((1ll << sh) < den) ++sh;
-    return sh;
-  };
-  a.grid.shift_x = pow2_shift(s.blocks_w);
-  a.grid.shift_y = pow2_shift(s.blocks_h);
+  a.grid.shift_x = pow2_shift(s, s.blocks_w);
+  a.grid.shift_y = pow2_shift(s, s.blocks_h);
   a.grid.fast8 = a.grid.u8 != nullptr && s.n_features == 8 && a.grid.shift_x >= 0 && a.grid.shift_y >= 0 &&
                  s.level_offset[s.n_levels] * 8 < (1ll << 31);
   for (int k = 0; k < s.n_layers; ++k) {

@@ -160,6 +160,7 @@ struct FeatArgs {
   const int32_t* ids;
   int64_t n;
   int n_levels, base_res, F, blocks_w, blocks_h;
+  int shift_x, shift_y;  // pow2_shift of the block grid, -1: the division path
   int64_t level_offset[NTBC_MAX_LEVELS + 1];
   float* x;          // [n][L*F]
 };
@@ -170,11 +171,11 @@ struct Tap {
   float w[4];
 };
 
-__device__ __forceinline__ Tap grid_tap(const FeatArgs& a, int64_t p, int l) {
-  const int id = clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h);
+__device__ __forceinline__ Tap grid_tap_id(const FeatArgs& a, int id, int l) {
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int res = a.base_res << l;
-  const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+  const dev::Corner cx = a.shift_x >= 0 ? dev::corner_pow2(bx, a.blocks_w, res, a.shift_x) : dev::corner(bx, a.blocks_w, res);
+  const dev::Corner cy = a.shift_y >= 0 ? dev::corner_pow2(by, a.blocks_h, res, a.shift_y) : dev::corner(by, a.blocks_h, res);
   const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
   Tap t;
   t.vtx[0] = v00;
@@ -186,6 +187,10 @@ __device__ __forceinline__ Tap grid_tap(const FeatArgs& a, int64_t p, int l) {
   t.w[2] = (1.0f - cx.f) * cy.f;
   t.w[3] = cx.f * cy.f;
   return t;
+}
+
+__device__ __forceinline__ Tap grid_tap(const FeatArgs& a, int64_t p, int l) {
+  return grid_tap_id(a, clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h), l);
 }
 
 // One thread per (position, level, feature); the F lanes of a (position, level) read the F
@@ -216,11 +221,10 @@ __global__ void __launch_bounds__(kBlock) k_features(FeatArgs a) {
 // scale (a power of two, *scale) and added with 64-bit integer atomics, whose sum does not depend on
 // the order.
 template <typename Acc>
-__device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l, int f,
-                                            Acc* __restrict__ dst, float scale) {
-  const float df = dx[(p * a.n_levels + l) * a.F + f];
+__device__ __forceinline__ void scatter_tap(const FeatArgs& a, float df, int id, int l, int f, Acc* __restrict__ dst,
+                                            float scale) {
   if (df == 0.0f) return;
-  const Tap t = grid_tap(a, p, l);
+  const Tap t = grid_tap_id(a, id, l);
   const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
   const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
 #pragma unroll
@@ -239,6 +243,14 @@ __device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __re
   }
 }
 
+template <typename Acc>
+__device__ __forceinline__ void scatter_one(const FeatArgs& a, const float* __restrict__ dx, int64_t p, int l, int f,
+                                            Acc* __restrict__ dst, float scale) {
+  const float df = dx[(p * a.n_levels + l) * a.F + f];
+  if (df == 0.0f) return;
+  scatter_tap<Acc>(a, df, clamp_id(a.ids[p], (int64_t)a.blocks_w * a.blocks_h), l, f, dst, scale);
+}
+
 // Levels [first_level, n_levels): one thread per (position, level, feature), feature fastest so that
 // the atomics of a corner land in one cache line.
 template <typename Acc>
@@ -252,27 +264,70 @@ __global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __r
   scatter_one<Acc>(a, dx, pl / nl, first_level + (int)(pl % nl), f, dgrid, det_scale ? *det_scale : 1.0f);
 }
 
-// Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a strided share of the
-// batch in LDS, then adds its non-zero sums to the grid gradient -- one global atomic per touched
-// value per block instead of one per position.
+// Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a contiguous share of the
+// batch in LDS and writes its sums to its own row of `part` ([gridDim.x][nv]); k_scatter_reduce then
+// adds the rows in block order.  No global atomics, and the sum does not depend on the schedule.
+constexpr int kCoarseBlocks = 512;
+constexpr int kCoarseThreads = 1024;  // sixteen waves share a block's LDS sums: two blocks fill a CU
+constexpr int kCoarseLds = 48 * 1024;
+
 template <typename Acc>
-__global__ void __launch_bounds__(kBlock) k_scatter_coarse(FeatArgs a, const float* __restrict__ dx, Acc* __restrict__ dgrid,
+__global__ void __launch_bounds__(kCoarseThreads) k_scatter_coarse(FeatArgs a, const float* __restrict__ dx, Acc* __restrict__ part,
                                                            int n_coarse, const float* __restrict__ det_scale) {
   extern __shared__ __align__(8) unsigned char acc_raw[];
   Acc* acc = reinterpret_cast<Acc*>(acc_raw);
   const float scale = det_scale ? *det_scale : 1.0f;
   const int64_t nv = a.level_offset[n_coarse] * a.F;
-  for (int64_t i = threadIdx.x; i < nv; i += kBlock) acc[i] = (Acc)0;
+  for (int64_t i = threadIdx.x; i < nv; i += kCoarseThreads) acc[i] = (Acc)0;
   __syncthreads();
   const int64_t per_pos = (int64_t)n_coarse * a.F;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < a.n * per_pos; e += (int64_t)gridDim.x * kBlock) {
-    const int64_t p = e / per_pos;
-    const int r = (int)(e - p * per_pos);
-    scatter_one<Acc>(a, dx, p, r / a.F, r % a.F, acc, scale);
+  const int64_t total = a.n * per_pos;
+  const int64_t share = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = (int64_t)blockIdx.x * share, e1 = e0 + share < total ? e0 + share : total;
+  // four elements a round, their loads issued together (the loop is latency-bound otherwise)
+  constexpr int kU = 4;
+  const int64_t npos = (int64_t)a.blocks_w * a.blocks_h;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kU * kCoarseThreads) {
+    float df[kU];
+    int id[kU], lf[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t ee = e + (int64_t)u * kCoarseThreads;
+      const bool ok = ee < e1;
+      const int64_t p = ok ? ee / per_pos : 0;
+      lf[u] = (int)(ee - p * per_pos);
+      df[u] = ok ? dx[p * a.n_levels * a.F + lf[u]] : 0.0f;
+      id[u] = ok ? a.ids[p] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      scatter_tap<Acc>(a, df[u], clamp_id(id[u], npos), lf[u] / a.F, lf[u] % a.F, acc, scale);
   }
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < nv; i += kBlock)
-    if (acc[i] != (Acc)0) atomicAdd(&dgrid[i], acc[i]);
+  Acc* row = part + (int64_t)blockIdx.x * nv;
+  for (int64_t i = threadIdx.x; i < nv; i += kCoarseThreads) row[i] = acc[i];
+}
+
+// dst[i] += sum over the rows of part[rows][nv] in row order: 64 values per block, four row ranges
+// per value summed by four thread groups and combined in order.
+template <typename Acc>
+__global__ void __launch_bounds__(256) k_scatter_reduce(const Acc* __restrict__ part, int rows, int64_t nv,
+                                                        Acc* __restrict__ dst) {
+  __shared__ Acc sums[4][64];
+  const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + col;
+  Acc s = (Acc)0;
+  if (i < nv) {
+    const int r0 = grp * rows / 4, r1 = (grp + 1) * rows / 4;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += part[(int64_t)r * nv + i];
+  }
+  sums[grp][col] = s;
+  __syncthreads();
+  if (grp == 0 && i < nv) {
+    const Acc t = ((sums[0][col] + sums[1][col]) + sums[2][col]) + sums[3][col];
+    if (t != (Acc)0) dst[i] += t;
+  }
 }
 
 // Deterministic mode: the fixed-point scale of a step.  amax = max |dX| over the batch (float bits);
@@ -666,10 +721,11 @@ struct LossArgs {
   int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
   const uint64_t* ref;
   const uint8_t* tex[NTBC_MAX_TEXTURES];
-  float inv_t, w_e, w_c, w_cde, w_cdc;
+  float inv_t, t2, w_e, w_c, w_cde, w_cdc;  // t2 = log2(e) / T
   float inv_ne, inv_nc;  // 1/(n E), 1/(n 16 C)
   float* losses;         // [5]
   int dsigmoid;          // write dL/dZ = dL/dY * Y (1 - Y) (the head's pre-activation) instead of dL/dY
+  int tex_of[2][NTBC_MAX_TEXTURES];  // the BC1 textures, then the BC4 textures, in head order
 };
 
 // The gradient written for a head value y: dL/dY, or dL/dZ through the sigmoid.
@@ -700,12 +756,15 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Straight-through decoded-colour term for one texel: distances dist[0..N) (d_n = -dist_n), the
-// reference palette pr (built from er0, er1 and the mode) and the texel colour c.  Adds (x - c)^2 to *loss for the hard choice x and
-// returns dL/d(d_n) = (1/T) s_n sum_c g_c (pr_n,c - xs_c), g = 2 (x - c) / N_cd, xs = sum_n s_n pr_n.
+// reference palette pr (built from er0, er1 and the mode) and the texel colour c.  Adds (x - c)^2 to
+// *loss for the hard choice x and returns dL/d(d_n) = (1/T) s_n sum_c g_c (pr_n,c - xs_c) with
+// g = 2 (x - c) / N_cd, xs = sum_n s_n pr_n, computed as dd_n = (e_n / (T tot)) (G_n - sum_m e_m G_m / tot)
+// with e_n = exp(-(dist_n - dist_min) / T), tot = sum e_n and G_n = g . pr_n.  t2 = log2(e) / T.
 template <int CH, int N>
 __device__ __forceinline__ void cd_term(const float* dist, const float (*pr)[3], const float* er0, const float* er1,
-                                        bool eight_ref, const float* c, float inv_ncd, float inv_t, float* loss,
-                                        float* dd) {
+                                        bool eight_ref, const float* c, float inv_ncd, float inv_t, float t2,
+                                        float* loss, float* dd) {
+#pragma clang fp contract(fast)
   // hard choice: the first nearest entry k.  Its colour is rebuilt from k with the same operations
   // that built pr (an indexed read of pr would force the palette out of registers).
   int k = 0;
@@ -725,38 +784,33 @@ __device__ __forceinline__ void cd_term(const float* dist, const float (*pr)[3],
     *loss += d * d;
     gx[ch] = 2.0f * d * inv_ncd;
   }
-  float s[N], tot = 0.0f;
+  float e[N], G[N], tot = 0.0f, gsum = 0.0f;
 #pragma unroll
   for (int n = 0; n < N; ++n) {
-    s[n] = __expf(-(dist[n] - dmin) * inv_t);
-    tot += s[n];
+    e[n] = __builtin_amdgcn_exp2f((dmin - dist[n]) * t2);
+    tot += e[n];
+    float g = gx[0] * pr[n][0];
+#pragma unroll
+    for (int ch = 1; ch < CH; ++ch) g += gx[ch] * pr[n][ch];
+    G[n] = g;
+    gsum += e[n] * g;
   }
-  const float inv_tot = fast_rcp(tot);
-  float xs[CH];
+  const float r = fast_rcp(tot);
+  const float gbar = gsum * r, scale = inv_t * r;
 #pragma unroll
-  for (int ch = 0; ch < CH; ++ch) xs[ch] = 0.0f;
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    s[n] *= inv_tot;
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch) xs[ch] += s[n] * pr[n][ch];
-  }
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int ch = 0; ch < CH; ++ch) acc += gx[ch] * (pr[n][ch] - xs[ch]);
-    dd[n] = s[n] * inv_t * acc;
-  }
+  for (int n = 0; n < N; ++n) dd[n] = e[n] * scale * (G[n] - gbar);
 }
 
 // Losses and head gradients of one texture of one position, for the texel row `sub` (texels
 // 4*sub .. 4*sub+3; four lanes share a position/texture).  Returns the partial endpoint gradients in
 // de0/de1; lane sub == 0 also carries the L_e term.  The caller combines the four lanes and writes the
-// endpoint gradients.  Non-finite heads show up as non-finite gradients, which the caller checks.
+// endpoint gradients.  Non-finite heads show up as non-finite gradients, which the caller checks.  A
+// distance ||v|| and its unit vector come from one reciprocal square root (CH = 3), or from |v| and
+// sign(v) (CH = 1: no transcendental).
 template <int CH>
-__device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int sub, float* le, float* lc, float* lcde,
-                             float* lcdc, bool* bad, float de0[3], float de1[3]) {
+__device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t, int id, int sub, float* le, float* lc,
+                                             float* lcde, float* lcdc, bool* bad, float de0[3], float de1[3]) {
+#pragma clang fp contract(fast)
   constexpr bool bc1 = CH == 3;
   constexpr int N = bc1 ? 4 : 8;
   const float* yp = a.y + p * a.ld;
@@ -787,6 +841,12 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
     eh0[ch] = yp[e + ch];
     eh1[ch] = yp[e + CH + ch];
   }
+  // the predicted colours of the lane's four texels, loaded before the palettes are built
+  float chat4[4][CH];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) chat4[x][ch] = yp[a.E + (4 * sub + x) * a.C + a.ch_off[t] + ch];
   const bool eight_hat = bc1 ? true : eh0[0] > eh1[0];
 #pragma unroll
   for (int n = 0; n < N; ++n) {
@@ -838,51 +898,77 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
       const int b = x * CH + ch;  // byte of the row (run-time x: words chosen by selects, no indexing)
       const uint32_t word = CH == 1 ? rw[0] : (b < 4 ? rw[0] : (b < 8 ? rw[CH > 1 ? 1 : 0] : rw[CH > 2 ? 2 : 0]));
       c[ch] = (float)((word >> (8 * (b & 3))) & 255u) * k255;
-      chat[ch] = yp[ci + ch];
+      chat[ch] = x == 0 ? chat4[0][ch] : (x == 1 ? chat4[1][ch] : (x == 2 ? chat4[2][ch] : chat4[3][ch]));
       const float d = chat[ch] - c[ch];
       *lc += d * d;
       dchat[ch] = a.w_c * 2.0f * d * a.inv_nc;
     }
     // endpoint branch: d_n = -||c - c^_n|| over the palette of the predicted endpoints
-    float dist[N], dd[N];
+    float dist[N], unit[N], dd[N];  // unit: 1/dist (CH = 3) or sign(c - c^_n) (CH = 1)
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      float acc = 0.0f;
+      if (CH == 1) {
+        const float v = c[0] - ph[n][0];
+        dist[n] = fabsf(v);
+        unit[n] = v > 0.0f ? 1.0f : (v < 0.0f ? -1.0f : 0.0f);
+      } else {
+        float acc = 0.0f;
 #pragma unroll
-      for (int ch = 0; ch < CH; ++ch) {
-        const float d = c[ch] - ph[n][ch];
-        acc += d * d;
+        for (int ch = 0; ch < CH; ++ch) {
+          const float d = c[ch] - ph[n][ch];
+          acc += d * d;
+        }
+        const float rs = acc > 0.0f ? __builtin_amdgcn_rsqf(acc) : 0.0f;
+        dist[n] = acc * rs;
+        unit[n] = rs;
       }
-      dist[n] = fast_sqrt(acc);
     }
-    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, lcde, dd);
+    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, a.t2, lcde, dd);
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      const float g = dist[n] > 0.0f ? a.w_cde * dd[n] * fast_rcp(dist[n]) : 0.0f;
+      const float q = a.w_cde * dd[n] * unit[n];
+      const float qa = q * ca[n], qb = q * cb[n];
+      if (CH == 1) {
+        de0[0] += qa;
+        de1[0] += qb;
+      } else {
 #pragma unroll
-      for (int ch = 0; ch < CH; ++ch) {
-        const float u = g * (c[ch] - ph[n][ch]);
-        de0[ch] += u * ca[n];
-        de1[ch] += u * cb[n];
+        for (int ch = 0; ch < CH; ++ch) {
+          const float v = c[ch] - ph[n][ch];
+          de0[ch] += qa * v;
+          de1[ch] += qb * v;
+        }
       }
     }
     // colour branch: d_n = -||c^ - c_n|| over the reference palette
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      float acc = 0.0f;
+      if (CH == 1) {
+        const float v = chat[0] - pr[n][0];
+        dist[n] = fabsf(v);
+        unit[n] = v > 0.0f ? 1.0f : (v < 0.0f ? -1.0f : 0.0f);
+      } else {
+        float acc = 0.0f;
 #pragma unroll
-      for (int ch = 0; ch < CH; ++ch) {
-        const float d = chat[ch] - pr[n][ch];
-        acc += d * d;
+        for (int ch = 0; ch < CH; ++ch) {
+          const float d = chat[ch] - pr[n][ch];
+          acc += d * d;
+        }
+        const float rs = acc > 0.0f ? __builtin_amdgcn_rsqf(acc) : 0.0f;
+        dist[n] = acc * rs;
+        unit[n] = rs;
       }
-      dist[n] = fast_sqrt(acc);
     }
-    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, lcdc, dd);
+    cd_term<CH, N>(dist, pr, er0, er1, eight_ref, c, a.inv_nc, a.inv_t, a.t2, lcdc, dd);
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      const float g = dist[n] > 0.0f ? a.w_cdc * dd[n] * fast_rcp(dist[n]) : 0.0f;
+      const float q = a.w_cdc * dd[n] * unit[n];
+      if (CH == 1) {
+        dchat[0] -= q;
+      } else {
 #pragma unroll
-      for (int ch = 0; ch < CH; ++ch) dchat[ch] -= g * (chat[ch] - pr[n][ch]);
+        for (int ch = 0; ch < CH; ++ch) dchat[ch] -= q * (chat[ch] - pr[n][ch]);
+      }
     }
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
@@ -900,11 +986,14 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
 // (same-address atomics from every wave serialise in L2).
 constexpr int kLossBlocks = 1024;  // about two resident rounds of five-wave blocks
 
+// One instance per format (CH = 3: BC1, CH = 1: BC4), so that each carries one path's registers; the
+// block has one wave per texture of that format (wave w works on texture a.tex_of[CH == 3 ? 0 : 1][w]).
+template <int CH>
 __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a) {
   __shared__ float part[NTBC_MAX_TEXTURES][4];
   __shared__ int part_bad[NTBC_MAX_TEXTURES];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t = wave;  // the block has a.n_textures waves
+  const int t = a.tex_of[CH == 3 ? 0 : 1][wave];
   const int64_t groups = (a.n + 15) / 16;
   float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
   bool bad = false;
@@ -915,10 +1004,7 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
     const bool active = p < a.n;
     if (active) {
       const int id = clamp_id(a.ids[p], a.n_positions);
-      if (a.formats[t] == NTBC_BC1)
-        texture_loss<3>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
-      else
-        texture_loss<1>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
+      texture_loss<CH>(a, p, t, id, sub, &le, &lc, &lcde, &lcdc, &bad, de0, de1);
     }
     // combine the endpoint gradients of the four lanes of a position (an aligned group of the wave)
 #pragma unroll
@@ -930,7 +1016,7 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
       }
     }
     if (active && sub == 0) {
-      const int ch_n = a.formats[t] == NTBC_BC1 ? 3 : 1;
+      constexpr int ch_n = CH;
       float* dyp = a.dy + p * a.ld + a.ep_off[t];
       const float* yp = a.y + p * a.ld + a.ep_off[t];
 #pragma unroll
@@ -1316,6 +1402,7 @@ struct FwdArgs {
   const int32_t* ids;
   int64_t n, n_positions;
   int n_levels, base_res, F, blocks_w, blocks_h, in_dim;
+  int shift_x, shift_y;       // pow2_shift of the block grid, -1: the division path
   int64_t level_offset[NTBC_MAX_LEVELS + 1];
   const u32x4* wpack;
   const float* bias;
@@ -1339,7 +1426,8 @@ __device__ __forceinline__ void ffeatures(const FwdArgs& a, int c0, int bx, int 
     if (c0 >= a.in_dim) return;
     const int l = c0 / 8;
     const int res = a.base_res << l;
-    const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+    const dev::Corner cx = a.shift_x >= 0 ? dev::corner_pow2(bx, a.blocks_w, res, a.shift_x) : dev::corner(bx, a.blocks_w, res);
+    const dev::Corner cy = a.shift_y >= 0 ? dev::corner_pow2(by, a.blocks_h, res, a.shift_y) : dev::corner(by, a.blocks_h, res);
     const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
     const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
     const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
@@ -1371,7 +1459,8 @@ __device__ __forceinline__ void ffeatures(const FwdArgs& a, int c0, int bx, int 
     if (c >= a.in_dim) break;
     const int l = c / a.F, f = c % a.F;
     const int res = a.base_res << l;
-    const dev::Corner cx = dev::corner(bx, a.blocks_w, res), cy = dev::corner(by, a.blocks_h, res);
+    const dev::Corner cx = a.shift_x >= 0 ? dev::corner_pow2(bx, a.blocks_w, res, a.shift_x) : dev::corner(bx, a.blocks_w, res);
+    const dev::Corner cy = a.shift_y >= 0 ? dev::corner_pow2(by, a.blocks_h, res, a.shift_y) : dev::corner(by, a.blocks_h, res);
     const int64_t v00 = a.level_offset[l] + (int64_t)cy.i0 * res + cx.i0;
     const int64_t vtx[4] = {v00, v00 + 1, v00 + res, v00 + res + 1};
     const float w[4] = {(1.0f - cx.f) * (1.0f - cy.f), cx.f * (1.0f - cy.f), (1.0f - cx.f) * cy.f, cx.f * cy.f};
@@ -1905,6 +1994,8 @@ FeatArgs feat_args(const Shape& s, const float* grid, const int* stats, const in
   f.F = s.n_features;
   f.blocks_w = s.blocks_w;
   f.blocks_h = s.blocks_h;
+  f.shift_x = pow2_shift(s, s.blocks_w);
+  f.shift_y = pow2_shift(s, s.blocks_h);
   for (int l = 0; l <= s.n_levels; ++l) f.level_offset[l] = s.level_offset[l];
   f.x = x;
   return f;
@@ -1981,6 +2072,15 @@ int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int
 
 // Grid scatter of dX ([n][in_dim]) into d_grid (QAT pass-through mask when qat).  Deterministic mode:
 // 64-bit fixed-point sums at a per-step power-of-two scale (k_det_scale), converted and added at the end.
+// Grid levels whose gradient (vbytes a value) fits in kCoarseLds of LDS.
+int coarse_levels(const Shape& s, size_t vbytes) {
+  int n = 0;
+  while (n < s.n_levels && s.level_offset[n + 1] * s.n_features * (int64_t)vbytes <= kCoarseLds) ++n;
+  return n;
+}
+
+int64_t coarse_offset(const Shape& s, int64_t batch);
+
 int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const float* dx, float* d_grid) {
   const Shape& s = c.s;
   const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
@@ -1998,18 +2098,23 @@ int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const 
                        c.strm, dx, nx, amax);
     hipLaunchKernelGGL(k_det_scale, dim3(1), dim3(1), 0, c.strm, amax, c.n, scale);
   }
-  // coarse levels whose gradient fits in 48 KB of LDS are pre-aggregated per block
-  int n_coarse = 0;
-  while (n_coarse < s.n_levels && s.level_offset[n_coarse + 1] * s.n_features * (int64_t)vbytes <= 48 * 1024) ++n_coarse;
+  // coarse levels whose gradient fits in kCoarseLds of LDS are pre-aggregated per block
+  const int n_coarse = coarse_levels(s, vbytes);
   if (n_coarse > 0) {
-    const size_t lds = (size_t)s.level_offset[n_coarse] * s.n_features * vbytes;
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(c.n * n_coarse * s.n_features, 16 * kBlock), 512));
-    if (c.det)
-      hipLaunchKernelGGL(k_scatter_coarse<unsigned long long>, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dx, acc, n_coarse,
-                         (const float*)scale);
-    else
-      hipLaunchKernelGGL(k_scatter_coarse<float>, dim3(blocks), dim3(kBlock), lds, c.strm, fa, dx, d_grid, n_coarse,
-                         (const float*)nullptr);
+    const int64_t nv = s.level_offset[n_coarse] * s.n_features;
+    const size_t lds = (size_t)nv * vbytes;
+    char* part = reinterpret_cast<char*>(c.ws) + coarse_offset(s, c.n);
+    if (c.det) {
+      hipLaunchKernelGGL(k_scatter_coarse<unsigned long long>, dim3(kCoarseBlocks), dim3(kCoarseThreads), lds, c.strm, fa, dx,
+                         reinterpret_cast<unsigned long long*>(part), n_coarse, (const float*)scale);
+      hipLaunchKernelGGL(k_scatter_reduce<unsigned long long>, dim3((unsigned)ceil_div(nv, 64)), dim3(256), 0, c.strm,
+                         reinterpret_cast<const unsigned long long*>(part), kCoarseBlocks, nv, acc);
+    } else {
+      hipLaunchKernelGGL(k_scatter_coarse<float>, dim3(kCoarseBlocks), dim3(kCoarseThreads), lds, c.strm, fa, dx,
+                         reinterpret_cast<float*>(part), n_coarse, (const float*)nullptr);
+      hipLaunchKernelGGL(k_scatter_reduce<float>, dim3((unsigned)ceil_div(nv, 64)), dim3(256), 0, c.strm,
+                         reinterpret_cast<const float*>(part), kCoarseBlocks, nv, d_grid);
+    }
   }
   if (n_coarse < s.n_levels) {
     const dim3 grid_dim((unsigned)ceil_div(c.n * (s.n_levels - n_coarse) * s.n_features, kBlock));
@@ -2120,6 +2225,7 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   }
   a.ref = t->ref_blocks;
   a.inv_t = 1.0f / temperature;
+  a.t2 = (float)(1.4426950408889634 / (double)temperature);
   a.w_e = lw ? lw[0] : 1.0f;
   a.w_c = lw ? lw[1] : 1.0f;
   a.w_cde = lw ? lw[2] : 1.0f;
@@ -2127,8 +2233,14 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
   a.inv_ne = (float)(1.0 / ((double)n * s.endpoint_dim));
   a.inv_nc = (float)(1.0 / ((double)n * 16.0 * s.channels));
   a.losses = losses;
-  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks))),
-                     dim3(64 * s.n_textures), 0, strm, a);
+  int nf[2] = {0, 0};
+  for (int i = 0; i < s.n_textures; ++i) {
+    const int k = s.formats[i] == NTBC_BC1 ? 0 : 1;
+    a.tex_of[k][nf[k]++] = i;
+  }
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks)));
+  if (nf[0] > 0) hipLaunchKernelGGL(k_loss_grad<3>, grid, dim3(64 * nf[0]), 0, strm, a);
+  if (nf[1] > 0) hipLaunchKernelGGL(k_loss_grad<1>, grid, dim3(64 * nf[1]), 0, strm, a);
   return check_launch("k_loss_grad");
 }
 
@@ -2323,6 +2435,8 @@ int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* we
   a.F = s.n_features;
   a.blocks_w = s.blocks_w;
   a.blocks_h = s.blocks_h;
+  a.shift_x = pow2_shift(s, s.blocks_w);
+  a.shift_y = pow2_shift(s, s.blocks_h);
   a.in_dim = s.in_dim;
   for (int i = 0; i <= s.n_levels; ++i) a.level_offset[i] = s.level_offset[i];
   a.wpack = pk.pack;
@@ -2431,12 +2545,19 @@ int64_t det_offset(const Shape& s, int64_t batch) {
   return (bytes + 255) / 256 * 256;
 }
 
+// Byte offset of the coarse scatter's per-block sums (after the deterministic scatter's region); one row
+// of at most kCoarseLds bytes per block.
+int64_t coarse_offset(const Shape& s, int64_t batch) {
+  return det_offset(s, batch) + 256 + (s.grid_vertices * s.n_features * 8 + 255) / 256 * 256;
+}
+
 }  // namespace
 
 namespace ntbc {
-// The unfused and fused layouts share the workspace; the deterministic scatter's 64-bit sums follow.
+// The unfused and fused layouts share the workspace; the deterministic scatter's 64-bit sums and the
+// coarse scatter's per-block sums follow.
 int64_t train_workspace_bytes(const Shape& s, int64_t batch) {
-  return det_offset(s, batch) + 256 + s.grid_vertices * s.n_features * 8;
+  return coarse_offset(s, batch) + (int64_t)kCoarseBlocks * kCoarseLds;
 }
 }  // namespace ntbc
 
