@@ -90,6 +90,59 @@ def cpu_baseline(cfg, layers, grid_codes, scale, zero, budget_s):
     return info, ids, ON.infer_blocks(cfg, levels, layers, ids)[0]
 
 
+def cpu_legs(cfg, layers, grid_codes, scale, zero, mat, n_sample):
+    """The other oracle timings, each bounded to a few seconds: the inference sample again on one core,
+    oracle training (100 steps of the 256^2 two-texture config at batch 512; one step of the 1024^2
+    five-texture config at batch 16,384) and the reference encoder (both small materials in full, one
+    texture of the 4096^2 material on a 65,536-block sample)."""
+    import dataclasses
+    from oracle import bc as OB
+    from oracle import ntbc as ON
+    from paper_2407_09543_amd import synth
+    from threadpoolctl import threadpool_limits
+    out = {}
+    levels = ON.grid_levels(cfg, codes=grid_codes, scales=scale, zeros=zero)
+    n1 = min(65536, max(4096, n_sample // 4))
+    ids = np.random.default_rng(1).choice(cfg.n_positions, n1, replace=False)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ON.infer_blocks(cfg, levels, layers, ids)
+        dt = time.perf_counter() - t0
+    out["inference_one_core"] = {"value": n1 * len(cfg.formats) / dt, "unit": "blocks/s", "cores": 1,
+                                 "sample": f"{n1} random block positions of the 4096^2 material, {dt:.1f} s"}
+
+    def encode_ref(blocks, fmt):
+        return OB.bc1_encode_ref(blocks) if fmt == 1 else OB.bc4_encode_ref(blocks[..., 0])
+
+    def training(c, m, seed, steps, batch, total):
+        blocks = [OB.image_to_blocks(t.texels) for t in m.textures]
+        t0 = time.perf_counter()
+        ref = [encode_ref(b, t.fmt) for b, t in zip(blocks, m.textures)]
+        t_enc = time.perf_counter() - t0
+        tg = ON.Targets(c.formats, ref, blocks)
+        st = ON.TrainState(synth.init_grid(c, seed), synth.init_weights(c, seed))
+        t0 = time.perf_counter()
+        for s in range(steps):
+            ON.train_step(c, st, tg, synth.batch_ids(seed, s, batch, c.n_positions), s, total, False)
+        return (time.perf_counter() - t0) / steps, t_enc, sum(len(b) for b in blocks)
+
+    c1 = synth.config_small(256)
+    ms1, enc1, nb1 = training(c1, synth.material_small(256, 1), 1, 100, 512, 100)
+    c2 = dataclasses.replace(synth.config_mid(1024), grid_u8=False)
+    ms2, enc2, nb2 = training(c2, synth.material_five(1024, 2), 2, 1, 16384, 2200)
+    out["training"] = {"ms_per_step_256_two_texture_batch_512": ms1 * 1e3,
+                       "ms_per_step_1024_five_texture_batch_16384": ms2 * 1e3, "unit": "ms/step (FP64 oracle)"}
+    tex = mat.textures[0]
+    sample = OB.image_to_blocks(tex.texels)[np.random.default_rng(2).choice(cfg.n_positions, 65536, replace=False)]
+    t0 = time.perf_counter()
+    encode_ref(sample, tex.fmt)
+    enc3 = time.perf_counter() - t0
+    out["ref_encoder"] = {"blocks_per_s_256_material": nb1 / enc1, "blocks_per_s_1024_material": nb2 / enc2,
+                          "blocks_per_s_4096_bc1_sample": 65536 / enc3,
+                          "note": "the 4096^2 figure is from 65,536 blocks of the diffuse texture"}
+    return out
+
+
 def versus_oracle(cfg, mat, outs, ids, words_or, names):
     """Block identity and decoded-PSNR delta of every precision's blocks against the FP64 oracle's, on
     the oracle's sample of block positions (all of them when the sample covers the material): PSNR of
@@ -466,6 +519,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"], ids_or, words_or = cpu_baseline(cfg, layers, codes, scale, zero, args.cpu_seconds)
+        log("oracle legs: one core, training, reference encoder")
+        result["cpu_baseline"]["legs"] = cpu_legs(cfg, layers, codes, scale, zero, mat, len(ids_or))
         log("identity and decoded-PSNR delta of every precision against the FP64 oracle")
         result["vs_fp64_oracle"] = versus_oracle(
             cfg, mat, outs, ids_or, words_or,
