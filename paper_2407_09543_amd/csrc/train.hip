@@ -1260,6 +1260,7 @@ __global__ void k_export_qparams(const int* __restrict__ stats, int n_levels, fl
 // W_k^T as the A operand, so the masks of the forward apply to the backward accumulators lane by lane.
 constexpr int kFW = 4;            // waves per workgroup: 128 positions
 constexpr int kFPos = 32 * kFW;
+constexpr int kFThreads = 64 * kFW;
 constexpr int kFChunkTiles = 2;   // output tiles per weight chunk
 constexpr int kFMaxChunks = 48;
 constexpr int kFMaxLayers = 5;
@@ -1295,11 +1296,11 @@ __device__ __forceinline__ void fchunk_dma(const u32x4* __restrict__ wp, const F
   const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
   const int len = ct.len[c];
   const u32x4* src = wp + ct.src[c];
-  for (int r = 0; r * kFPos < len; ++r) {
-    const int e = tid + kFPos * r;
+  for (int r = 0; r * kFThreads < len; ++r) {
+    const int e = tid + kFThreads * r;
     if (e < len)
-      __builtin_amdgcn_global_load_lds(src + e, (__attribute__((address_space(3))) void*)(dst + wave_base + kFPos * r), 16,
-                                       0, 0);
+      __builtin_amdgcn_global_load_lds(src + e, (__attribute__((address_space(3))) void*)(dst + wave_base + kFThreads * r),
+                                       16, 0, 0);
   }
 }
 
@@ -1817,7 +1818,12 @@ constexpr int kDwLd = kDwK / 16;  // 16-byte loads per thread and operand
 __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
   __shared__ __align__(16) uint16_t As[2][128][kDwRow];
   __shared__ __align__(16) uint16_t Bs[2][128][kDwRow];
-  const int tile = blockIdx.x % a.n_tiles, split = blockIdx.x / a.n_tiles;
+  // Workgroups are dispatched round-robin over the eight XCDs; give each XCD a contiguous run of
+  // (split, tile) pairs, tiles fastest, so the tiles that read the same K range of the same A (or B)
+  // rows run at the same time on one XCD and the second read hits its L2.
+  const int nwg = (int)gridDim.x, per = nwg / 8, extra = nwg % 8, x = (int)blockIdx.x % 8, kx = (int)blockIdx.x / 8;
+  const int flat = x * per + (x < extra ? x : extra) + kx;
+  const int tile = flat % a.n_tiles, split = flat / a.n_tiles;
   int jb = 0;
   while (jb + 1 < a.n_jobs && tile >= a.job[jb + 1].tile0) ++jb;
   const DwJob& J = a.job[jb];
@@ -1919,6 +1925,8 @@ __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
   const int m = tm * 128 + r, nn = tn * 128 + col;
   if (m < J.M && nn < J.N) {
     float s = 0.0f;
+    // unrolled so that eight loads are in flight; the additions stay in split order
+#pragma unroll 8
     for (int k = 0; k < a.splits; ++k) s += part[(int64_t)k * (128 * 128) + e];
     J.c[(int64_t)m * J.N + nn] += s;
   }
@@ -1926,6 +1934,7 @@ __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
     const int mr = tm * 128 + threadIdx.x;
     if (mr < J.M) {
       float s = 0.0f;
+#pragma unroll 8
       for (int k = 0; k < a.splits; ++k) s += a.dbpart[((int64_t)tile * a.splits + k) * 128 + threadIdx.x];
       J.db[mr] += s;
     }
