@@ -289,6 +289,62 @@ def _plain(x):
     raise TypeError(f"not JSON serializable: {type(x).__name__}")
 
 
+def paper_layout(args):
+    """The paper's own network layout (endpoint network + per-texel colour network, SELU, half precision)
+    on the workload of its inference table: a 4096^2 material of two BC1 and four BC4 textures, and one
+    of two BC1 textures only, each with the aggressive (one model) and the conservative (a BC1 model
+    and a BC4 model) layout; random parameters of the paper's shapes (the cost does not depend on the
+    values).  Times one full material per call (weight packing included)."""
+    import torch
+    from paper_2407_09543_amd import ntbc
+    rng = np.random.default_rng(11)
+    dev = torch.device("cuda:0")
+    bw = bh = args.size // 4
+
+    def model(formats):
+        e = sum(6 if f == 1 else 2 for f in formats)
+        c = sum(3 if f == 1 else 1 for f in formats)
+
+        def net(n_in, n_out):
+            dims = [n_in, 64, 64, 64, n_out]
+            return np.concatenate([np.concatenate([(rng.standard_normal((dims[k + 1], dims[k])) * np.sqrt(2.0 / dims[k])).ravel(),
+                                                   0.2 * rng.standard_normal(dims[k + 1])]) for k in range(4)]).astype(np.float32)
+
+        def grid(levels):
+            nv = sum((16 << l) ** 2 for l in range(levels))
+            return (torch.from_numpy(rng.integers(0, 256, (nv, 2), dtype=np.uint8)).to(dev),
+                    torch.full((levels,), 0.006, dtype=torch.float32, device=dev),
+                    torch.full((levels,), 128, dtype=torch.int32, device=dev))
+
+        eg, es, ez = grid(7)
+        cg, cs, cz = grid(8)
+        return ntbc.FaithfulModel(formats, bw, bh, eg, cg, torch.from_numpy(net(14, e)).to(dev),
+                                  torch.from_numpy(net(16, c)).to(dev), ep_scale=es, ep_zero=ez, col_scale=cs,
+                                  col_zero=cz)
+
+    def flop(formats):
+        e = sum(6 if f == 1 else 2 for f in formats)
+        c = sum(3 if f == 1 else 1 for f in formats)
+        return 2 * ((14 * 64 + 2 * 64 * 64 + 64 * e) + 16 * (16 * 64 + 2 * 64 * 64 + 64 * c)) * bw * bh
+
+    out = {"texture_size": args.size, "blocks_per_texture": bw * bh,
+           "paper_ms_rx7900xt_half": {"bc1_bc4_conservative": 49.84, "bc1_only_conservative": 25.57,
+                                      "bc1_bc4_aggressive": 27.31, "bc1_only_aggressive": 25.96,
+                                      "note": "Tab. inferPerf: another GPU; context only"}}
+    for name, formats in (("bc1_bc4", [1, 1, 4, 4, 4, 4]), ("bc1_only", [1, 1])):
+        for layout in ("aggressive", "conservative"):
+            groups = [formats] if layout == "aggressive" else [g for g in ([f for f in formats if f == 1],
+                                                                          [f for f in formats if f == 4]) if g]
+            models = [model(g) for g in groups]
+            outs = [torch.empty((len(g), bw * bh), dtype=torch.int64, device=dev) for g in groups]
+            ms = time_call(lambda: [m.infer(out=o) for m, o in zip(models, outs)], args.steps, args.warmup, torch)
+            fl = sum(flop(g) for g in groups)
+            out[f"{name}_{layout}"] = {"ms": ms, "blocks_per_s": len(formats) * bw * bh / (ms * 1e-3),
+                                       "models": len(groups), "tflops": fl / (ms * 1e-3) / 1e12,
+                                       "frac_fp16_peak": fl / (ms * 1e-3) / PEAK_BF16_TFLOPS / 1e12}
+    return out
+
+
 def naive_ablation(args, cfg, tex, ntbc_psnr):
     """The naive approach (Sec. 3.1: weight head, two-stage 80/20 training) encoded with the same
     steps, batch, seed and training precision as NTBC, its blocks inferred in BF16: PSNR per texture
@@ -513,6 +569,8 @@ def main():
         "encode": encode_info,
         "model_note": model_note,
     }
+    log("the paper's own network layout on its inference-table workload")
+    result["paper_layout"] = paper_layout(args)
     if not args.no_batched:
         log("batched load-time decode of 16 materials with mip chains")
         result["batched_decode"] = batched_decode(torch, ntbc, synth)

@@ -248,6 +248,53 @@ int ntbc_batch_set_waves(void* table, int32_t group, int32_t waves);
 int ntbc_infer_batch(const void* table, const void* table_device, void* workspace, size_t workspace_bytes,
                      uint64_t* stamps, void* stream);
 
+/* ---- the paper's own network layout -------------------------------------------------------------- */
+
+/* One model of the paper's layout (Sec. 3.4; Sec. 4.1 for the material layouts): an endpoint network on
+ * the block's cell of a multi-resolution grid and a colour network on each texel's cell of a second
+ * grid, both with 2 features per level, three hidden layers of 64 SELU units (lambda =
+ * 1.0507009873554805, alpha = 1.6732632423543772) and sigmoid outputs, evaluated with IEEE-half
+ * operands and FP32 accumulation.  A block's endpoints come from one endpoint-network run and its 16
+ * texels' predicted colours from 16 colour-network runs; the heads are assembled in the NTBC layout
+ * and packed as ntbc_infer_blocks packs them (Eq. dist).  The aggressive layout is one model over
+ * every texture; the conservative layout is two models (the BC1 textures, the BC4 textures), i.e. two
+ * calls.  Host struct, sizes only. */
+typedef struct {
+  int32_t ep_levels, ep_base_res;     /* endpoint grid: levels 1..8, coarsest resolution (paper: 7, 16) */
+  int32_t col_levels, col_base_res;   /* colour grid over texel cells (paper: 8, 16)                    */
+  int32_t grid_dtype;                 /* NTBC_GRID_F32 or NTBC_GRID_U8 (both grids)                     */
+  int32_t n_textures;
+  int32_t formats[NTBC_MAX_TEXTURES]; /* endpoint outputs 6*nBC1 + 2*nBC4 <= 64, colour outputs
+                                         3*nBC1 + nBC4 <= 32, per texture in order                      */
+  int32_t blocks_w, blocks_h;         /* block grid; the colour grid's cells are the 4*blocks texels   */
+} ntbc_faithful_desc;
+
+/* Parameters (host struct of device pointers).  Grids level-major, vertex j*res + i, 2 features;
+ * U8 grids with per-level scale and zero point.  Weights in the canonical FP32 layout of each network:
+ * W1,b1,W2,b2,W3,b3,W4,b4 with W row-major [out][in]; in = 2*levels, hidden 64, out as above. */
+typedef struct {
+  const void* ep_grid;
+  const float* ep_scale;
+  const int32_t* ep_zero;
+  const void* col_grid;
+  const float* col_scale;
+  const int32_t* col_zero;
+  const float* ep_weights;
+  const float* col_weights;
+} ntbc_faithful_params;
+
+/* FP32 weights of each network and the workspace bytes of ntbc_faithful_infer.  Host only. */
+int ntbc_faithful_sizes(const ntbc_faithful_desc* d, int64_t* ep_weights, int64_t* col_weights,
+                        size_t* workspace_bytes);
+
+/* Blocks [first_block, first_block + n_blocks) of every texture of the model: blocks_out
+ * uint64[n_textures][n_blocks]; heads_out (optional, NULL to skip) float[n_blocks][E + 16*C] in the
+ * NTBC head layout.  Packs the weights into the workspace on every call.  Errors: NTBC_EINVAL,
+ * NTBC_ENOWORKSPACE. */
+int ntbc_faithful_infer(const ntbc_faithful_desc* d, const ntbc_faithful_params* p, int64_t first_block,
+                        int64_t n_blocks, uint64_t* blocks_out, float* heads_out, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
 /* ---- training ----------------------------------------------------------------------------------- */
 
 /* Training state (host struct of device pointers, caller-owned).  Master parameters in FP32; Adam

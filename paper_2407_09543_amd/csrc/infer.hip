@@ -31,8 +31,8 @@
 // The build compiles this file once per part so that the many kernel instances compile in parallel:
 // NTBC_INFER_PART = 0 holds the host code, the FP32 kernels and the weight packing, 1-3 the
 // single-range 16-bit/FP8 instances (BF16, FP16, FP8), 4-6 the batched ones (BF16 with 4-wave tiles,
-// FP16, FP8), 7-8 the BF16 batched ones with 2- and 8-wave tiles.  Without the macro one translation
-// unit holds everything.
+// FP16, FP8), 7-8 the BF16 batched ones with 2- and 8-wave tiles, 9 the paper-layout model.  Without
+// the macro one translation unit holds everything.
 #ifndef NTBC_INFER_PART
 #define NTBC_INFER_PART -1
 #endif
@@ -2051,3 +2051,352 @@ extern "C" int ntbc_infer_batch(const void* table, const void* table_device, voi
   return NTBC_OK;
 }
 #endif  // NTBC_PART(0)
+
+// ------------------------------------------------------------------------------ the paper's own layout
+// One model of the paper's network layout (Sec. 3.4): an endpoint network on the block's grid cell and
+// a colour network on each of its 16 texels' cells, each 2 features per grid level (at most 16
+// inputs: one K-step), three hidden layers of 64 SELU units and sigmoid outputs, with half-precision
+// operands and float32 accumulation.  A wave owns 32 blocks: one endpoint-network run and 16
+// colour-network runs (texel i of the 32 blocks at a time), all with the layers chained in registers
+// as in the kernels above; the sigmoid outputs go to LDS in the NTBC head layout and the LDS-staged BC
+// epilogue packs them (Eq. dist), exactly as for the one-trunk model.
+#if NTBC_PART(9)
+namespace {
+
+constexpr int kFaWaves = 2;                    // waves (of 32 blocks) per workgroup
+constexpr int kFaHidden = 64;
+constexpr int kFaLayers = 4;                   // three hidden layers and the head
+constexpr float kSeluLambda = 1.0507009873554805f;
+constexpr float kSeluLambdaAlpha = 1.0507009873554805f * 1.6732632423543772f;
+
+struct FaNet {
+  int64_t pack_off[kFaLayers];  // u32x4 units in the packed weights
+  int bias_off[kFaLayers];      // floats in the padded biases
+  int ksteps[kFaLayers];        // 1, 4, 4, 4
+  int head_tiles;               // 32-row tiles of the outputs
+  int n_out;
+};
+
+struct FaithArgs {
+  InferArgs pk;                 // texture layout, block range, outputs, head stride (for pack_blocks)
+  dev::GridView eg, cg;         // endpoint grid (cells = blocks), colour grid (cells = texels)
+  const u32x4* wpack;
+  const float* bias;
+  FaNet ep, col;
+};
+
+__device__ __forceinline__ float selu(float z) {
+  return z > 0.0f ? kSeluLambda * z : kSeluLambdaAlpha * (__expf(z) - 1.0f);
+}
+
+// SELU of a hidden tile's accumulators (started from the biases) -> the next layer's two B operands.
+__device__ __forceinline__ void selu_epilogue(const f32x16_t& acc, u32x4* lo, u32x4* hi) {
+  float r[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) r[v] = selu(acc[v]);
+  *lo = x8_of<Lp::FP16>(r);
+  *hi = x8_of<Lp::FP16>(r + 8);
+}
+
+// One network run on the 32 positions of the wave (layer-0 operand x0): the first n.n_out sigmoid
+// outputs of position j go to y[j * hs + col0 + k].
+__device__ __forceinline__ void fa_net(const FaithArgs& a, const FaNet& n, const u32x4& x0, float* y, int hs, int col0,
+                                       int lane) {
+  const int j = lane & 31, g = lane >> 5;
+  // the weights and biases are re-read from the cache on every run (opaque base pointers keep the
+  // compiler from hoisting all of them into registers across the 17 runs, which would leave one wave
+  // per SIMD)
+  const u32x4* wp = a.wpack;
+  const float* bias = a.bias;
+  asm volatile("" : "+s"(wp), "+s"(bias));
+  u32x4 h[4], o[4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    f32x16_t acc = acc_init<Lp::FP16>(bias + n.bias_off[0] + 32 * t, g);
+    acc = mfma16<Lp::FP16>(wp[n.pack_off[0] + (int64_t)t * 64 + lane], x0, acc);
+    selu_epilogue(acc, &h[2 * t], &h[2 * t + 1]);
+  }
+#pragma unroll
+  for (int l = 1; l < kFaLayers - 1; ++l) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      f32x16_t acc = acc_init<Lp::FP16>(bias + n.bias_off[l] + 32 * t, g);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma16<Lp::FP16>(wp[n.pack_off[l] + ((int64_t)t * 4 + s) * 64 + lane], h[s], acc);
+      selu_epilogue(acc, &o[2 * t], &o[2 * t + 1]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) h[s] = o[s];
+  }
+  for (int t = 0; t < n.head_tiles; ++t) {
+    f32x16_t acc = acc_init<Lp::FP16>(bias + n.bias_off[kFaLayers - 1] + 32 * t, g);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc = mfma16<Lp::FP16>(wp[n.pack_off[kFaLayers - 1] + ((int64_t)t * 4 + s) * 64 + lane], h[s], acc);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int neuron = 32 * t + 8 * (v / 4) + 4 * g + (v % 4);
+      if (neuron < n.n_out) y[j * hs + col0 + neuron] = sigmoid(acc[v]);
+    }
+  }
+}
+
+// Colour-grid gather of a texel split in two so that the loads of the next texel are in flight while
+// the current texel's network runs: the corner loads (uint8 grid, 2 features a vertex: one 16-bit load
+// per corner) and bilinear weights of the lane's four levels (features 8g .. 8g+7), then the blend.
+struct FaTaps {
+  uint32_t raw[4][4];
+  float w[4][4];
+};
+
+__device__ __forceinline__ void fa_load_u8(const dev::GridView& g, int gi, int tx, int ty, FaTaps& t) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int level = 4 * gi + h;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      t.raw[h][c] = 0;
+      t.w[h][c] = 0.0f;
+    }
+    if (level < g.n_levels) {
+      const int res = g.base_res << level;
+      const dev::Corner cx = g.shift_x >= 0 ? dev::corner_pow2(tx, g.blocks_w, res, g.shift_x) : dev::corner(tx, g.blocks_w, res);
+      const dev::Corner cy = g.shift_y >= 0 ? dev::corner_pow2(ty, g.blocks_h, res, g.shift_y) : dev::corner(ty, g.blocks_h, res);
+      const int64_t v00 = g.level_offset[level] + (int64_t)cy.i0 * res + cx.i0;
+      const uint16_t* p = reinterpret_cast<const uint16_t*>(g.u8);
+      t.raw[h][0] = p[v00];
+      t.raw[h][1] = p[v00 + 1];
+      t.raw[h][2] = p[v00 + res];
+      t.raw[h][3] = p[v00 + res + 1];
+      t.w[h][0] = (1.0f - cx.f) * (1.0f - cy.f);
+      t.w[h][1] = cx.f * (1.0f - cy.f);
+      t.w[h][2] = (1.0f - cx.f) * cy.f;
+      t.w[h][3] = cx.f * cy.f;
+    }
+  }
+}
+
+__device__ __forceinline__ void fa_blend_u8(const dev::GridView& g, int gi, const FaTaps& t, float v[8]) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int level = 4 * gi + h;
+    const bool on = level < g.n_levels;
+    const float s = on ? g.scale[level] : 0.0f;
+    const float sz = on ? -s * (float)g.zero[level] : 0.0f;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      float q[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = (float)((t.raw[h][c] >> (8 * f)) & 255u);
+      v[2 * h + f] = on ? fmaf(s, fmaf(t.w[h][0], q[0], fmaf(t.w[h][1], q[1], fmaf(t.w[h][2], q[2], t.w[h][3] * q[3]))), sz)
+                        : 0.0f;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64 * kFaWaves) k_faithful(FaithArgs a) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 31, g = lane >> 5;
+  const int64_t pos0 = a.pk.first + ((int64_t)blockIdx.x * kFaWaves + wave) * 32;
+  const int64_t last = a.pk.first + a.pk.n - 1;
+  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  const int bx = (int)(id % a.eg.blocks_w), by = (int)(id / a.eg.blocks_w);
+  const int hs = a.pk.head_stride;
+  float* y = lds + wave * 32 * hs;
+  float v[8];
+  dev::features<8>(a.eg, 8 * g, bx, by, v);
+  fa_net(a, a.ep, x8_of<Lp::FP16>(v), y, hs, 0, lane);
+  if (a.cg.u8) {
+    // texel i + 1's corner loads are issued before texel i's network runs
+    FaTaps taps;
+    fa_load_u8(a.cg, g, 4 * bx, 4 * by, taps);
+#pragma unroll 1
+    for (int i = 0; i < 16; ++i) {
+      fa_blend_u8(a.cg, g, taps, v);
+      const u32x4 x = x8_of<Lp::FP16>(v);
+      if (i < 15) fa_load_u8(a.cg, g, 4 * bx + ((i + 1) & 3), 4 * by + ((i + 1) >> 2), taps);
+      fa_net(a, a.col, x, y, hs, a.pk.endpoint_dim + i * a.pk.channels, lane);
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < 16; ++i) {
+      dev::features<8>(a.cg, 8 * g, 4 * bx + (i & 3), 4 * by + (i >> 2), v);
+      fa_net(a, a.col, x8_of<Lp::FP16>(v), y, hs, a.pk.endpoint_dim + i * a.pk.channels, lane);
+    }
+  }
+  __syncthreads();
+  // inlined here: an out-of-line call would take the kernel argument by address, i.e. copy it to scratch
+  [[clang::always_inline]] pack_blocks<32>(a.pk, y, lane, pos0);
+}
+
+// Shape of one model of the paper's layout.
+struct FaShape {
+  int E, C, in_ep, in_col, ep_tiles;
+  int64_t n_ep, n_col;                  // canonical FP32 weights of each network
+  int64_t pack_units, bias_floats;      // packed operands (u32x4) and padded biases of both networks
+  FaNet ep, col;
+  PackArgs pa_ep, pa_col;
+};
+
+int64_t fa_net_weights(int in, int out) {
+  return (int64_t)in * kFaHidden + kFaHidden + 2 * ((int64_t)kFaHidden * kFaHidden + kFaHidden) + (int64_t)kFaHidden * out + out;
+}
+
+void fa_plan_net(int in, int out, int64_t* units, int64_t* bias, FaNet* n, PackArgs* pa) {
+  const int dims[kFaLayers + 1] = {in, kFaHidden, kFaHidden, kFaHidden, out};
+  *pa = PackArgs{};
+  pa->n_layers = kFaLayers;
+  int64_t w = 0;
+  n->n_out = out;
+  n->head_tiles = (out + 31) / 32;
+  for (int k = 0; k < kFaLayers; ++k) {
+    pa->in_dim[k] = dims[k];
+    pa->out_dim[k] = dims[k + 1];
+    pa->w_off[k] = w;
+    w += (int64_t)dims[k] * dims[k + 1];
+    pa->b_off[k] = w;
+    w += dims[k + 1];
+    n->ksteps[k] = k == 0 ? 1 : 4;
+    pa->ksteps[k] = n->ksteps[k];
+    pa->otiles[k] = k == kFaLayers - 1 ? n->head_tiles : 2;
+    pa->pack_off[k] = *units;
+    n->pack_off[k] = *units;
+    *units += (int64_t)pa->otiles[k] * pa->ksteps[k] * 64;
+    pa->bias_off[k] = *bias;
+    n->bias_off[k] = (int)*bias;
+    *bias += 32 * pa->otiles[k];
+  }
+}
+
+int fa_shape(const ntbc_faithful_desc* d, FaShape* s) {
+  NTBC_REQUIRE(d != nullptr, "desc is NULL");
+  NTBC_REQUIRE(d->ep_levels >= 1 && d->ep_levels <= 8 && d->col_levels >= 1 && d->col_levels <= 8,
+               "grid levels (%d, %d) must be 1..8 (2 features each: at most 16 inputs)", d->ep_levels, d->col_levels);
+  NTBC_REQUIRE(d->ep_base_res >= 2 && d->col_base_res >= 2, "base resolutions must be >= 2");
+  NTBC_REQUIRE(((int64_t)d->ep_base_res << (d->ep_levels - 1)) <= 32768 &&
+                   ((int64_t)d->col_base_res << (d->col_levels - 1)) <= 32768,
+               "finest grid level too large");
+  NTBC_REQUIRE(d->grid_dtype == NTBC_GRID_F32 || d->grid_dtype == NTBC_GRID_U8, "bad grid_dtype %d", d->grid_dtype);
+  NTBC_REQUIRE(d->n_textures >= 1 && d->n_textures <= NTBC_MAX_TEXTURES, "n_textures %d out of range", d->n_textures);
+  NTBC_REQUIRE(d->blocks_w >= 1 && d->blocks_h >= 1 && (int64_t)d->blocks_w * 4 <= 65536 && (int64_t)d->blocks_h * 4 <= 65536,
+               "block grid %dx%d out of range", d->blocks_w, d->blocks_h);
+  *s = FaShape{};
+  for (int t = 0; t < d->n_textures; ++t) {
+    NTBC_REQUIRE(d->formats[t] == NTBC_BC1 || d->formats[t] == NTBC_BC4, "formats[%d] = %d", t, d->formats[t]);
+    s->E += d->formats[t] == NTBC_BC1 ? 6 : 2;
+    s->C += d->formats[t] == NTBC_BC1 ? 3 : 1;
+  }
+  NTBC_REQUIRE(s->E <= 64 && s->C <= 32, "endpoint outputs %d > 64 or colour outputs %d > 32", s->E, s->C);
+  s->in_ep = 2 * d->ep_levels;
+  s->in_col = 2 * d->col_levels;
+  s->n_ep = fa_net_weights(s->in_ep, s->E);
+  s->n_col = fa_net_weights(s->in_col, s->C);
+  fa_plan_net(s->in_ep, s->E, &s->pack_units, &s->bias_floats, &s->ep, &s->pa_ep);
+  fa_plan_net(s->in_col, s->C, &s->pack_units, &s->bias_floats, &s->col, &s->pa_col);
+  s->ep_tiles = s->ep.head_tiles;
+  return NTBC_OK;
+}
+
+size_t fa_workspace(const FaShape& s) { return (size_t)s.pack_units * 16 + 256 + (size_t)s.bias_floats * 4; }
+
+dev::GridView fa_grid(int levels, int base, int blocks_w, int blocks_h, int u8, const void* grid, const float* scale,
+                      const int32_t* zero) {
+  Shape sh{};
+  sh.n_levels = levels;
+  sh.base_res = base;
+  dev::GridView g{};
+  g.u8 = u8 ? static_cast<const uint8_t*>(grid) : nullptr;
+  g.f32 = u8 ? nullptr : static_cast<const float*>(grid);
+  g.scale = scale;
+  g.zero = zero;
+  g.n_levels = levels;
+  g.base_res = base;
+  g.n_features = 2;
+  g.blocks_w = blocks_w;
+  g.blocks_h = blocks_h;
+  int64_t off = 0;
+  for (int l = 0; l < levels; ++l) {
+    g.level_offset[l] = off;
+    off += ((int64_t)base << l) * ((int64_t)base << l);
+  }
+  g.level_offset[levels] = off;
+  g.shift_x = pow2_shift(sh, blocks_w);
+  g.shift_y = pow2_shift(sh, blocks_h);
+  g.fast8 = 0;
+  return g;
+}
+
+}  // namespace
+
+extern "C" int ntbc_faithful_sizes(const ntbc_faithful_desc* d, int64_t* ep_weights, int64_t* col_weights,
+                                   size_t* workspace_bytes) {
+  FaShape s;
+  int st = fa_shape(d, &s);
+  if (st != NTBC_OK) return st;
+  if (ep_weights) *ep_weights = s.n_ep;
+  if (col_weights) *col_weights = s.n_col;
+  if (workspace_bytes) *workspace_bytes = fa_workspace(s);
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_faithful_infer(const ntbc_faithful_desc* d, const ntbc_faithful_params* p, int64_t first_block,
+                                   int64_t n_blocks, uint64_t* blocks_out, float* heads_out, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  FaShape s;
+  int st = fa_shape(d, &s);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(p != nullptr && p->ep_grid && p->col_grid && p->ep_weights && p->col_weights, "params: a NULL pointer");
+  NTBC_REQUIRE(d->grid_dtype != NTBC_GRID_U8 || (p->ep_scale && p->ep_zero && p->col_scale && p->col_zero),
+               "params: U8 grids need their scales and zero points");
+  const int64_t npos = (int64_t)d->blocks_w * d->blocks_h;
+  NTBC_REQUIRE(first_block >= 0 && n_blocks >= 0 && first_block + n_blocks <= npos, "block range out of the grid");
+  if (n_blocks == 0) return NTBC_OK;
+  NTBC_REQUIRE(blocks_out != nullptr, "blocks_out is NULL");
+  if (workspace == nullptr || workspace_bytes < fa_workspace(s))
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %zu bytes", fa_workspace(s));
+  hipStream_t strm = as_stream(stream);
+  u32x4* pack = static_cast<u32x4*>(workspace);
+  float* bias = reinterpret_cast<float*>(static_cast<char*>(workspace) + (size_t)s.pack_units * 16 + 256);
+  // both networks' FP16 operands (layer 0 in input order, the hidden layers in the chained order)
+  s.pa_ep.w = p->ep_weights;
+  s.pa_col.w = p->col_weights;
+  hipLaunchKernelGGL(k_pack_lp<Lp::FP16>, dim3(64, kFaLayers), dim3(256), 0, strm, s.pa_ep, pack, bias);
+  hipLaunchKernelGGL(k_pack_lp<Lp::FP16>, dim3(64, kFaLayers), dim3(256), 0, strm, s.pa_col, pack, bias);
+  st = check_launch("ntbc_faithful_infer: pack");
+  if (st != NTBC_OK) return st;
+  FaithArgs a{};
+  InferArgs& k = a.pk;
+  k.n_textures = d->n_textures;
+  int e = 0, c = 0;
+  for (int t = 0; t < d->n_textures; ++t) {
+    k.formats[t] = d->formats[t];
+    k.ep_off[t] = e;
+    k.ch_off[t] = c;
+    e += d->formats[t] == NTBC_BC1 ? 6 : 2;
+    c += d->formats[t] == NTBC_BC1 ? 3 : 1;
+  }
+  k.endpoint_dim = s.E;
+  k.channels = s.C;
+  k.head_dim = s.E + 16 * s.C;
+  k.head_stride = k.head_dim | 1;
+  k.first = first_block;
+  k.n = n_blocks;
+  k.out = blocks_out;
+  k.heads = heads_out;
+  const int u8 = d->grid_dtype == NTBC_GRID_U8;
+  a.eg = fa_grid(d->ep_levels, d->ep_base_res, d->blocks_w, d->blocks_h, u8, p->ep_grid, p->ep_scale, p->ep_zero);
+  a.cg = fa_grid(d->col_levels, d->col_base_res, 4 * d->blocks_w, 4 * d->blocks_h, u8, p->col_grid, p->col_scale,
+                 p->col_zero);
+  a.wpack = pack;
+  a.bias = bias;
+  a.ep = s.ep;
+  a.col = s.col;
+  const size_t lds = (size_t)kFaWaves * 32 * k.head_stride * sizeof(float);
+  NTBC_REQUIRE(lds <= 160 * 1024, "heads need %zu bytes of LDS", lds);
+  NTBC_HIP(hipFuncSetAttribute((const void*)k_faithful, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const unsigned blocks = (unsigned)ceil_div(n_blocks, 32 * kFaWaves);
+  hipLaunchKernelGGL(k_faithful, dim3(blocks), dim3(64 * kFaWaves), lds, strm, a);
+  return check_launch("k_faithful");
+}
+#endif  // NTBC_PART(9)

@@ -38,6 +38,17 @@ class ModelDesc(ctypes.Structure):
                 ("blocks_w", ctypes.c_int32), ("blocks_h", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
+class FaithfulDesc(ctypes.Structure):
+    _fields_ = [("ep_levels", ctypes.c_int32), ("ep_base_res", ctypes.c_int32), ("col_levels", ctypes.c_int32),
+                ("col_base_res", ctypes.c_int32), ("grid_dtype", ctypes.c_int32), ("n_textures", ctypes.c_int32),
+                ("formats", ctypes.c_int32 * MAX_TEXTURES), ("blocks_w", ctypes.c_int32), ("blocks_h", ctypes.c_int32)]
+
+
+class FaithfulParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("ep_grid", "ep_scale", "ep_zero", "col_grid", "col_scale", "col_zero",
+                                                 "ep_weights", "col_weights")]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_void_p), ("grid_scale", ctypes.c_void_p),
                 ("grid_zero", ctypes.c_void_p), ("weights", ctypes.c_void_p),
@@ -98,6 +109,10 @@ _SIGNATURES = {
                        ctypes.c_int),
     "ntbc_naive_loss_grad": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TargetsC), _P, _P, _I32, _I32, _P, _P, _P],
                              ctypes.c_int),
+    "ntbc_faithful_sizes": ([ctypes.POINTER(FaithfulDesc), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                             ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ntbc_faithful_infer": ([ctypes.POINTER(FaithfulDesc), ctypes.POINTER(FaithfulParams), _I64, _I64, _P, _P, _P, _SZ,
+                             _P], ctypes.c_int),
     "ntbc_train_step": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TrainStateC), ctypes.POINTER(TargetsC), _P,
                          _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P], ctypes.c_int),
     "ntbc_quantize_grid": ([ctypes.POINTER(ModelDesc), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
@@ -299,6 +314,47 @@ class Model:
         p.flags = REUSE_PACKED if reuse_packed else 0
         _check(lib().ntbc_infer_blocks_noalloc(ctypes.byref(self.desc), ctypes.byref(p), precision, first_block,
                                                n_blocks, _ptr(out), _ptr(h), _stream()))
+        return (out, h) if heads else out
+
+
+class FaithfulModel:
+    """One model of the paper's own layout (endpoint network + per-texel colour network, SELU, half
+    precision; ntbc_faithful_infer).  Grids are device tensors of 2 features per vertex (uint8 with
+    per-level scale/zero, or float32); weights are the canonical FP32 layouts of the two networks."""
+
+    def __init__(self, formats, blocks_w: int, blocks_h: int, ep_grid, col_grid, ep_weights, col_weights,
+                 ep_levels: int = 7, ep_base_res: int = 16, col_levels: int = 8, col_base_res: int = 16,
+                 ep_scale=None, ep_zero=None, col_scale=None, col_zero=None):
+        d = FaithfulDesc()
+        d.ep_levels, d.ep_base_res, d.col_levels, d.col_base_res = ep_levels, ep_base_res, col_levels, col_base_res
+        d.grid_dtype = GRID_U8 if ep_grid.dtype == torch.uint8 else GRID_F32
+        d.n_textures = len(formats)
+        for i, f in enumerate(formats):
+            d.formats[i] = int(f)
+        d.blocks_w, d.blocks_h = blocks_w, blocks_h
+        self.desc = d
+        self.tensors = [t.contiguous() if t is not None else None
+                        for t in (ep_grid, ep_scale, ep_zero, col_grid, col_scale, col_zero, ep_weights, col_weights)]
+        self.params = FaithfulParams(*[t.data_ptr() if t is not None else None for t in self.tensors])
+        ne, nc, ws = _I64(), _I64(), _SZ()
+        _check(lib().ntbc_faithful_sizes(ctypes.byref(d), ctypes.byref(ne), ctypes.byref(nc), ctypes.byref(ws)))
+        self.n_ep_weights, self.n_col_weights = ne.value, nc.value
+        self.ws = torch.empty(max(ws.value, 1), dtype=torch.uint8, device=ep_grid.device)
+        e = sum(6 if f == BC1 else 2 for f in formats)
+        c = sum(3 if f == BC1 else 1 for f in formats)
+        self.head_dim = e + 16 * c
+
+    def infer(self, first_block: int = 0, n_blocks: Optional[int] = None, heads: bool = False,
+              out: Optional[torch.Tensor] = None):
+        """Packed blocks int64 [n_textures, n_blocks] (and heads float32 [n_blocks, E + 16 C])."""
+        if n_blocks is None:
+            n_blocks = self.desc.blocks_w * self.desc.blocks_h - first_block
+        dev = self.ws.device
+        if out is None:
+            out = torch.empty((self.desc.n_textures, n_blocks), dtype=torch.int64, device=dev)
+        h = torch.empty((n_blocks, self.head_dim), dtype=torch.float32, device=dev) if heads else None
+        _check(lib().ntbc_faithful_infer(ctypes.byref(self.desc), ctypes.byref(self.params), first_block, n_blocks,
+                                         _ptr(out), _ptr(h), _ptr(self.ws), self.ws.numel(), _stream()))
         return (out, h) if heads else out
 
 
