@@ -5,7 +5,7 @@ Heads against the oracle's half-precision emulation (every layer input and weigh
 float64 accumulation): float32 accumulation noise now and then moves an activation across a half
 rounding boundary (one half ulp, 2^-11 relative), as for the one-trunk FP16 path: max 2e-3, p99 4e-4,
 median 1e-6.  Packing bit-exact on the kernel's own heads.  Both material layouts, uint8 and FP32 grids,
-a ragged block range."""
+ragged block ranges, single blocks at either end of the grid, the largest heads."""
 import numpy as np
 import pytest
 import torch
@@ -74,7 +74,6 @@ def test_paper_layout_matches_oracle(layout, u8):
     first, n = 37, bw * bh - 37 - 21                        # ragged at both ends
     ids = np.arange(first, first + n)
     bx, by = ids % bw, ids // bw
-    words_all = np.zeros((len(SIX), n), dtype=np.uint64)
     dys = []
     for grp in F.models_of(SIX, layout):
         fm = [SIX[i] for i in grp]
@@ -88,8 +87,6 @@ def test_paper_layout_matches_oracle(layout, u8):
         dys.append(dy.ravel())
         log(f"paper layout {layout} u8={u8} {len(fm)} textures: max|dY| {dy.max():.3g} p99 "
             f"{np.percentile(dy, 99):.3g} median {np.median(dy):.3g}")
-        for k, t in enumerate(grp):
-            words_all[t] = words[k]
     dy = np.concatenate(dys)
     assert dy.max() <= 2e-3 and np.percentile(dy, 99) <= 4e-4 and np.median(dy) <= 1e-6
 
@@ -103,3 +100,20 @@ def test_paper_layout_rejects_bad_shapes():
     m, _ = _model(rng, [BC1], 64, 64, False)
     with pytest.raises(ntbc.NtbcError):          # beyond the block grid
         m.infer(4000, 200)
+
+
+@pytest.mark.parametrize("formats,first,n", [([BC4], 4095, 1), ([BC1], 0, 1), ([BC1] * 8, 100, 65), ([BC4] * 8, 0, 4096)])
+def test_paper_layout_edge_ranges(formats, first, n):
+    # one block at either end of the grid, the largest endpoint head (eight BC1 textures: 48 outputs, two
+    # head tiles; 24 colour outputs) and eight single-channel textures, against the oracle
+    rng = np.random.default_rng(len(formats) + first)
+    bw = bh = 64
+    m, (el, ew, cl, cw) = _model(rng, formats, bw, bh, True)
+    words, heads = m.infer(first, n, heads=True)
+    words, heads = u64(words), heads.cpu().numpy()
+    assert np.array_equal(words, ON.pack(heads, formats, "f32"))
+    ids = np.arange(first, first + n)
+    y_or = F.block_heads(formats, el, ew, cl, cw, ids % bw, ids // bw, bw, bh, "fp16")
+    dy = np.abs(heads - y_or)
+    log(f"paper layout {len(formats)} textures, blocks [{first}, {first + n}): max|dY| {dy.max():.3g}")
+    assert dy.max() <= 2e-3 and np.median(dy) <= 1e-6
