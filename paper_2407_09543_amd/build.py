@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, object, extra flags): infer.hip compiles in parts (its NTBC_INFER_PART macro) so that its
 # many kernel instances build in parallel
 SOURCES = [("api.cpp", "api.o", []), ("codec.hip", "codec.o", []), ("train.hip", "train.o", [])] + [
-    ("infer.hip", f"infer_p{k}.o", [f"-DNTBC_INFER_PART={k}"]) for k in range(10)]
+    ("infer.hip", f"infer_p{k}.o", [f"-DNTBC_INFER_PART={k}"]) for k in range(11)]
 
 # Packed FP32 instructions are disabled (-packed-fp32-ops); contraction of a*b+c into FMA is disabled so
 # that the integer decisions taken in float32 (endpoint rounding, nearest palette entry) are the exact

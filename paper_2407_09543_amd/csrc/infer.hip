@@ -431,7 +431,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_lp(InferArgs a) {
 // two halves of 16 positions per wave for the BC epilogue, which reads code/255 from an LDS table.
 constexpr int kHeadTiles = 6;
 static_assert(32 * kHeadTiles == kHeadRows, "head rows");
-constexpr int kMaxChunks = 48;
+// chunks of the deepest network (kMaxLayers layers): FP32 (one 16-row tile per chunk, width 256)
+// needs 4 * 16 + 12 = 76, the 16-bit formats (two 32-row tiles) 4 * 4 + 3
+constexpr int kMaxChunks = 80;
 constexpr int kLdsWaves = 4;
 constexpr int kChunkTiles = 2;
 
@@ -1102,6 +1104,156 @@ __global__ void __launch_bounds__(64 * kWaves) k_infer_f32(InferArgs a) {
   pack_blocks<16>(a, y, lane, pos0);
 }
 
+// ------------------------------------------------------------------------------ FP32 kernel, LDS-staged
+// FP32 operands through v_mfma_f32_16x16x4f32, 16 positions per wave: lane (j, g) holds position j and
+// row g of every K-step, accumulator v of output tile t is neuron 16t + 4g + v, which the packer's
+// column order (f32_col) makes input row g of K-step 4t + v of the next layer, so a layer's outputs are
+// the next layer's B operands in place.  The weights stream through LDS as in the 16-bit kernels
+// (chunks of kF32ChunkTiles output tiles over the full K, double-buffered, the next chunk's DMA under
+// the current chunk's products, A fragments read kPrefetch K-steps ahead); every index into the
+// activation arrays is a compile-time constant, so they stay in registers.  One 16-row tile per chunk
+// (16 KB at width 256) keeps a block's LDS near 46 KB, so three blocks of four waves share a CU: three
+// waves per SIMD (at most 168 registers: the two activation arrays take 128), which keeps the matrix
+// cores busier than two-tile chunks at two waves per SIMD (3.40 against 3.78 ms at the 4096^2
+// five-texture workload, the same words).  The first layer takes
+// 4 KQ K-steps (16 KQ inputs; the plan rounds its K-steps up to a multiple of four, padded with zero
+// weights).  The heads go through the exact sigmoid into LDS (reusing the chunk buffers) for the pack.
+constexpr int kF32Waves = 4;
+constexpr int kF32ChunkTiles = 1;
+constexpr int kF32HeadTiles = 2 * kHeadTiles;  // 16-row tiles: head_dim <= 192
+static_assert(kMaxChunks >= (kMaxLayers - 1) * 16 + kF32HeadTiles, "chunk table of the deepest FP32 network");
+
+template <int KS, int CT, int S>
+__device__ __forceinline__ void chunk_mfma_f32(const float* wb, const float (&b)[S], int lane, int valid,
+                                               f32x4_t (&acc)[CT]) {
+  constexpr int PD = kPrefetch < KS ? kPrefetch : KS;
+  float ring[PD][CT];
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+#pragma unroll
+    for (int u = 0; u < CT; ++u) ring[d][u] = u < valid ? wb[(u * KS + d) * 64 + lane] : 0.0f;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    float cur[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) cur[u] = ring[s % PD][u];
+    if (s + PD < KS) {
+#pragma unroll
+      for (int u = 0; u < CT; ++u)
+        if (u < valid) ring[s % PD][u] = wb[(u * KS + s + PD) * 64 + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+      if (u < valid) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[u], b[s], acc[u], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// One hidden layer of T output tiles over KS input K-steps: bias-initialised accumulators, products,
+// ReLU into `out` (K-step 4t + v of the next layer); chunk c is in LDS, chunk c + 1 is fetched meanwhile.
+template <int KS, int T, int S, int PR, int NT, int CH>
+__device__ __forceinline__ void f32_hidden(const float (&in)[KS], float (&out)[S], const float* bl,
+                                           const u32x4* __restrict__ wp, const ChunkTable& ct, u32x4* smem, int& c,
+                                           int tid, int lane, int g) {
+  constexpr int CT = kF32ChunkTiles;
+#pragma unroll
+  for (int tc = 0; tc < T / CT; ++tc) {
+    if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+    f32x4_t acc[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) {
+      const float4 b = *reinterpret_cast<const float4*>(bl + 16 * (CT * tc + u) + 4 * g);
+      acc[u] = f32x4_t{b.x, b.y, b.z, b.w};
+    }
+    chunk_mfma_f32<KS, CT, KS>(reinterpret_cast<const float*>(smem + (c & 1) * CH), in, lane, CT, acc);
+#pragma unroll
+    for (int u = 0; u < CT; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[4 * (CT * tc + u) + v] = fmaxf(acc[u][v], 0.0f);
+    wait_dma();
+    __syncthreads();
+    ++c;
+  }
+}
+
+template <int HID, int KQ>
+__global__ void __launch_bounds__(64 * kF32Waves) __attribute__((amdgpu_waves_per_eu(3)))
+k_infer_f32_lds(InferArgs a, ChunkTable ct) {
+  constexpr int S = HID / 4;   // K-steps of a hidden input
+  constexpr int T = HID / 16;  // output tiles of a hidden layer
+  constexpr int KS0 = 4 * KQ;  // first-layer K-steps
+  constexpr int CT = kF32ChunkTiles;
+  constexpr int CH = CT * S * 64 / 4;  // u32x4 per chunk buffer
+  constexpr int NT = 64 * kF32Waves;
+  constexpr int PR = (CH + NT - 1) / NT;
+  static_assert(T % CT == 0 && kF32HeadTiles % CT == 0 && KS0 <= S, "tile counts");
+  extern __shared__ u32x4 smem[];
+  float* tab = reinterpret_cast<float*>(smem + ct.stage);
+  float* bias_s = tab + 256;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int64_t pos0 = a.first + (xcd_tile(blockIdx.x, gridDim.x) * kF32Waves + wave) * 16;
+  const int64_t last = a.first + a.n - 1;
+  const int64_t id = pos0 + j <= last ? pos0 + j : last;
+  const int bx = (int)(id % a.grid.blocks_w), by = (int)(id / a.grid.blocks_w);
+  const u32x4* wp = reinterpret_cast<const u32x4*>(a.wpack);
+
+  chunk_dma<PR, NT>(wp, ct.src[0], ct.len[0], smem, tid);
+  for (int i = tid; i < 256; i += NT) tab[i] = (float)i / 255.0f;
+  for (int i = tid; i < ct.n_bias; i += NT) bias_s[i] = a.bias[i];
+  float x0[KS0];
+#pragma unroll
+  for (int s = 0; s < KS0; ++s) dev::features<1>(a.grid, 4 * s + g, bx, by, &x0[s]);
+  wait_dma();
+  __syncthreads();
+
+  int c = 0;
+  float bin[S], bout[S];
+  f32_hidden<KS0, T, S, PR, NT, CH>(x0, bin, bias_s + a.bias_off[0], wp, ct, smem, c, tid, lane, g);
+  for (int layer = 1; layer < a.n_layers - 1; ++layer) {
+    f32_hidden<S, T, S, PR, NT, CH>(bin, bout, bias_s + a.bias_off[layer], wp, ct, smem, c, tid, lane, g);
+#pragma unroll
+    for (int s = 0; s < S; ++s) bin[s] = bout[s];
+  }
+  // head: accumulators kept until the last chunk is done, then the sigmoid into the staged heads
+  const int head = a.n_layers - 1;
+  const int nht = a.otiles[head];
+  const float* bl = bias_s + a.bias_off[head];
+  f32x4_t hacc[kF32HeadTiles];
+#pragma unroll
+  for (int tc = 0; tc < kF32HeadTiles / CT; ++tc) {
+    if (CT * tc < nht) {
+      if (c + 1 < ct.n) chunk_dma<PR, NT>(wp, ct.src[c + 1], ct.len[c + 1], smem + ((c + 1) & 1) * CH, tid);
+      f32x4_t acc[CT];
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const float4 b = *reinterpret_cast<const float4*>(bl + 16 * (CT * tc + u) + 4 * g);
+        acc[u] = f32x4_t{b.x, b.y, b.z, b.w};
+      }
+      chunk_mfma_f32<S, CT, S>(reinterpret_cast<const float*>(smem + (c & 1) * CH), bin, lane, nht - CT * tc, acc);
+#pragma unroll
+      for (int u = 0; u < CT; ++u) hacc[CT * tc + u] = acc[u];
+      wait_dma();
+      __syncthreads();
+      ++c;
+    }
+  }
+  float* y = reinterpret_cast<float*>(smem) + wave * 16 * a.head_stride;
+#pragma unroll
+  for (int t = 0; t < kF32HeadTiles; ++t) {
+    if (t < nht) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int neuron = 16 * t + 4 * g + v;
+        if (neuron < a.head_dim) y[j * a.head_stride + neuron] = sigmoid(hacc[t][v]);
+      }
+    }
+  }
+  __syncthreads();
+  pack_blocks<16>(a, y, lane, pos0, tab);
+}
+
 // ------------------------------------------------------------------------------ host side
 constexpr int64_t kCalibBytes = 256;  // 2 x kMaxLayers maxima, padded
 
@@ -1138,6 +1290,7 @@ int make_plan(const ntbc_model_desc* d, int precision, Plan* p) {
     const int in = k == 0 ? p->s.in_dim : p->hid_inst;
     const int out = k == p->s.n_layers - 1 ? p->s.head_dim : p->hid_inst;
     p->ksteps[k] = (int)ceil_div(in, p->kstep);
+    if (!bf && k == 0) p->ksteps[k] = 4 * (int)ceil_div(in, 16);  // whole groups of 16 inputs (zero-padded)
     p->otiles[k] = (int)ceil_div(out, p->rows);
     p->pack_off[k] = off;
     // FP8 mode: offsets in 8-byte units; the first layer and the head hold bfloat16 operands (two units)
@@ -1240,6 +1393,31 @@ int make_chunks(const Plan& p, bool fp8, int head_stride, bool staged, ChunkTabl
   return NTBC_OK;
 }
 
+// The FP32 kernel's chunks: kF32ChunkTiles tiles of 16 rows over a layer's K-steps (4-byte operands).
+int make_chunks_f32(const Plan& p, int head_stride, ChunkTable* ct, size_t* lds_out) {
+  const Shape& s = p.s;
+  *ct = ChunkTable{};
+  for (int k = 0; k < s.n_layers; ++k) {
+    for (int t0 = 0; t0 < p.otiles[k]; t0 += kF32ChunkTiles) {
+      NTBC_REQUIRE(ct->n < kMaxChunks, "more than %d weight chunks", kMaxChunks);
+      const int nt = std::min(kF32ChunkTiles, p.otiles[k] - t0);
+      ct->src[ct->n] = (p.pack_off[k] + (int64_t)t0 * p.ksteps[k] * 64) * 4 / 16;
+      ct->len[ct->n] = (int)((int64_t)nt * p.ksteps[k] * 64 * 4 / 16);
+      ++ct->n;
+    }
+  }
+  int64_t nb = 0;
+  for (int k = 0; k < s.n_layers; ++k) nb = std::max<int64_t>(nb, p.bias_off[k] + (int64_t)p.otiles[k] * 16);
+  ct->n_bias = (int)((nb + 3) / 4 * 4);
+  const size_t chunk = (size_t)kF32ChunkTiles * (p.hid_inst / 4) * 64 * 4;
+  const size_t ybytes = (size_t)kF32Waves * 16 * head_stride * sizeof(float);
+  const size_t stage = std::max(2 * chunk, (ybytes + sizeof(u32x4) - 1) / sizeof(u32x4) * sizeof(u32x4));
+  ct->stage = (int)(stage / sizeof(u32x4));
+  *lds_out = stage + (256 + (size_t)ct->n_bias) * sizeof(float);
+  NTBC_REQUIRE(*lds_out <= 160 * 1024, "head_dim %d needs %zu bytes of LDS", s.head_dim, *lds_out);
+  return NTBC_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------ kernel instances
@@ -1256,6 +1434,7 @@ bool lds_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, const void** f
 bool batch_instance_bf16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
 bool batch_instance_fp16(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
 bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, int waves, const void** fn, BatchLaunch* launch);
+bool lds_instance_f32(int hid, int kq, const void** fn, LdsLaunch* launch);
 }  // namespace ntbc
 
 // Single-range instances: every precision at widths 64/128/256 with one to four input K-steps and a
@@ -1370,6 +1549,25 @@ bool batch_instance_fp8(int hid, int ks0, int nh, int nb1, int nb4, int waves, c
 #endif
 #undef NTBC_BATCH_W
 #undef NTBC_BATCH_BF16_W
+#if NTBC_PART(10)
+// FP32 LDS-staged instances: widths 64/128/256, one to four groups of 16 first-layer inputs.
+#define NTBC_F32_INSTANCE(H, KQ)                                                                        \
+  if (hid == H && kq == KQ) {                                                                           \
+    *fn = (const void*)k_infer_f32_lds<H, KQ>;                                                          \
+    *launch = [](dim3 gr, dim3 bl, size_t sh, hipStream_t st, const void* x, const void* y) {          \
+      hipLaunchKernelGGL((k_infer_f32_lds<H, KQ>), gr, bl, sh, st, *static_cast<const InferArgs*>(x), \
+                         *static_cast<const ChunkTable*>(y));                                           \
+    };                                                                                                  \
+    return true;                                                                                        \
+  }
+bool lds_instance_f32(int hid, int kq, const void** fn, LdsLaunch* launch) {
+  NTBC_F32_INSTANCE(64, 1) NTBC_F32_INSTANCE(64, 2) NTBC_F32_INSTANCE(64, 3) NTBC_F32_INSTANCE(64, 4)
+  NTBC_F32_INSTANCE(128, 1) NTBC_F32_INSTANCE(128, 2) NTBC_F32_INSTANCE(128, 3) NTBC_F32_INSTANCE(128, 4)
+  NTBC_F32_INSTANCE(256, 1) NTBC_F32_INSTANCE(256, 2) NTBC_F32_INSTANCE(256, 3) NTBC_F32_INSTANCE(256, 4)
+  return false;
+}
+#undef NTBC_F32_INSTANCE
+#endif
 }  // namespace ntbc
 #undef NTBC_LDS_INSTANCE_L
 #undef NTBC_LDS_INSTANCES
@@ -1630,6 +1828,19 @@ int infer_blocks(const Plan& p, const ntbc_model_desc* d, const ntbc_params* prm
     NTBC_REQUIRE(fn != nullptr, "no LDS kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
     NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     launch(dim3((unsigned)nwg), dim3(64 * kLdsWaves), lds, strm, &a, &ct);
+    return check_launch("ntbc_infer_blocks");
+  }
+  if (precision == NTBC_FP32 && p.otiles[s.n_layers - 1] <= kF32HeadTiles && p.ksteps[0] <= 16 && s.n_layers >= 2) {
+    ChunkTable ct{};
+    size_t lds = 0;
+    st = make_chunks_f32(p, a.head_stride, &ct, &lds);
+    if (st != NTBC_OK) return st;
+    const void* fn = nullptr;
+    LdsLaunch launch = nullptr;
+    if (!lds_instance_f32(p.hid_inst, p.ksteps[0] / 4, &fn, &launch)) fn = nullptr;
+    NTBC_REQUIRE(fn != nullptr, "no FP32 kernel instance for width %d, %d input K-steps", p.hid_inst, p.ksteps[0]);
+    NTBC_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    launch(dim3((unsigned)ceil_div(n_blocks, (int64_t)16 * kF32Waves)), dim3(64 * kF32Waves), lds, strm, &a, &ct);
     return check_launch("ntbc_infer_blocks");
   }
   const int64_t nwg = ceil_div(n_blocks, (int64_t)ppw * kWaves);

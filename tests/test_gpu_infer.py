@@ -54,7 +54,7 @@ def _device_model(cfg, flat, g):
     return ntbc.Model(desc, w, torch.from_numpy(g["grid"]).cuda())
 
 
-def _check(cfg, layers, g, words, heads, ids, precision):
+def _check(cfg, layers, g, words, heads, ids, precision, min_identity=None):
     """Compares GPU (words [T,n], heads [n,H]) at positions ids against the oracle."""
     lv = oracle_levels(cfg, g)
     y_or = ON.heads(cfg, lv, layers, ids, EMULATION[precision])
@@ -84,7 +84,7 @@ def _check(cfg, layers, g, words, heads, ids, precision):
         assert dy.max() <= tol[0]
         assert np.percentile(dy, 99) <= tol[1]
         assert np.median(dy) <= tol[2]
-        assert ident >= MIN_IDENTITY[precision], ident
+        assert ident >= (min_identity or MIN_IDENTITY)[precision], ident
     assert res["ties"] == res["differ"], "a differing block is not a boundary tie"
     return ident
 
@@ -153,7 +153,16 @@ VARIANTS = [
     ("f1_h64_bc1only", dict(n_levels=6, base_res=2, n_features=1, hidden=64, n_hidden=4, formats=(1, 1))),
     ("f4_bc4x8", dict(n_levels=4, base_res=8, n_features=4, hidden=96, n_hidden=2, formats=(4,) * 8)),
     ("f8_rect", dict(n_levels=4, base_res=4, n_features=8, hidden=64, n_hidden=2, blocks_w=48, blocks_h=20)),
+    # the deepest network at width 256 (the FP32 kernel's largest chunk table), and 80 inputs (beyond
+    # the weight-streaming kernels' 64: the per-wave kernels)
+    ("f8_h256_deep", dict(n_levels=4, base_res=4, n_features=8, hidden=256, n_hidden=4)),
+    ("f16_in80", dict(n_levels=5, base_res=2, n_features=16, hidden=128, n_hidden=1)),
 ]
+# four hidden layers of 256 carry more float32 accumulation-order noise into the heads than the other
+# shapes (16-bit max |dY| against the emulation 3e-3 for BF16, 3.4e-4 for half, p99 1e-3 / 1.4e-4), so
+# more blocks sit on a rounding boundary: measured 97.4% (BF16) and 99.3% (half) identical with a uint8
+# grid, every differing block a tie
+MIN_IDENTITY_DEEP = {ntbc.FP32: 0.999, ntbc.BF16: 0.95, ntbc.FP16: 0.985}
 
 
 @pytest.mark.parametrize("name,over", VARIANTS)
@@ -165,7 +174,8 @@ def test_shape_variants(name, over, precision):
         m = _device_model(dataclasses.replace(cfg, grid_u8=u8), flat, g)
         words, heads = m.infer(precision, heads=True)
         log(f"variant {name} u8={u8}")
-        _check(cfg, layers, g, u64(words), heads.cpu().numpy(), np.arange(cfg.n_positions), precision)
+        _check(cfg, layers, g, u64(words), heads.cpu().numpy(), np.arange(cfg.n_positions), precision,
+               MIN_IDENTITY_DEEP if name == "f8_h256_deep" else None)
 
 
 @pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16, ntbc.FP16])
