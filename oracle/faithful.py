@@ -20,6 +20,11 @@ A block decodes exactly as in oracle.ntbc: its endpoints come from one endpoint-
 16 texels' colours from 16 colour-network runs, and the index of each texel is the palette entry
 nearest to its predicted colour (Eq. dist).  So the heads of a block are assembled in oracle.ntbc's
 head layout and packed by oracle.ntbc.pack.
+Training (Sec. 3.2, Sec. 3.4) assembles the same heads for a batch of blocks, takes the NTBC losses
+and their straight-through gradient on them (oracle.ntbc.loss_and_grad: the aggressive layout's
+dummy distance nodes change neither value nor gradient), and back-propagates the endpoint part through
+the endpoint network to its grid and the 16 colour parts of each block through the colour network to
+its grid; Adam with the warm-up / cosine schedule updates both networks and both grids.
 
 Readings where the paper is silent:
   * SELU with the published constants of Klambauer et al. (2017): lambda = 1.0507009873554805,
@@ -31,6 +36,11 @@ Readings where the paper is silent:
   * Per-block cost: network executions (the inference table's measure) = 1 endpoint + 16 colour runs
     per model and block; "four network executions" of the conservative layout count each network of
     each model once.
+  * Training: the colour network of a batch of n blocks sees the 16 n texels of those blocks; the
+    losses are normalised per block batch as in oracle.ntbc (so a texel's colour error weighs as in
+    the one-trunk model); SELU's derivative is lambda (z > 0) and lambda alpha e^z (z <= 0, the left
+    branch at z = 0, as the forward's case split); grids in FP32 master form, fake-quantised per level
+    when QAT is on (oracle.grid), as in oracle.ntbc.
 """
 from __future__ import annotations
 
@@ -157,3 +167,128 @@ def infer_blocks(formats, models, bx, by, blocks_w: int, blocks_h: int, layout: 
         for k, t in enumerate(grp):
             out[t] = words[k]
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Training (Sec. 3.2, Sec. 3.4)
+# ------------------------------------------------------------------------------------------------
+def selu_grad(z):
+    """d selu / dz: lambda for z > 0, lambda alpha e^z otherwise."""
+    z = np.asarray(z, dtype=np.float64)
+    return np.where(z > 0.0, SELU_LAMBDA, SELU_LAMBDA * SELU_ALPHA * np.exp(np.minimum(z, 0.0)))
+
+
+def mlp_forward_cache(layers, x):
+    """Exact (float64) forward with the layer inputs and pre-activations kept for the backward."""
+    h = np.asarray(x, dtype=np.float64)
+    hs, zs = [h], []
+    for k, (w, b) in enumerate(layers):
+        z = h @ np.asarray(w, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
+        zs.append(z)
+        if k < len(layers) - 1:
+            h = selu(z)
+            hs.append(h)
+    with np.errstate(over="ignore"):
+        y = 1.0 / (1.0 + np.exp(-zs[-1]))
+    return y, (hs, zs)
+
+
+def mlp_backward(layers, cache, d_y, y):
+    """(dW list, db list, dx) of a scalar loss from dL/dY by the chain rule: dZ_out = dL/dY Y (1 - Y),
+    dW_k = dZ_k^T h_k, db_k = column sums of dZ_k, dh_k = dZ_k W_k, dZ_{k-1} = dh_k selu'(z_{k-1})."""
+    hs, zs = cache
+    dz = np.asarray(d_y, dtype=np.float64) * y * (1.0 - y)
+    dws, dbs = [None] * len(layers), [None] * len(layers)
+    dx = None
+    for k in range(len(layers) - 1, -1, -1):
+        dws[k] = dz.T @ hs[k]
+        dbs[k] = dz.sum(axis=0)
+        dh = dz @ np.asarray(layers[k][0], dtype=np.float64)
+        if k > 0:
+            dz = dh * selu_grad(zs[k - 1])
+        else:
+            dx = dh
+    return dws, dbs, dx
+
+
+def texel_coords(bx, by):
+    """Texture coordinates (tx, ty) of the 16 texels of each block, block-major (texel i = 4y + x)."""
+    bx = np.asarray(bx, dtype=np.int64)
+    by = np.asarray(by, dtype=np.int64)
+    i = np.arange(16)
+    tx = (4 * bx[:, None] + (i % 4)[None, :]).ravel()
+    ty = (4 * by[:, None] + (i // 4)[None, :]).ravel()
+    return tx, ty
+
+
+def _grid_values(grid, g, qat):
+    if qat:
+        return G.fake_quant_grid(grid, g["n_levels"], g["base_res"])
+    return np.asarray(grid, dtype=np.float64), None
+
+
+def gradients(formats, ep_grid, ep_layers, col_grid, col_layers, tg, ids, blocks_w: int, blocks_h: int,
+              qat: bool = False, temp: float = 0.01, terms=(1.0, 1.0, 1.0, 1.0), ep_cfg=None, col_cfg=None):
+    """Losses and gradients of one model of the layout at the given parameters for the block batch ids:
+    (losses, d_ep_grid, [(dW, db)] of the endpoint network, d_col_grid, [(dW, db)] of the colour
+    network, heads).  Grids [vertices][2] (FP32 master values), tg: oracle.ntbc.Targets of `formats`."""
+    ep_cfg = ep_cfg or ENDPOINT_GRID
+    col_cfg = col_cfg or COLOUR_GRID
+    ids = np.asarray(ids, dtype=np.int64)
+    n = len(ids)
+    e_dim, c_dim = output_nodes(formats)
+    bx, by = ids % blocks_w, ids // blocks_w
+    ge, me = _grid_values(ep_grid, ep_cfg, qat)
+    gc, mc = _grid_values(col_grid, col_cfg, qat)
+    xe = G.features(G.split_levels(ge, ep_cfg["n_levels"], ep_cfg["base_res"]), bx, by, blocks_w, blocks_h)
+    ye, ce = mlp_forward_cache(ep_layers, xe)
+    tx, ty = texel_coords(bx, by)
+    xc = G.features(G.split_levels(gc, col_cfg["n_levels"], col_cfg["base_res"]), tx, ty, 4 * blocks_w, 4 * blocks_h)
+    yc, cc = mlp_forward_cache(col_layers, xc)
+    y = np.concatenate([ye, yc.reshape(n, 16 * c_dim)], axis=1)
+    losses, dy = N.loss_and_grad(y, tg, ids, temp, terms)
+    dwe, dbe, dxe = mlp_backward(ep_layers, ce, dy[:, :e_dim], ye)
+    dwc, dbc, dxc = mlp_backward(col_layers, cc, dy[:, e_dim:].reshape(16 * n, c_dim), yc)
+    dge = G.features_backward(dxe, bx, by, blocks_w, blocks_h, ep_cfg["n_levels"], ep_cfg["base_res"],
+                              ep_cfg["n_features"], me)
+    dgc = G.features_backward(dxc, tx, ty, 4 * blocks_w, 4 * blocks_h, col_cfg["n_levels"], col_cfg["base_res"],
+                              col_cfg["n_features"], mc)
+    return losses, dge, list(zip(dwe, dbe)), dgc, list(zip(dwc, dbc)), y
+
+
+class TrainState:
+    """Parameters and Adam moments of one model of the layout (float64)."""
+
+    def __init__(self, ep_grid, ep_layers, col_grid, col_layers):
+        cp = lambda layers: [(np.asarray(w, np.float64).copy(), np.asarray(b, np.float64).copy()) for w, b in layers]
+        self.params = [np.asarray(ep_grid, np.float64).copy(), cp(ep_layers),
+                       np.asarray(col_grid, np.float64).copy(), cp(col_layers)]
+        zeros = lambda p: np.zeros_like(p) if isinstance(p, np.ndarray) else [(np.zeros_like(w), np.zeros_like(b))
+                                                                             for w, b in p]
+        self.m = [zeros(p) for p in self.params]
+        self.v = [zeros(p) for p in self.params]
+
+
+def train_step(formats, st: TrainState, tg, ids, blocks_w: int, blocks_h: int, step: int, total_steps: int,
+               qat: bool = False, lr_grid: float = 0.01, lr_mlp: float = 0.005, temp: float = 0.01,
+               ep_cfg=None, col_cfg=None):
+    """One iteration: gradients of both networks and grids, then Adam (grids at lr_grid, networks at
+    lr_mlp, both on oracle.ntbc's warm-up / cosine schedule); returns the losses."""
+    out = gradients(formats, st.params[0], st.params[1], st.params[2], st.params[3], tg, ids, blocks_w, blocks_h,
+                    qat, temp, ep_cfg=ep_cfg, col_cfg=col_cfg)
+    grads = out[1:5]
+    t = step + 1
+    lg = N.learning_rate(step, lr_grid, total_steps)
+    lm = N.learning_rate(step, lr_mlp, total_steps)
+    for k in range(4):
+        if k % 2 == 0:
+            st.params[k], st.m[k], st.v[k] = N.adam(st.params[k], grads[k], st.m[k], st.v[k], t, lg)
+            continue
+        for j, ((w, b), (dw, db)) in enumerate(zip(st.params[k], grads[k])):
+            (mw, mb), (vw, vb) = st.m[k][j], st.v[k][j]
+            w, mw, vw = N.adam(w, dw, mw, vw, t, lm)
+            b, mb, vb = N.adam(b, db, mb, vb, t, lm)
+            st.params[k][j] = (w, b)
+            st.m[k][j] = (mw, mb)
+            st.v[k][j] = (vw, vb)
+    return out[0]

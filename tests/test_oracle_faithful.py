@@ -150,3 +150,123 @@ def test_dummy_distance_nodes_change_nothing():
         l8, dd8, _ = N._cd_branch(delta8, pal8, c, n * 16 * 3, 0.01)
     assert l8 == l4
     assert np.allclose(dd8[..., :4], dd4, rtol=1e-9, atol=1e-15) and (dd8[..., 4:] == 0).all()
+
+
+# ------------------------------------------------------------------------------------------ training
+TINY_EP = dict(n_levels=3, base_res=2, n_features=2)    # 2 .. 8
+TINY_COL = dict(n_levels=3, base_res=4, n_features=2)   # 4 .. 16
+
+
+def _train_problem(seed=0, n=24):
+    """A 64^2 BC1 + BC4 material (16 x 16 blocks), small grids of both networks, random parameters."""
+    from oracle import bc
+    from paper_2407_09543_amd import synth
+    m = synth.material_small(64, seed + 1)
+    fm = [BC1, BC4]
+    blocks = [bc.image_to_blocks(t.texels) for t in m.textures]
+    tg = N.Targets(fm, [bc.bc1_encode_ref(blocks[0]), bc.bc4_encode_ref(blocks[1])], blocks)
+    rng = np.random.default_rng(seed)
+    e, c = F.output_nodes(fm)
+    ew, cw = _layers(rng, 6, e, 0.3), _layers(rng, 6, c, 0.3)
+    eg = rng.uniform(-0.5, 0.5, (F.grid_vertices(TINY_EP), 2))
+    cg = rng.uniform(-0.5, 0.5, (F.grid_vertices(TINY_COL), 2))
+    ids = rng.choice(256, n, replace=False)
+    return fm, tg, eg, ew, cg, cw, ids
+
+
+def test_selu_derivative_closed_form():
+    z = np.array([-6.0, -1.3, -0.2, -1e-3, 1e-3, 0.4, 3.0])
+    h = 1e-6
+    fd = (F.selu(z + h) - F.selu(z - h)) / (2 * h)
+    assert np.allclose(F.selu_grad(z), fd, rtol=1e-7, atol=0)
+    # the left branch at 0 (the forward's case split): lambda alpha
+    assert F.selu_grad(0.0) == F.SELU_LAMBDA * F.SELU_ALPHA
+
+
+def _fd_check(fm, tg, eg, ew, cg, cw, ids, rng, grads):
+    """Central differences of L_e + L_c (the smooth terms) against the analytic gradients at a sample
+    of weights, biases and touched grid vertices of both networks; returns the largest mismatch."""
+    terms = (1.0, 1.0, 0.0, 0.0)
+
+    def loss(p):
+        l = F.gradients(fm, p[0], p[1], p[2], p[3], tg, ids, 16, 16, terms=terms, ep_cfg=TINY_EP, col_cfg=TINY_COL)[0]
+        return l[0] + l[1]
+    params = [eg, ew, cg, cw]
+    h = 1e-6
+    worst = 0.0
+    for k in range(4):
+        for _ in range(8 if k % 2 else 5):
+            pp = [x.copy() if isinstance(x, np.ndarray) else [(w.copy(), b.copy()) for w, b in x] for x in params]
+            pm = [x.copy() if isinstance(x, np.ndarray) else [(w.copy(), b.copy()) for w, b in x] for x in params]
+            if k % 2 == 0:
+                touched = np.nonzero(np.abs(grads[k]).sum(axis=1) > 0)[0]
+                v, f = rng.choice(touched), rng.integers(0, 2)
+                pp[k][v, f] += h
+                pm[k][v, f] -= h
+                an = grads[k][v, f]
+            else:
+                layer = rng.integers(0, len(params[k]))
+                w = params[k][layer][0]
+                if rng.integers(0, 3) == 0:
+                    i = rng.integers(0, w.shape[0])
+                    pp[k][layer][1][i] += h
+                    pm[k][layer][1][i] -= h
+                    an = grads[k][layer][1][i]
+                else:
+                    i, j = rng.integers(0, w.shape[0]), rng.integers(0, w.shape[1])
+                    pp[k][layer][0][i, j] += h
+                    pm[k][layer][0][i, j] -= h
+                    an = grads[k][layer][0][i, j]
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            worst = max(worst, abs(fd - an) / max(abs(fd), 1e-6))
+    return worst
+
+
+def test_training_gradients_against_finite_differences():
+    # both networks and both grids, through the head assembly, the SELU layers and the texel-centre
+    # scatter of the colour grid
+    fm, tg, eg, ew, cg, cw, ids = _train_problem()
+    out = F.gradients(fm, eg, ew, cg, cw, tg, ids, 16, 16, terms=(1.0, 1.0, 0.0, 0.0), ep_cfg=TINY_EP,
+                      col_cfg=TINY_COL)
+    worst = _fd_check(fm, tg, eg, ew, cg, cw, ids, np.random.default_rng(7), out[1:5])
+    assert worst < 1e-5, worst
+
+
+def test_training_gradient_planted_selu_mistake_fails(monkeypatch):
+    # the ReLU-style derivative (lambda on both sides) is a plausible slip: the check catches it
+    fm, tg, eg, ew, cg, cw, ids = _train_problem(1)
+    monkeypatch.setattr(F, "selu_grad", lambda z: np.full(np.shape(z), F.SELU_LAMBDA))
+    out = F.gradients(fm, eg, ew, cg, cw, tg, ids, 16, 16, terms=(1.0, 1.0, 0.0, 0.0), ep_cfg=TINY_EP,
+                      col_cfg=TINY_COL)
+    worst = _fd_check(fm, tg, eg, ew, cg, cw, ids, np.random.default_rng(8), out[1:5])
+    assert worst > 1e-3, worst
+
+
+def test_training_heads_are_the_inference_heads():
+    # the training forward assembles the same heads as the inference oracle (float64)
+    fm, tg, eg, ew, cg, cw, ids = _train_problem(2)
+    y = F.gradients(fm, eg, ew, cg, cw, tg, ids, 16, 16, ep_cfg=TINY_EP, col_cfg=TINY_COL)[5]
+    el = G.split_levels(eg, TINY_EP["n_levels"], TINY_EP["base_res"])
+    cl = G.split_levels(cg, TINY_COL["n_levels"], TINY_COL["base_res"])
+    y_inf = F.block_heads(fm, el, ew, cl, cw, ids % 16, ids // 16, 16, 16, "f64")
+    assert np.allclose(y, y_inf, rtol=0, atol=1e-14)
+
+
+def test_train_step_first_adam_update_is_signed_learning_rate():
+    # Adam's first bias-corrected step moves every parameter by lr g / (|g| + eps), i.e. by lr sign(-g)
+    # where |g| >> eps (lr of the warm-up's first step: lr0 / 10), grids at lr_grid and networks at
+    # lr_mlp; untouched vertices stay
+    fm, tg, eg, ew, cg, cw, ids = _train_problem(3)
+    st = F.TrainState(eg, ew, cg, cw)
+    grads = F.gradients(fm, eg, ew, cg, cw, tg, ids, 16, 16, ep_cfg=TINY_EP, col_cfg=TINY_COL)[1:5]
+    F.train_step(fm, st, tg, ids, 16, 16, 0, 100, lr_grid=0.01, lr_mlp=0.005, ep_cfg=TINY_EP, col_cfg=TINY_COL)
+    for k, lr in ((0, 0.001), (1, 0.0005), (2, 0.001), (3, 0.0005)):
+        if k % 2 == 0:
+            pairs = [(st.params[k], (eg, cg)[k // 2], grads[k])]
+        else:
+            pairs = [(a, b, c) for (a, _), (b, _), (c, _) in zip(st.params[k], (ew, cw)[k // 2], grads[k])]
+        for new, old, g in pairs:
+            big = np.abs(g) > 1e-6
+            assert big.mean() > 0.5
+            assert np.allclose((new - old)[big], -lr * np.sign(g[big]), rtol=1e-8, atol=0)
+            assert (new[g == 0] == old[g == 0]).all()
