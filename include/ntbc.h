@@ -407,6 +407,40 @@ int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state* st, const 
  * the flag later, or never. */
 int ntbc_train_status(const float* losses, void* stream);
 
+/* ---- the paper's own layout: training ------------------------------------------------------------ */
+
+/* Training state of one model of the paper's layout (host struct of device pointers, caller-owned):
+ * FP32 master grids ([V][2], level-major as in ntbc_faithful_params) and weights (each network's
+ * canonical layout, sizes from ntbc_faithful_sizes), Adam moments of the same shapes (zero before the
+ * first step) and the gradient buffers that each step overwrites. */
+typedef struct {
+  float *ep_grid, *col_grid, *ep_weights, *col_weights;
+  float *m_ep_grid, *v_ep_grid, *m_col_grid, *v_col_grid;
+  float *m_ep_weights, *v_ep_weights, *m_col_weights, *v_col_weights;
+  float *d_ep_grid, *d_col_grid, *d_ep_weights, *d_col_weights;
+} ntbc_faithful_train_state;
+
+/* Workspace bytes of ntbc_faithful_train_step for `batch` blocks.  Host only. */
+int ntbc_faithful_train_size(const ntbc_faithful_desc* d, int32_t batch, size_t* workspace_bytes);
+
+/* One training iteration of one model of the paper's layout (Sec. 3.2 training procedure and Eqs.
+ * lossNTBC; App. A straight-through estimator; Sec. 3.3 QAT; Sec. 3.4 configuration, Adam and schedule;
+ * Sec. 4.1 layouts): the endpoint network at the batch's blocks and the colour network at their 16 *
+ * batch texels (FP32 products, SELU hidden layers), the heads assembled in the NTBC layout, the NTBC
+ * losses and their straight-through gradient (as ntbc_loss_grad: the aggressive layout's dummy distance
+ * nodes change neither), the backward through both networks into both grids (the quantiser's
+ * pass-through when h->qat), then Adam on the four parameter sets (grids at lr_grid, networks at lr_mlp,
+ * the learning rates of step `step` of the schedule).  d->grid_dtype must be NTBC_GRID_F32 (the master
+ * grids); h->precision NTBC_FP32, else NTBC_EUNSUPPORTED; h->deterministic as for ntbc_train_step;
+ * t: the targets of the model's textures, in their order.  losses_out (device float[5]) as for
+ * ntbc_train_step: a non-finite value skips the update and sets losses_out[4] = 1.  A conservative
+ * material trains its two models with one call each.  Errors: NTBC_EINVAL, NTBC_ENOWORKSPACE,
+ * NTBC_EUNSUPPORTED. */
+int ntbc_faithful_train_step(const ntbc_faithful_desc* d, const ntbc_faithful_train_state* st,
+                             const ntbc_targets* t, const int32_t* batch_ids, int32_t batch, int64_t step,
+                             const ntbc_hparams* h, float* losses_out, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
 /* Training batch `step`: `batch` block-position ids drawn uniformly with replacement from
  * [0, n_positions) (the paper leaves the sampling unspecified).  Generator: SplitMix64 (Steele, Lea &
  * Flood 2014).  The stream key is k = mix(mix(mix(0, seed), 0xBA7C4), step) with

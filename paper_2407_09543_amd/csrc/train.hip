@@ -369,7 +369,16 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t count) {
 }
 
 // ------------------------------------------------------------------------------------------ GEMM
-enum Epi { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS_SIGMOID = 2, EPI_MASK = 3, EPI_ATOMIC = 4 };
+enum Epi { EPI_STORE = 0, EPI_BIAS_RELU = 1, EPI_BIAS_SIGMOID = 2, EPI_MASK = 3, EPI_ATOMIC = 4, EPI_BIAS_SELU = 5,
+           EPI_SELU_MASK = 6 };
+
+// SELU (the paper's own layout, Sec. 3.4) with the constants of Klambauer et al. (2017).  Its
+// derivative from the layer output h = selu(z): lambda where h > 0 (z > 0), otherwise
+// lambda alpha e^z = h + lambda alpha; NaN stays NaN in both.
+constexpr float kSeluLambda = 1.0507009873554805f;
+constexpr float kSeluLambdaAlpha = 1.0507009873554805f * 1.6732632423543772f;
+__device__ __forceinline__ float selu_f(float z) { return z > 0.0f ? kSeluLambda * z : kSeluLambdaAlpha * expm1f(z); }
+__device__ __forceinline__ float selu_grad_of_out(float h) { return h > 0.0f ? kSeluLambda : h + kSeluLambdaAlpha; }
 
 struct GemmArgs {
   const float* a;
@@ -461,6 +470,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
           *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
         } else if (EPI == EPI_BIAS_SIGMOID) {
           *out = 1.0f / (1.0f + expf(-(val + g.bias[n])));
+        } else if (EPI == EPI_BIAS_SELU) {
+          *out = selu_f(val + g.bias[n]);
+        } else if (EPI == EPI_SELU_MASK) {
+          *out = val * selu_grad_of_out(g.mask[(int64_t)m * g.ldm + n]);
         } else if (EPI == EPI_MASK) {
           *out = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? val : 0.0f;
         } else if (EPI == EPI_ATOMIC) {
@@ -644,10 +657,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     const int n = n0 + wn * 64 + 32 * j + li;
     if (n >= g.N) continue;
     // the lane's column: its bias read once, rows addressed from one base with 32-bit row offsets
-    const float bn = (EPI == EPI_BIAS_RELU || EPI == EPI_BIAS_SIGMOID) ? g.bias[n] : 0.0f;
+    const float bn = (EPI == EPI_BIAS_RELU || EPI == EPI_BIAS_SIGMOID || EPI == EPI_BIAS_SELU) ? g.bias[n] : 0.0f;
     const int mb = m0 + wm * 64 + 4 * lg;
     float* __restrict__ cb = g.c + (int64_t)mb * g.ldc + n;
-    const float* __restrict__ kb = EPI == EPI_MASK ? g.mask + (int64_t)mb * g.ldm + n : nullptr;
+    const float* __restrict__ kb = EPI == EPI_MASK || EPI == EPI_SELU_MASK ? g.mask + (int64_t)mb * g.ldm + n : nullptr;
     const int ldc = (int)g.ldc, ldm = (int)g.ldm;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -662,6 +675,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
           *out = z < 0.0f ? 0.0f : z;  // ReLU that keeps NaN (so a non-finite parameter is detected)
         } else if (EPI == EPI_BIAS_SIGMOID) {
           *out = 1.0f / (1.0f + expf(-(val + bn)));
+        } else if (EPI == EPI_BIAS_SELU) {
+          *out = selu_f(val + bn);
+        } else if (EPI == EPI_SELU_MASK) {
+          *out = val * selu_grad_of_out(kb[dm * ldm]);
         } else if (EPI == EPI_MASK) {
           *out = kb[dm * ldm] > 0.0f ? val : 0.0f;
         } else if (EPI == EPI_ATOMIC) {
@@ -1283,6 +1300,12 @@ __device__ __forceinline__ u32x4 fpack8(const float* v) {
 
 __device__ __forceinline__ uint16_t fbf1(float x) { return (uint16_t)(fbf2(x, 0.0f) & 0xFFFFu); }
 
+// Sigmoid from the hardware exp2 and reciprocal (each within about one ulp): |error| < 3e-7 for |z| < 64,
+// far inside the bfloat16 products' rounding.
+__device__ __forceinline__ float fsigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * 1.4426950408889634f));
+}
+
 __device__ __forceinline__ f32x16_t fmma(const u32x4& a, const u32x4& b, const f32x16_t& c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
                                                  0, 0, 0);
@@ -1489,37 +1512,68 @@ __device__ __forceinline__ f32x16_t facc_bias(const float* bt, int g) {
   return r;
 }
 
-// Stores the eight bfloat16 values of operand x (rows r0 .. r0+7) at column p of buf.
-__device__ __forceinline__ void fstore_rows8(uint16_t* __restrict__ buf, int64_t bpad, int r0, int64_t p, const u32x4& x) {
-  int stride = (int)bpad;
-  asm volatile("" : "+s"(stride));
-  const uint32_t base = (uint32_t)r0 * (uint32_t)stride + (uint32_t)p;
-#pragma unroll
-  for (int m = 0; m < 8; ++m) buf[base + (uint32_t)(m * stride)] = (uint16_t)((x[m / 2] >> (16 * (m % 2))) & 0xFFFFu);
+// Position-contiguous bfloat16 stores ([row][bpad], 32 rows x the wave's 32 positions at a time)
+// go through a per-wave LDS patch: each lane writes its values of the 32 rows at its position (two-byte
+// LDS writes), then lane l reads row l/2, positions 16(l%2) .. +15 and stores them as two 16-byte words
+// (a wave writes 64 contiguous bytes of each row).  A wave's LDS operations complete in issue order, so
+// the wave needs no barrier between its writes and its reads, nor before its next patch.
+constexpr int kPatchLd = 40;                         // bfloat16 per patch row (80 bytes: the two lane
+                                                     // groups' rows fall on different LDS banks)
+constexpr int kPatchBytes = 32 * kPatchLd * 2;       // per wave
+static_assert(kPatchBytes % 16 == 0, "patch alignment");
+
+struct FStore {
+  uint16_t* patch;  // the wave's LDS patch
+  int j, lane;
+  int64_t p0;       // the wave's first position (a multiple of 32)
+};
+
+__device__ __forceinline__ uint16_t fhalf(const uint32_t* w, int v) { return (uint16_t)((w[v / 2] >> (16 * (v % 2))) & 0xFFFFu); }
+
+// Reads the patch back and stores rows row0 .. row0+31 (those below n_rows) of buf.
+__device__ __forceinline__ void fpatch_out(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int row0,
+                                           int n_rows) {
+  const int row = st.lane >> 1, h = st.lane & 1;
+  const u32x4 lo = *reinterpret_cast<const u32x4*>(st.patch + row * kPatchLd + 16 * h);
+  const u32x4 hi = *reinterpret_cast<const u32x4*>(st.patch + row * kPatchLd + 16 * h + 8);
+  if (row0 + row < n_rows) {
+    int stride = (int)bpad;
+    asm volatile("" : "+s"(stride));
+    uint16_t* dst = buf + (uint32_t)(row0 + row) * (uint32_t)stride + st.p0 + 16 * h;
+    *reinterpret_cast<u32x4*>(dst) = lo;
+    *reinterpret_cast<u32x4*>(dst + 8) = hi;
+  }
 }
 
-// Stores the 16 bfloat16 values of an epilogue tile (words w: value v in the half v%2 of word v/2)
-// position-contiguous: value v belongs to neuron 32t + 8(v/4) + 4g + v%4, stored at element
-// neuron * stride + p of buf (zero for positions past the batch).  The stride passes through an empty
-// asm so that the row offsets are recomputed per tile (scalar multiplies) instead of being hoisted for
-// every tile of the layer into registers.
-__device__ __forceinline__ void fstore_tile(uint16_t* __restrict__ buf, int64_t bpad, int t, int g, int64_t p,
-                                            const uint32_t (&w)[8], bool live) {
-  int stride = (int)bpad;
-  asm volatile("" : "+s"(stride));
-  const uint32_t base = (uint32_t)(32 * t + 4 * g) * (uint32_t)stride + (uint32_t)p;
+// Two 16-row K-step operands (rows 32 pair + 16 u + 8g + m, m < 8, of operand x[u]) stored at the
+// lane's position: rows at or past n_rows are not stored.
+__device__ __forceinline__ void fstore_ksteps(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int pair, int g,
+                                              const u32x4& x0, const u32x4& x1, int n_rows) {
+  const uint32_t w0[4] = {x0[0], x0[1], x0[2], x0[3]}, w1[4] = {x1[0], x1[1], x1[2], x1[3]};
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const uint32_t off = base + (uint32_t)((8 * (v / 4) + v % 4) * stride);
-    buf[off] = live ? (uint16_t)((w[v / 2] >> (16 * (v % 2))) & 0xFFFFu) : (uint16_t)0;
+  for (int m = 0; m < 8; ++m) {
+    st.patch[(8 * g + m) * kPatchLd + st.j] = fhalf(w0, m);
+    st.patch[(16 + 8 * g + m) * kPatchLd + st.j] = fhalf(w1, m);
   }
+  fpatch_out(st, buf, bpad, 32 * pair, n_rows);
+}
+
+// The 16 bfloat16 values of an epilogue tile (words w: value v in the half v%2 of word v/2; value v is
+// neuron 32t + 8(v/4) + 4g + v%4), zero for positions past the batch.
+__device__ __forceinline__ void fstore_tile(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int t, int g,
+                                            const uint32_t (&w)[8], bool live) {
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    st.patch[(8 * (v / 4) + 4 * g + v % 4) * kPatchLd + st.j] = live ? fhalf(w, v) : (uint16_t)0;
+  fpatch_out(st, buf, bpad, 32 * t, 1 << 30);
 }
 
 // Forward epilogue of a hidden tile: ReLU (NaN kept, so a non-finite parameter reaches the gradient
 // check), the next product's two B operands, the derivative bits (z > 0) and the bfloat16 outputs
 // stored position-contiguous (zero for positions past the batch).
 __device__ __forceinline__ uint32_t fhidden_epilogue(const f32x16_t& acc, int t, int g, u32x4* lo, u32x4* hi,
-                                                     uint16_t* __restrict__ ht, int64_t bpad, int64_t p, bool live) {
+                                                     uint16_t* __restrict__ ht, int64_t bpad, const FStore& st,
+                                                     bool live) {
   float r[16];
   uint32_t bits = 0;
 #pragma unroll
@@ -1531,14 +1585,14 @@ __device__ __forceinline__ uint32_t fhidden_epilogue(const f32x16_t& acc, int t,
   *lo = fpack8(r);
   *hi = fpack8(r + 8);
   const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
-  fstore_tile(ht, bpad, t, g, p, w, live);
+  fstore_tile(st, ht, bpad, t, g, w, live);
   return bits;
 }
 
 template <int S, int T>
 __device__ __forceinline__ void fwd_hidden(const FwdArgs& a, const u32x4 (&in)[S], u32x4 (&out)[S], const float* bl,
                                            uint16_t* __restrict__ ht, uint32_t* __restrict__ mk, u32x4* smem, int& c,
-                                           int tid, int lane, int g, int64_t p, bool live) {
+                                           int tid, int lane, int g, const FStore& st, bool live) {
 #pragma unroll
   for (int tc = 0; tc < T / kFChunkTiles; ++tc) {
     fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
@@ -1550,7 +1604,7 @@ __device__ __forceinline__ void fwd_hidden(const FwdArgs& a, const u32x4 (&in)[S
 #pragma unroll
     for (int u = 0; u < kFChunkTiles; ++u) {
       const int t = kFChunkTiles * tc + u;
-      word |= fhidden_epilogue(acc[u], t, g, &out[2 * t], &out[2 * t + 1], ht, a.bpad, p, live) << (16 * u);
+      word |= fhidden_epilogue(acc[u], t, g, &out[2 * t], &out[2 * t + 1], ht, a.bpad, st, live) << (16 * u);
     }
     mk[tc * 64] = word;
     fwait_dma();
@@ -1563,10 +1617,11 @@ template <int HID, int KS0, int NH, int HT>
 __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2))) k_train_fwd(FwdArgs a) {
   constexpr int S = HID / 16, T = HID / 32;
   extern __shared__ u32x4 smem[];
-  float* bias_s = reinterpret_cast<float*>(smem + 2 * a.ct.cap);
+  float* bias_s = reinterpret_cast<float*>(smem + 2 * a.ct.cap + kFW * kPatchBytes / 16);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 31, g = lane >> 5;
   const int64_t p = (int64_t)blockIdx.x * kFPos + wave * 32 + j;
   const bool live = p < a.n;
+  const FStore st{reinterpret_cast<uint16_t*>(smem + 2 * a.ct.cap + wave * kPatchBytes / 16), j, lane, p - j};
   const int id = live ? clamp_id(a.ids[p], a.n_positions) : 0;
   const int bx = id % a.blocks_w, by = id / a.blocks_w;
   const int n_hidden = a.n_layers - 1;
@@ -1584,8 +1639,9 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
       for (int m = 0; m < 8; ++m) v[m] = 0.0f;
     }
     x0[s] = fpack8(v);
-    fstore_rows8(a.xt, a.bpad, 16 * s + 8 * g, p, x0[s]);
   }
+#pragma unroll
+  for (int s = 0; s < KS0; s += 2) fstore_ksteps(st, a.xt, a.bpad, s / 2, g, x0[s], s + 1 < KS0 ? x0[s + 1] : u32x4{}, 16 * KS0);
   fwait_dma();
   __syncthreads();
 
@@ -1605,7 +1661,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
       for (int u = 0; u < kFChunkTiles; ++u) {
         const int t = kFChunkTiles * tc + u;
-        word |= fhidden_epilogue(acc[u], t, g, &bin[2 * t], &bin[2 * t + 1], a.ht, a.bpad, p, live) << (16 * u);
+        word |= fhidden_epilogue(acc[u], t, g, &bin[2 * t], &bin[2 * t + 1], a.ht, a.bpad, st, live) << (16 * u);
       }
       mk[tc * 64] = word;
       fwait_dma();
@@ -1615,10 +1671,10 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
   }
   static_assert(NH >= 1 && NH <= 2, "one or two middle hidden layers");
   fwd_hidden<S, T>(a, bin, bout, bias_s + a.bias_off[1], a.ht + (int64_t)HID * a.bpad, mbase + (T / 2) * 64, smem, c, tid,
-                   lane, g, p, live);
+                   lane, g, st, live);
   if constexpr (NH == 2) {
     fwd_hidden<S, T>(a, bout, bin, bias_s + a.bias_off[2], a.ht + (int64_t)2 * HID * a.bpad, mbase + 2 * (T / 2) * 64,
-                     smem, c, tid, lane, g, p, live);
+                     smem, c, tid, lane, g, st, live);
   } else {
 #pragma unroll
     for (int s = 0; s < S; ++s) bin[s] = bout[s];
@@ -1642,7 +1698,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
           const int r0 = 32 * t + 8 * q + 4 * g;
           float o[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) o[r] = 1.0f / (1.0f + expf(-acc[u][4 * q + r]));
+          for (int r = 0; r < 4; ++r) o[r] = fsigmoid(acc[u][4 * q + r]);
           float* dst = a.y + p * a.y_ld + r0;
           if ((a.y_ld & 3) == 0) {
             if (r0 < a.head_dim) *reinterpret_cast<float4*>(dst) = float4{o[0], o[1], o[2], o[3]};
@@ -1677,21 +1733,21 @@ struct BwdArgs {
 // Backward epilogue of a tile: dZ = dH * (z > 0) (`bits`), the next product's B operands, and the
 // bfloat16 dZ stored position-contiguous.
 __device__ __forceinline__ void fbwd_epilogue(const f32x16_t& acc, uint32_t bits, int t, int g, u32x4* lo, u32x4* hi,
-                                              uint16_t* __restrict__ zt, int64_t bpad, int64_t p, bool live) {
+                                              uint16_t* __restrict__ zt, int64_t bpad, const FStore& st, bool live) {
   float r[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) r[v] = ((bits >> v) & 1u) ? acc[v] : 0.0f;
   *lo = fpack8(r);
   *hi = fpack8(r + 8);
   const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
-  fstore_tile(zt, bpad, t, g, p, w, live);
+  fstore_tile(st, zt, bpad, t, g, w, live);
 }
 
 // One backward product W_k^T dZ_k over a hidden layer's rows (T tiles), K = KS steps of `in`.
 template <int KS, int NB, int S, int T>
 __device__ __forceinline__ void bwd_hidden(const BwdArgs& a, const u32x4 (&in)[NB], u32x4 (&out)[S],
                                            const uint32_t* __restrict__ mk, uint16_t* __restrict__ zt, u32x4* smem,
-                                           int& c, int tid, int lane, int g, int64_t p, bool live) {
+                                           int& c, int tid, int lane, int g, const FStore& st, bool live) {
 #pragma unroll
   for (int tc = 0; tc < T / kFChunkTiles; ++tc) {
     fchunk_dma(a.wpack, a.ct, c + 1, smem + ((c + 1) & 1) * a.ct.cap, tid);
@@ -1703,7 +1759,7 @@ __device__ __forceinline__ void bwd_hidden(const BwdArgs& a, const u32x4 (&in)[N
 #pragma unroll
     for (int u = 0; u < kFChunkTiles; ++u) {
       const int t = kFChunkTiles * tc + u;
-      fbwd_epilogue(acc[u], word >> (16 * u), t, g, &out[2 * t], &out[2 * t + 1], zt, a.bpad, p, live);
+      fbwd_epilogue(acc[u], word >> (16 * u), t, g, &out[2 * t], &out[2 * t + 1], zt, a.bpad, st, live);
     }
     fwait_dma();
     __syncthreads();
@@ -1720,6 +1776,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 31, g = lane >> 5;
   const int64_t p = (int64_t)blockIdx.x * kFPos + wave * 32 + j;
   const bool live = p < a.n;
+  const FStore st{reinterpret_cast<uint16_t*>(smem + 2 * a.ct.cap + wave * kPatchBytes / 16), j, lane, p - j};
   const int n_hidden = a.n_layers - 1;
   const uint32_t* mbase = a.masks + ((int64_t)(blockIdx.x * kFW + wave) * n_hidden) * (T / 2) * 64 + lane;
 
@@ -1734,8 +1791,9 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = (live && r0 + m < a.head_dim) ? a.dz[p * a.dz_ld + r0 + m] : 0.0f;
     dzh[s] = fpack8(v);
-    fstore_rows8(zh, a.bpad, r0, p, dzh[s]);
   }
+#pragma unroll
+  for (int s = 0; s < KH; s += 2) fstore_ksteps(st, zh, a.bpad, s / 2, g, dzh[s], dzh[s + 1], 16 * KH);
   fwait_dma();
   __syncthreads();
 
@@ -1744,14 +1802,14 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
   const int top = a.n_layers - 2;  // the last hidden layer
   // head^T: dZ of the last hidden layer
   bwd_hidden<KH, KH, S, T>(a, dzh, bin, mbase + top * (T / 2) * 64, a.dzt + a.zrow[top] * a.bpad, smem, c, tid, lane, g,
-                           p, live);
+                           st, live);
   // middle layers, from the top down
   static_assert(NH >= 1 && NH <= 2, "one or two middle hidden layers");
   bwd_hidden<S, S, S, T>(a, bin, bout, mbase + (top - 1) * (T / 2) * 64, a.dzt + a.zrow[top - 1] * a.bpad, smem, c,
-                         tid, lane, g, p, live);
+                         tid, lane, g, st, live);
   if constexpr (NH == 2) {
     bwd_hidden<S, S, S, T>(a, bout, bin, mbase + (top - 2) * (T / 2) * 64, a.dzt + a.zrow[top - 2] * a.bpad, smem, c,
-                           tid, lane, g, p, live);
+                           tid, lane, g, st, live);
   } else {
 #pragma unroll
     for (int s = 0; s < S; ++s) bin[s] = bout[s];
@@ -1773,9 +1831,15 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int f0 = 32 * t + 8 * q + 4 * g;
+            float* dst = a.dx + p * a.in_dim + f0;
+            if ((a.in_dim & 3) == 0) {
+              if (f0 < a.in_dim)
+                *reinterpret_cast<float4*>(dst) = float4{acc[u][4 * q], acc[u][4 * q + 1], acc[u][4 * q + 2], acc[u][4 * q + 3]};
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (f0 + r < a.in_dim) a.dx[p * a.in_dim + f0 + r] = acc[u][4 * q + r];
+              for (int r = 0; r < 4; ++r)
+                if (f0 + r < a.in_dim) dst[r] = acc[u][4 * q + r];
+            }
           }
         }
       }
@@ -2018,6 +2082,7 @@ struct Ctx {
   hipStream_t strm;
   bool bf16;  // bfloat16 matrix-core operands (FP32 accumulation, FP32 master parameters)
   bool det = false;     // deterministic reductions (grid scatter in fixed point, unsplit weight products)
+  bool selu = false;    // SELU hidden layers (the paper's own layout) instead of ReLU
   int64_t det_off = 0;  // byte offset of the deterministic scatter's sums in the workspace
   int* stats() { return reinterpret_cast<int*>(ws + lay.stats); }
   float* act_in(int k) { return k == 0 ? ws + lay.x : ws + lay.h[k - 1]; }
@@ -2073,7 +2138,9 @@ int forward(Ctx& c, const float* grid, const float* weights, bool qat, const int
     g.K = s.layer_in[k];
     g.k_split = g.K;
     g.bias = weights + s.b_off[k];
-    st = last ? gemm<EPI_BIAS_SIGMOID>(g, 1, c.strm, c.bf16) : gemm<EPI_BIAS_RELU>(g, 1, c.strm, c.bf16);
+    st = last     ? gemm<EPI_BIAS_SIGMOID>(g, 1, c.strm, c.bf16)
+         : c.selu ? gemm<EPI_BIAS_SELU>(g, 1, c.strm, c.bf16)
+                  : gemm<EPI_BIAS_RELU>(g, 1, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
   }
   return NTBC_OK;
@@ -2180,7 +2247,7 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
       st = check_launch("k_colsum");
       if (st != NTBC_OK) return st;
     }
-    // dH_k = dZ_k W_k, masked by the ReLU of the layer input (none for the grid features)
+    // dH_k = dZ_k W_k, times the activation derivative of the layer input (none for the grid features)
     GemmArgs gd{};
     gd.a = dz;
     gd.sam = out;
@@ -2197,7 +2264,7 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     if (k > 0) {
       gd.mask = c.act_in(k);
       gd.ldm = in;
-      st = gemm<EPI_MASK>(gd, 1, c.strm, c.bf16);
+      st = c.selu ? gemm<EPI_SELU_MASK>(gd, 1, c.strm, c.bf16) : gemm<EPI_MASK>(gd, 1, c.strm, c.bf16);
     } else {
       st = gemm<EPI_STORE>(gd, 1, c.strm, c.bf16);
     }
@@ -2464,7 +2531,7 @@ int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* we
   FwdKernel fk;
   BwdKernel bk;
   fused_kernels(f.hid, &fk, &bk);
-  const size_t lds = (size_t)2 * f.fct.cap * 16 + (size_t)f.n_bias * 4;
+  const size_t lds = (size_t)2 * f.fct.cap * 16 + (size_t)kFW * kPatchBytes + (size_t)f.n_bias * 4;
   NTBC_HIP(hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(fk, dim3((unsigned)(l.bpad / kFPos)), dim3(64 * kFW), lds, c.strm, a);
   return check_launch("k_train_fwd");
@@ -2494,7 +2561,7 @@ int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, cons
   FwdKernel fk;
   BwdKernel bk;
   fused_kernels(f.hid, &fk, &bk);
-  const size_t lds = (size_t)2 * f.bct.cap * 16;
+  const size_t lds = (size_t)2 * f.bct.cap * 16 + (size_t)kFW * kPatchBytes;
   NTBC_HIP(hipFuncSetAttribute((const void*)bk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(bk, dim3((unsigned)(l.bpad / kFPos)), dim3(64 * kFW), lds, c.strm, b);
   int st = check_launch("k_train_bwd");
@@ -2743,6 +2810,224 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(ng, 256), 8192)), dim3(256), 0, c.strm, tsd->grid,
                      tsd->d_grid, tsd->m_grid, tsd->v_grid, ng, aa);
   return check_launch("k_adam");
+}
+
+// ------------------------------------------------------------------------------------------ paper layout
+// Training of one model of the paper's own layout (Sec. 3.2, Sec. 3.4, Sec. 4.1): the endpoint network
+// runs as a model over the block grid and the colour network as a model over the texel grid (4 blocks_w
+// x 4 blocks_h cells), both through the FP32 forward / backward above with SELU hidden layers; the heads
+// of the batch's blocks are assembled in the NTBC layout for the loss, and its gradient is split back.
+namespace {
+
+void set_outputs(Shape* s, int out) {
+  s->head_dim = out;
+  s->layer_out[s->n_layers - 1] = out;
+  int64_t w = 0;
+  for (int k = 0; k < s->n_layers; ++k) {
+    s->w_off[k] = w;
+    w += (int64_t)s->layer_in[k] * s->layer_out[k];
+    s->b_off[k] = w;
+    w += s->layer_out[k];
+  }
+  s->n_weights = w;
+}
+
+// ep: the endpoint network (its grid over the block grid, E outputs); col: the colour network (its grid
+// over the texel grid, C outputs); loss: the NTBC head layout of the model's textures (E + 16 C).
+int faithful_shapes(const ntbc_faithful_desc* d, Shape* ep, Shape* col, Shape* loss) {
+  NTBC_REQUIRE(d != nullptr, "desc is NULL");
+  NTBC_REQUIRE(d->grid_dtype == NTBC_GRID_F32, "the paper layout trains FP32 master grids (grid_dtype %d)",
+               d->grid_dtype);
+  NTBC_REQUIRE(d->blocks_w >= 1 && d->blocks_h >= 1 && 16 * (int64_t)d->blocks_w * d->blocks_h < (1ll << 31),
+               "block grid %dx%d: its texels must number below 2^31", d->blocks_w, d->blocks_h);
+  NTBC_REQUIRE(d->n_textures >= 1 && d->n_textures <= NTBC_MAX_TEXTURES, "n_textures %d out of 1..%d", d->n_textures,
+               NTBC_MAX_TEXTURES);
+  ntbc_model_desc m{};
+  m.n_levels = d->ep_levels;
+  m.base_res = d->ep_base_res;
+  m.n_features = 2;
+  m.grid_dtype = NTBC_GRID_F32;
+  m.hidden_width = 64;
+  m.n_hidden = 3;
+  m.n_textures = d->n_textures;
+  for (int t = 0; t < d->n_textures; ++t) m.formats[t] = d->formats[t];
+  m.blocks_w = d->blocks_w;
+  m.blocks_h = d->blocks_h;
+  m.variant = NTBC_NTBC;
+  int st = make_shape(&m, loss);
+  if (st != NTBC_OK) return st;
+  *ep = *loss;
+  set_outputs(ep, loss->endpoint_dim);
+  m.n_levels = d->col_levels;
+  m.base_res = d->col_base_res;
+  m.blocks_w = 4 * d->blocks_w;
+  m.blocks_h = 4 * d->blocks_h;
+  st = make_shape(&m, col);
+  if (st != NTBC_OK) return st;
+  set_outputs(col, loss->channels);
+  return NTBC_OK;
+}
+
+struct FaithfulTrainLayout {
+  int64_t ep, col, tids, heads, dheads, total;  // byte offsets
+};
+
+FaithfulTrainLayout faithful_train_layout(const Shape& ep, const Shape& col, const Shape& loss, int64_t batch) {
+  FaithfulTrainLayout l{};
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  l.ep = take(train_workspace_bytes(ep, batch));
+  l.col = take(train_workspace_bytes(col, 16 * batch));
+  l.tids = take(16 * batch * 4);
+  l.heads = take(batch * loss.head_dim * 4);
+  l.dheads = take(batch * loss.head_dim * 4);
+  l.total = o;
+  return l;
+}
+
+Ctx faithful_ctx(const Shape& s, int64_t n, char* ws, hipStream_t strm, bool det) {
+  Ctx c;
+  c.s = s;
+  c.lay = train_layout(s, n);
+  c.ws = reinterpret_cast<float*>(ws);
+  c.n = n;
+  c.strm = strm;
+  c.bf16 = false;
+  c.det = det;
+  c.det_off = det_offset(s, n);
+  c.selu = true;
+  return c;
+}
+
+// The colour network's positions: texel i = 4y + x of block ids[p] is cell (4 bx + x, 4 by + y) of the
+// texel grid.
+__global__ void k_texel_ids(const int32_t* __restrict__ ids, int64_t n, int blocks_w, int64_t n_positions,
+                            int32_t* __restrict__ tids) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 16 * n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int id = clamp_id(ids[e >> 4], n_positions);
+    const int i = (int)(e & 15), bx = id % blocks_w, by = id / blocks_w;
+    tids[e] = (4 * by + (i >> 2)) * (4 * blocks_w) + 4 * bx + (i & 3);
+  }
+}
+
+// Heads [n][E + 16 C] from the endpoint outputs [n][E] and the colour outputs [16 n][C] (those of block p,
+// texel-major with C channels each, are its heads E .. E + 16 C - 1 in order); split = 1: the reverse.
+__global__ void k_fa_heads(float* __restrict__ heads, float* __restrict__ ye, float* __restrict__ yc, int64_t n,
+                           int E, int C, int split) {
+  const int H = E + 16 * C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * H; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / H;
+    const int k = (int)(e - p * H);
+    float* part = k < E ? ye + p * E + k : yc + p * 16 * C + (k - E);
+    if (split) *part = heads[e];
+    else heads[e] = *part;
+  }
+}
+
+// Learning rate of `step` (0-based): linear warm-up, then cosine annealing to 0 at total_steps.
+double schedule_lr(const ntbc_hparams* h, int64_t step, double lr0) {
+  if (step < h->warmup) return lr0 * (double)(step + 1) / h->warmup;
+  const double span = h->total_steps - h->warmup > 0 ? (double)(h->total_steps - h->warmup) : 1.0;
+  return lr0 * 0.5 * (1.0 + std::cos(M_PI * (double)(step - h->warmup) / span));
+}
+
+}  // namespace
+
+extern "C" int ntbc_faithful_train_size(const ntbc_faithful_desc* d, int32_t batch, size_t* workspace_bytes) {
+  NTBC_REQUIRE(workspace_bytes != nullptr, "workspace_bytes is NULL");
+  NTBC_REQUIRE(batch >= 1, "batch %d < 1", batch);
+  Shape ep, col, loss;
+  const int st = faithful_shapes(d, &ep, &col, &loss);
+  if (st != NTBC_OK) return st;
+  *workspace_bytes = (size_t)faithful_train_layout(ep, col, loss, batch).total;
+  return NTBC_OK;
+}
+
+extern "C" int ntbc_faithful_train_step(const ntbc_faithful_desc* d, const ntbc_faithful_train_state* tsd,
+                                        const ntbc_targets* t, const int32_t* batch_ids, int32_t batch, int64_t step,
+                                        const ntbc_hparams* h, float* losses_out, void* workspace,
+                                        size_t workspace_bytes, void* stream) {
+  NTBC_REQUIRE(h != nullptr && tsd != nullptr, "hparams or state is NULL");
+  Shape ep, col, loss;
+  int st = faithful_shapes(d, &ep, &col, &loss);
+  if (st != NTBC_OK) return st;
+  if (h->precision != NTBC_FP32)
+    return fail(NTBC_EUNSUPPORTED, "the paper layout trains with FP32 products (precision %d)", h->precision);
+  st = check_targets(loss, t);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(batch > 0 && batch_ids != nullptr, "batch must be positive, with ids");
+  NTBC_REQUIRE(step >= 0, "step must be >= 0");
+  NTBC_REQUIRE(tsd->ep_grid && tsd->col_grid && tsd->ep_weights && tsd->col_weights && tsd->m_ep_grid && tsd->v_ep_grid &&
+                   tsd->m_col_grid && tsd->v_col_grid && tsd->m_ep_weights && tsd->v_ep_weights && tsd->m_col_weights &&
+                   tsd->v_col_weights && tsd->d_ep_grid && tsd->d_col_grid && tsd->d_ep_weights && tsd->d_col_weights,
+               "a train-state pointer is NULL");
+  NTBC_REQUIRE(losses_out != nullptr, "losses_out is NULL");
+  NTBC_REQUIRE(h->temperature > 0.0f && h->total_steps > 0 && h->warmup >= 0, "bad temperature or schedule");
+  const FaithfulTrainLayout l = faithful_train_layout(ep, col, loss, batch);
+  if (workspace == nullptr || workspace_bytes < (size_t)l.total)
+    return fail(NTBC_ENOWORKSPACE, "workspace needs %lld bytes", (long long)l.total);
+  char* ws = static_cast<char*>(workspace);
+  const hipStream_t strm = as_stream(stream);
+  const bool det = h->deterministic != 0, qat = h->qat != 0;
+  Ctx ce = faithful_ctx(ep, batch, ws + l.ep, strm, det);
+  Ctx cc = faithful_ctx(col, 16 * (int64_t)batch, ws + l.col, strm, det);
+  int32_t* tids = reinterpret_cast<int32_t*>(ws + l.tids);
+  float* heads = reinterpret_cast<float*>(ws + l.heads);
+  float* dheads = reinterpret_cast<float*>(ws + l.dheads);
+  float* ye = ce.ws + ce.lay.y;
+  float* yc = cc.ws + cc.lay.y;
+  const int E = loss.endpoint_dim, C = loss.channels;
+  const unsigned hb = (unsigned)std::min<int64_t>(ceil_div((int64_t)batch * loss.head_dim, 256), 4096);
+  hipLaunchKernelGGL(k_texel_ids, dim3((unsigned)std::min<int64_t>(ceil_div(16 * (int64_t)batch, 256), 4096)), dim3(256),
+                     0, strm, batch_ids, (int64_t)batch, loss.blocks_w, loss.n_positions, tids);
+  st = check_launch("k_texel_ids");
+  if (st == NTBC_OK) st = forward(ce, tsd->ep_grid, tsd->ep_weights, qat, batch_ids, ye);
+  if (st == NTBC_OK) st = forward(cc, tsd->col_grid, tsd->col_weights, qat, tids, yc);
+  if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_fa_heads, dim3(hb), dim3(256), 0, strm, heads, ye, yc, (int64_t)batch, E, C, 0);
+  // dL/dZ of the output pre-activations of both networks, in the head layout, then split
+  st = loss_grad(loss, t, heads, batch_ids, batch, h->temperature, h->loss_weights, losses_out, dheads, strm, true);
+  if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_fa_heads, dim3(hb), dim3(256), 0, strm, dheads, ce.ws + ce.lay.dy, cc.ws + cc.lay.dy,
+                     (int64_t)batch, E, C, 1);
+  const int64_t nge = ep.grid_vertices * 2, ngc = col.grid_vertices * 2;
+  st = fill(tsd->d_ep_grid, nge, 0.0f, strm);
+  if (st == NTBC_OK) st = fill(tsd->d_col_grid, ngc, 0.0f, strm);
+  if (st == NTBC_OK) st = fill(tsd->d_ep_weights, ep.n_weights, 0.0f, strm);
+  if (st == NTBC_OK) st = fill(tsd->d_col_weights, col.n_weights, 0.0f, strm);
+  if (st == NTBC_OK) st = backward(ce, tsd->ep_grid, tsd->ep_weights, qat, batch_ids, tsd->d_ep_grid, tsd->d_ep_weights);
+  if (st == NTBC_OK) st = backward(cc, tsd->col_grid, tsd->col_weights, qat, tids, tsd->d_col_grid, tsd->d_col_weights);
+  if (st != NTBC_OK) return st;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(ep.n_weights, 256), 1024)), dim3(256), 0,
+                     strm, tsd->d_ep_weights, ep.n_weights, losses_out + 4);
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(col.n_weights, 256), 1024)), dim3(256), 0,
+                     strm, tsd->d_col_weights, col.n_weights, losses_out + 4);
+  const double tt = (double)step + 1.0;
+  AdamArgs aa{};
+  aa.b1 = h->beta1;
+  aa.b2 = h->beta2;
+  aa.eps = h->eps;
+  aa.bc1 = (float)(1.0 / (1.0 - std::pow((double)h->beta1, tt)));
+  aa.bc2 = (float)(1.0 / (1.0 - std::pow((double)h->beta2, tt)));
+  aa.flag = losses_out + 4;
+  struct Set {
+    float *p, *g, *m, *v;
+    int64_t n;
+    bool grid;
+  } sets[4] = {{tsd->ep_grid, tsd->d_ep_grid, tsd->m_ep_grid, tsd->v_ep_grid, nge, true},
+               {tsd->col_grid, tsd->d_col_grid, tsd->m_col_grid, tsd->v_col_grid, ngc, true},
+               {tsd->ep_weights, tsd->d_ep_weights, tsd->m_ep_weights, tsd->v_ep_weights, ep.n_weights, false},
+               {tsd->col_weights, tsd->d_col_weights, tsd->m_col_weights, tsd->v_col_weights, col.n_weights, false}};
+  for (const Set& q : sets) {
+    aa.lr = (float)schedule_lr(h, step, q.grid ? h->lr_grid : h->lr_mlp);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(q.n, 256), 8192)), dim3(256), 0, strm, q.p, q.g,
+                       q.m, q.v, q.n, aa);
+  }
+  return check_launch("ntbc_faithful_train_step");
 }
 
 extern "C" int ntbc_train_status(const float* losses, void* stream) {

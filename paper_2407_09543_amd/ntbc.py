@@ -62,6 +62,13 @@ class TrainStateC(ctypes.Structure):
                                                  "v_weights", "d_grid", "d_weights")]
 
 
+class FaithfulTrainStateC(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "ep_grid", "col_grid", "ep_weights", "col_weights", "m_ep_grid", "v_ep_grid", "m_col_grid", "v_col_grid",
+        "m_ep_weights", "v_ep_weights", "m_col_weights", "v_col_weights", "d_ep_grid", "d_col_grid", "d_ep_weights",
+        "d_col_weights")]
+
+
 class TargetsC(ctypes.Structure):
     _fields_ = [("ref_blocks", ctypes.c_void_p), ("texels", ctypes.c_void_p * MAX_TEXTURES)]
 
@@ -115,6 +122,10 @@ _SIGNATURES = {
                              _P], ctypes.c_int),
     "ntbc_train_step": ([ctypes.POINTER(ModelDesc), ctypes.POINTER(TrainStateC), ctypes.POINTER(TargetsC), _P,
                          _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P], ctypes.c_int),
+    "ntbc_faithful_train_size": ([ctypes.POINTER(FaithfulDesc), _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "ntbc_faithful_train_step": ([ctypes.POINTER(FaithfulDesc), ctypes.POINTER(FaithfulTrainStateC),
+                                  ctypes.POINTER(TargetsC), _P, _I32, _I64, ctypes.POINTER(HParams), _P, _P, _SZ, _P],
+                                 ctypes.c_int),
     "ntbc_quantize_grid": ([ctypes.POINTER(ModelDesc), _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "ntbc_train_status": ([_P, _P], ctypes.c_int),
     "ntbc_batch_ids": ([ctypes.c_uint64, _I64, _I32, _I64, _P, _P], ctypes.c_int),
@@ -559,6 +570,51 @@ class Trainer:
         """ntbc_train_status of the last step: OK, or ENONFINITE when it skipped its update (waits for
         the stream)."""
         return lib().ntbc_train_status(_ptr(self.losses), _stream())
+
+
+class FaithfulTrainer:
+    """FP32 master parameters, Adam state and scratch of one model of the paper's own layout
+    (ntbc_faithful_train_step): grids [V][2] float32, canonical FP32 weights of each network."""
+
+    def __init__(self, formats, blocks_w: int, blocks_h: int, ep_grid: torch.Tensor, col_grid: torch.Tensor,
+                 ep_weights: torch.Tensor, col_weights: torch.Tensor, targets: Targets, batch: int, total_steps: int,
+                 ep_levels: int = 7, ep_base_res: int = 16, col_levels: int = 8, col_base_res: int = 16,
+                 lr_grid: float = 0.01, lr_mlp: float = 0.005, temperature: float = 0.01, warmup: int = 10,
+                 loss_weights=(1.0, 1.0, 1.0, 1.0), deterministic: bool = False):
+        d = FaithfulDesc()
+        d.ep_levels, d.ep_base_res, d.col_levels, d.col_base_res = ep_levels, ep_base_res, col_levels, col_base_res
+        d.grid_dtype = GRID_F32
+        d.n_textures = len(formats)
+        for i, f in enumerate(formats):
+            d.formats[i] = int(f)
+        d.blocks_w, d.blocks_h = blocks_w, blocks_h
+        self.desc = d
+        self.formats = list(formats)
+        self.targets = targets
+        self.params = [t.clone().contiguous() for t in (ep_grid, col_grid, ep_weights, col_weights)]
+        self.ep_grid, self.col_grid, self.ep_weights, self.col_weights = self.params
+        self.m = [torch.zeros_like(t) for t in self.params]
+        self.v = [torch.zeros_like(t) for t in self.params]
+        self.grads = [torch.zeros_like(t) for t in self.params]
+        self.d_ep_grid, self.d_col_grid, self.d_ep_weights, self.d_col_weights = self.grads
+        ptrs = self.params + [self.m[0], self.v[0], self.m[1], self.v[1], self.m[2], self.v[2], self.m[3], self.v[3]] + \
+            self.grads
+        self.state = FaithfulTrainStateC(*[t.data_ptr() for t in ptrs])
+        ws = _SZ()
+        _check(lib().ntbc_faithful_train_size(ctypes.byref(d), batch, ctypes.byref(ws)))
+        self.ws = _scratch(ws.value, ep_grid.device)
+        self.losses = torch.zeros(5, dtype=torch.float32, device=ep_grid.device)
+        self.h = HParams(lr_grid, lr_mlp, 0.9, 0.999, 1e-15, temperature, warmup, total_steps, 0, FP32,
+                         (ctypes.c_float * 4)(*loss_weights), int(deterministic), 0)
+
+    def step(self, ids: torch.Tensor, step: int, qat: bool = False) -> torch.Tensor:
+        """One step on the block batch ids (int32, device); returns the device losses[5] (overwritten)."""
+        self.h.qat = int(qat)
+        _check(lib().ntbc_faithful_train_step(ctypes.byref(self.desc), ctypes.byref(self.state),
+                                              ctypes.byref(self.targets.c), _ptr(ids), ids.numel(), step,
+                                              ctypes.byref(self.h), _ptr(self.losses), _ptr(self.ws), self.ws.numel(),
+                                              _stream()))
+        return self.losses
 
 
 def batch_ids(seed: int, step: int, batch: int, n_positions: int, out: Optional[torch.Tensor] = None,

@@ -122,3 +122,33 @@ def test_batch_plan_validates_on_host():
     junk = (ctypes.c_uint8 * 64)()
     assert lib.ntbc_infer_batch(ctypes.addressof(junk), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 1 << 20,
                                 None, None) == ntbc.EINVAL
+
+
+def test_paper_layout_training_arguments_on_host():
+    # workspace sizing and the host-side refusals of ntbc_faithful_train_step (no GPU call is reached)
+    ensure_built()
+    lib = ntbc.lib()
+    d = ntbc.FaithfulDesc()
+    d.ep_levels, d.ep_base_res, d.col_levels, d.col_base_res = 7, 16, 8, 16
+    d.grid_dtype, d.n_textures = ntbc.GRID_F32, 6
+    for i, f in enumerate([ntbc.BC1, ntbc.BC1, ntbc.BC4, ntbc.BC4, ntbc.BC4, ntbc.BC4]):
+        d.formats[i] = f
+    d.blocks_w = d.blocks_h = 1024
+    sizes = []
+    for batch in (1, 1024, 4096):
+        ws = ctypes.c_size_t()
+        assert lib.ntbc_faithful_train_size(ctypes.byref(d), batch, ctypes.byref(ws)) == ntbc.OK
+        sizes.append(ws.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    ws = ctypes.c_size_t()
+    assert lib.ntbc_faithful_train_size(ctypes.byref(d), 0, ctypes.byref(ws)) == ntbc.EINVAL
+    d.grid_dtype = ntbc.GRID_U8
+    assert lib.ntbc_faithful_train_size(ctypes.byref(d), 64, ctypes.byref(ws)) == ntbc.EINVAL
+    assert b"FP32 master grids" in lib.ntbc_last_error()
+    d.grid_dtype = ntbc.GRID_F32
+    h = ntbc.HParams(0.01, 0.005, 0.9, 0.999, 1e-15, 0.01, 10, 100, 0, ntbc.BF16, (ctypes.c_float * 4)(1, 1, 1, 1), 0, 0)
+    st = ntbc.FaithfulTrainStateC()
+    assert lib.ntbc_faithful_train_step(ctypes.byref(d), None, None, None, 1, 0, ctypes.byref(h), None, None, 0,
+                                        None) == ntbc.EINVAL
+    assert lib.ntbc_faithful_train_step(ctypes.byref(d), ctypes.byref(st), None, None, 1, 0, ctypes.byref(h), None,
+                                        None, 0, None) == ntbc.EUNSUPPORTED
