@@ -342,6 +342,56 @@ def paper_layout(args):
             out[f"{name}_{layout}"] = {"ms": ms, "blocks_per_s": len(formats) * bw * bh / (ms * 1e-3),
                                        "models": len(groups), "tflops": fl / (ms * 1e-3) / 1e12,
                                        "frac_fp16_peak": fl / (ms * 1e-3) / PEAK_BF16_TFLOPS / 1e12}
+    out["training"] = paper_layout_training(args, rng, bw, bh)
+    return out
+
+
+def paper_layout_training(args, rng, bw, bh):
+    """Training steps of the paper's layout (ntbc_faithful_train_step, FP32 products) for the two-BC1 +
+    four-BC4 4096^2 material at the encode's batch of blocks (the colour network sees 16 texels each),
+    aggressive (one model) and conservative (two models, one step each); random textures and
+    parameters (the cost does not depend on the values)."""
+    import torch
+    from paper_2407_09543_amd import ntbc
+    dev = torch.device("cuda:0")
+    six = [1, 1, 4, 4, 4, 4]
+    tex = [torch.from_numpy(rng.integers(0, 256, (args.size, args.size, 3) if f == 1 else (args.size, args.size),
+                                         dtype=np.uint8)).to(dev) for f in six]
+    ref = [ntbc.encode_ref(t, f) for t, f in zip(tex, six)]
+
+    def net(n_in, n_out):
+        dims = [n_in, 64, 64, 64, n_out]
+        return torch.from_numpy(np.concatenate([np.concatenate([
+            (rng.standard_normal((dims[k + 1], dims[k])) * np.sqrt(1.0 / dims[k])).ravel(),
+            0.1 * rng.standard_normal(dims[k + 1])]) for k in range(4)]).astype(np.float32)).to(dev)
+
+    def grid(levels):
+        nv = sum((16 << l) ** 2 for l in range(levels))
+        return torch.from_numpy(rng.uniform(-0.1, 0.1, (nv, 2)).astype(np.float32)).to(dev)
+
+    out = {"batch_blocks": args.batch, "texels_per_step": 16 * args.batch,
+           "paper_minutes_20k_iterations": {"aggressive": 10, "conservative": 16,
+                                            "note": "Fig. training: another GPU and batch; context only"}}
+    ids = ntbc.batch_ids(3, 0, args.batch, bw * bh)
+    for layout, groups in (("aggressive", [list(range(6))]), ("conservative", [[0, 1], [2, 3, 4, 5]])):
+        trainers = []
+        for g in groups:
+            fm = [six[i] for i in g]
+            e = sum(6 if f == 1 else 2 for f in fm)
+            c = sum(3 if f == 1 else 1 for f in fm)
+            tg = ntbc.Targets(torch.stack([ref[i] for i in g]), [tex[i] for i in g])
+            trainers.append(ntbc.FaithfulTrainer(fm, bw, bh, grid(7), grid(8), net(14, e), net(16, c), tg, args.batch,
+                                                 20000))
+        step = [0]
+
+        def run():
+            for tr in trainers:
+                tr.step(ids, step[0])
+            step[0] += 1
+        ms = time_call(run, 10, 2, torch)
+        out[layout] = {"ms_per_step": ms, "models": len(groups), "minutes_20k_iterations": ms * 20000 / 60000.0}
+        del trainers
+        torch.cuda.empty_cache()
     return out
 
 

@@ -391,7 +391,7 @@ struct GemmArgs {
   const float* bias;  // [N]
   const float* mask;  // C(m, n) *= (mask[m*ldm + n] > 0)
   int64_t ldm;
-  float* colsum;      // bfloat16 split-K product only: colsum[m] += sum over k of A(m, k) in FP32 (bias gradient)
+  float* colsum;      // optional: colsum[m] += sum over k of A(m, k) in FP32 (the bias gradient of a weight product)
 };
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -399,6 +399,8 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 // C = A * B with a fused epilogue on the FP32 matrix cores: 64x64 workgroup tile, 16-deep K slices
 // staged in LDS; wave w computes the 32x32 quadrant (w/2, w%2) as 2x2 v_mfma_f32_16x16x4f32 tiles
 // (operand lane l: row/column l%16, k = l/16; accumulator v of lane l: row 4(l/16)+v, column l%16).
+// With g.colsum, the blocks of the first column tile also sum their A rows over their K range from the
+// staged slices (one atomic add per row and K range).
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   constexpr int TM = 64, TN = 64, TK = 16;
@@ -416,6 +418,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{};
   const int li = lane & 15, lk = lane >> 4;
+  const bool do_cs = g.colsum != nullptr && blockIdx.x == 0 && tid < TM;
+  float csum = 0.0f;
   for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -442,6 +446,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       Bs[kb][nn] = (n < g.N && kq < kend) ? g.b[(int64_t)kq * g.sbk + (int64_t)n * g.sbn] : 0.0f;
     }
     __syncthreads();
+    if (do_cs) {
+#pragma unroll
+      for (int kk = 0; kk < TK; ++kk) csum += As[kk][tid];
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const float a0 = As[kk + lk][wm * 32 + li], a1 = As[kk + lk][wm * 32 + 16 + li];
@@ -453,6 +461,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     __syncthreads();
   }
+  if (do_cs && m0 + tid < g.M) atomicAdd(&g.colsum[m0 + tid], csum);
 #pragma unroll
   for (int tm = 0; tm < 2; ++tm) {
 #pragma unroll
@@ -2235,8 +2244,9 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
     const int kq = c.bf16 ? kBTK : 16;
     gw.k_split = (int)(ceil_div(ceil_div(c.n, splits), kq) * kq);
     splits = (int)ceil_div(c.n, gw.k_split);
-    // db_k += column sums of dZ_k: fused into the bfloat16 product, a separate kernel otherwise
-    const bool fused = c.bf16 && gw.sak != 1;  // the kernel sums A staged MN-contiguous
+    // db_k += column sums of dZ_k: fused into the product (the bfloat16 kernel sums A staged MN-contiguous
+    // only), a separate kernel otherwise
+    const bool fused = !c.bf16 || gw.sak != 1;
     if (fused) gw.colsum = d_weights + s.b_off[k];
     st = gemm<EPI_ATOMIC>(gw, splits, c.strm, c.bf16);
     if (st != NTBC_OK) return st;
