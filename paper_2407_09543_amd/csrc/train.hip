@@ -264,6 +264,81 @@ __global__ void __launch_bounds__(kBlock) k_scatter(FeatArgs a, const float* __r
   scatter_one<Acc>(a, dx, pl / nl, first_level + (int)(pl % nl), f, dgrid, det_scale ? *det_scale : 1.0f);
 }
 
+// Levels [first_level, n_levels) when the positions are the texels of whole blocks (16 consecutive
+// positions: texels (4bx + x, 4by + y), i = 4y + x, of a texel grid of blocks_w x blocks_h cells) and
+// no level is finer than the texel grid: one thread per (block, level, feature).  Adjacent texels'
+// corners then differ by at most one vertex, so a block's 16 texels touch at most 5 x 5 vertices of a
+// level; their 64 weighted terms are summed in registers first (the bilinear weights are separable:
+// sum over y of wy(y, b) * sum over x of wx(x, a) d(x, y)), and the block adds each touched vertex once.
+template <typename Acc>
+__global__ void __launch_bounds__(kBlock) k_scatter_texels(FeatArgs a, const float* __restrict__ dx,
+                                                           Acc* __restrict__ dgrid, int first_level,
+                                                           const float* __restrict__ det_scale) {
+  const int nl = a.n_levels - first_level;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= (a.n / 16) * nl * a.F) return;
+  const int f = (int)(gid % a.F);
+  const int64_t pl = gid / a.F;
+  const int l = first_level + (int)(pl % nl);
+  const int64_t b = pl / nl;
+  const int t0 = clamp_id(a.ids[16 * b], (int64_t)a.blocks_w * a.blocks_h);
+  const int tx0 = t0 % a.blocks_w, ty0 = t0 / a.blocks_w;
+  const int res = a.base_res << l;
+  dev::Corner cx[4], cy[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    cx[k] = a.shift_x >= 0 ? dev::corner_pow2(tx0 + k, a.blocks_w, res, a.shift_x) : dev::corner(tx0 + k, a.blocks_w, res);
+    cy[k] = a.shift_y >= 0 ? dev::corner_pow2(ty0 + k, a.blocks_h, res, a.shift_y) : dev::corner(ty0 + k, a.blocks_h, res);
+  }
+  // rows: T[y][c] = sum over x of wx(x, c) d(x, y), column c = vertex cx[0].i0 + c
+  float tr[4][5];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) tr[y][c] = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const float d = dx[((16 * b + 4 * y + x) * a.n_levels + l) * a.F + f];
+      const int o = cx[x].i0 - cx[0].i0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const float w = c == o ? 1.0f - cx[x].f : (c == o + 1 ? cx[x].f : 0.0f);
+        tr[y][c] = fmaf(w, d, tr[y][c]);
+      }
+    }
+  }
+  const float s = a.stats ? reinterpret_cast<const float*>(a.stats)[2 * NTBC_MAX_LEVELS + l] : 1.0f;
+  const int z = a.stats ? a.stats[3 * NTBC_MAX_LEVELS + l] : 0;
+  const float scale = det_scale ? *det_scale : 1.0f;
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    float acc[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int o = cy[y].i0 - cy[0].i0;
+      const float w = r == o ? 1.0f - cy[y].f : (r == o + 1 ? cy[y].f : 0.0f);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] = fmaf(w, tr[y][c], acc[c]);
+    }
+    const int vy = cy[0].i0 + r;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const int vx = cx[0].i0 + c;
+      if (acc[c] == 0.0f || vx > res - 1 || vy > res - 1) continue;
+      const int64_t v = a.level_offset[l] + (int64_t)vy * res + vx;
+      if (a.stats) {
+        bool inside;
+        fake_quant(a.grid[v * a.F + f], s, z, &inside);
+        if (!inside) continue;
+      }
+      if constexpr (sizeof(Acc) == 8)
+        atomicAdd(&dgrid[v * a.F + f], (Acc)(long long)rint((double)acc[c] * (double)scale));
+      else
+        atomicAdd(&dgrid[v * a.F + f], acc[c]);
+    }
+  }
+}
+
 // Levels [0, n_coarse) (their gradient fits in LDS): every block accumulates a contiguous share of the
 // batch in LDS and writes its sums to its own row of `part` ([gridDim.x][nv]); k_scatter_reduce then
 // adds the rows in block order.  No global atomics, and the sum does not depend on the schedule.
@@ -2092,6 +2167,7 @@ struct Ctx {
   bool bf16;  // bfloat16 matrix-core operands (FP32 accumulation, FP32 master parameters)
   bool det = false;     // deterministic reductions (grid scatter in fixed point, unsplit weight products)
   bool selu = false;    // SELU hidden layers (the paper's own layout) instead of ReLU
+  bool texel_blocks = false;  // the positions are the 16 texels of each block in turn (texel-grid ids)
   int64_t det_off = 0;  // byte offset of the deterministic scatter's sums in the workspace
   int* stats() { return reinterpret_cast<int*>(ws + lay.stats); }
   float* act_in(int k) { return k == 0 ? ws + lay.x : ws + lay.h[k - 1]; }
@@ -2201,7 +2277,17 @@ int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const 
                          reinterpret_cast<const float*>(part), kCoarseBlocks, nv, d_grid);
     }
   }
-  if (n_coarse < s.n_levels) {
+  // texel blocks: per-block sums when no fine level is finer than the texel grid
+  const int64_t finest = (int64_t)s.base_res << (s.n_levels - 1);
+  if (n_coarse < s.n_levels && c.texel_blocks && c.n % 16 == 0 && finest <= s.blocks_w && finest <= s.blocks_h) {
+    const dim3 grid_dim((unsigned)ceil_div(c.n / 16 * (s.n_levels - n_coarse) * s.n_features, kBlock));
+    if (c.det)
+      hipLaunchKernelGGL(k_scatter_texels<unsigned long long>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, acc, n_coarse,
+                         (const float*)scale);
+    else
+      hipLaunchKernelGGL(k_scatter_texels<float>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, d_grid, n_coarse,
+                         (const float*)nullptr);
+  } else if (n_coarse < s.n_levels) {
     const dim3 grid_dim((unsigned)ceil_div(c.n * (s.n_levels - n_coarse) * s.n_features, kBlock));
     if (c.det)
       hipLaunchKernelGGL(k_scatter<unsigned long long>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, acc, n_coarse,
@@ -2913,6 +2999,12 @@ Ctx faithful_ctx(const Shape& s, int64_t n, char* ws, hipStream_t strm, bool det
   return c;
 }
 
+Ctx faithful_colour_ctx(const Shape& s, int64_t n, char* ws, hipStream_t strm, bool det) {
+  Ctx c = faithful_ctx(s, n, ws, strm, det);
+  c.texel_blocks = true;
+  return c;
+}
+
 // The colour network's positions: texel i = 4y + x of block ids[p] is cell (4 bx + x, 4 by + y) of the
 // texel grid.
 __global__ void k_texel_ids(const int32_t* __restrict__ ids, int64_t n, int blocks_w, int64_t n_positions,
@@ -2984,7 +3076,7 @@ extern "C" int ntbc_faithful_train_step(const ntbc_faithful_desc* d, const ntbc_
   const hipStream_t strm = as_stream(stream);
   const bool det = h->deterministic != 0, qat = h->qat != 0;
   Ctx ce = faithful_ctx(ep, batch, ws + l.ep, strm, det);
-  Ctx cc = faithful_ctx(col, 16 * (int64_t)batch, ws + l.col, strm, det);
+  Ctx cc = faithful_colour_ctx(col, 16 * (int64_t)batch, ws + l.col, strm, det);
   int32_t* tids = reinterpret_cast<int32_t*>(ws + l.tids);
   float* heads = reinterpret_cast<float*>(ws + l.heads);
   float* dheads = reinterpret_cast<float*>(ws + l.dheads);

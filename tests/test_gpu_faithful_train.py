@@ -3,13 +3,17 @@ colour network, SELU, FP32 products; Sec. 3.2, Sec. 3.4, Sec. 4.1) against its o
 (oracle.faithful.gradients / train_step).
 
 * Gradients of both networks and both grids, and the losses, at the initial parameters, without and
-  with QAT: within float32 rounding of the FP64 oracle (relative norm 1e-4; losses 1e-5).  Blocks where
+  with QAT, with the atomic and the fixed-point (deterministic) grid scatter, with a colour grid whose
+  finest level matches the texel grid (per-block texel sums) and one finer than it (the generic
+  scatter): within float32 rounding of the FP64 oracle (relative norm 1e-4, measured about 1e-6;
+  losses 1e-5).  Blocks where
   a texel's two nearest palette entries are within 1e-6 of each other are left out of the batch: there
   the float32 and float64 argmax of the decoded-colour terms may differ (a different straight-through
   target, not a rounding difference).
 * The first Adam step: every parameter with a gradient moves by lr g / (|g| + eps) of its set's learning
   rate (grids lr_grid, networks lr_mlp, the warm-up's first step), the others stay; the moments are
   (1 - beta) g and (1 - beta2) g^2.
+* Deterministic steps repeat bitwise.
 * Training learns in both material layouts: the loss falls and the trained models' blocks (decoded by
   ntbc_faithful_infer from the FP32 grids) beat the untrained ones in PSNR."""
 import numpy as np
@@ -26,9 +30,12 @@ from paper_2407_09543_amd import encode, ntbc, synth
 
 pytestmark = pytest.mark.gpu
 
-SIZE = 128                                             # 32 x 32 blocks
+SIZE = 128                                             # 32 x 32 blocks, 128 x 128 texels
 EP = dict(n_levels=3, base_res=4, n_features=2)        # 4 .. 16 over the block grid
-COL = dict(n_levels=4, base_res=8, n_features=2)       # 8 .. 64 over the texel grid
+# 8 .. 128 over the texel grid: levels 8 .. 64 fit the LDS pre-sum of the grid scatter, level 128 takes
+# the per-block texel sums; COL_FINE adds a level finer than the texel grid (256: the generic scatter)
+COL = dict(n_levels=5, base_res=8, n_features=2)
+COL_FINE = dict(n_levels=6, base_res=8, n_features=2)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -40,7 +47,8 @@ def _lib():
 class Problem:
     """The 128^2 BC1 + BC4 material, the textures of one model, targets on both sides, parameters."""
 
-    def __init__(self, which, seed):
+    def __init__(self, which, seed, col=COL):
+        self.col = col
         mat = synth.material_small(SIZE, seed)
         texs = [t for t in mat.textures if which == "all" or (t.fmt == BC1) == (which == "bc1")]
         self.formats = [t.fmt for t in texs]
@@ -52,9 +60,9 @@ class Problem:
                                    self.tex)
         rng = np.random.default_rng(seed)
         e, c = F.output_nodes(self.formats)
-        self.ew, self.cw = self._net(rng, 2 * EP["n_levels"], e), self._net(rng, 2 * COL["n_levels"], c)
+        self.ew, self.cw = self._net(rng, 2 * EP["n_levels"], e), self._net(rng, 2 * col["n_levels"], c)
         self.eg = rng.uniform(-0.5, 0.5, (F.grid_vertices(EP), 2)).astype(np.float32)
-        self.cg = rng.uniform(-0.5, 0.5, (F.grid_vertices(COL), 2)).astype(np.float32)
+        self.cg = rng.uniform(-0.5, 0.5, (F.grid_vertices(col), 2)).astype(np.float32)
         self.bw = self.bh = SIZE // 4
 
     @staticmethod
@@ -70,12 +78,12 @@ class Problem:
         t = lambda a: torch.from_numpy(a).cuda()
         return ntbc.FaithfulTrainer(self.formats, self.bw, self.bh, t(self.eg), t(self.cg), t(self.flat(self.ew)),
                                     t(self.flat(self.cw)), self.tg_gpu, batch, total, ep_levels=EP["n_levels"],
-                                    ep_base_res=EP["base_res"], col_levels=COL["n_levels"],
-                                    col_base_res=COL["base_res"], **kw)
+                                    ep_base_res=EP["base_res"], col_levels=self.col["n_levels"],
+                                    col_base_res=self.col["base_res"], **kw)
 
     def oracle(self, ids, qat):
         return F.gradients(self.formats, self.eg, self.ew, self.cg, self.cw, self.tg_oracle, ids, self.bw, self.bh,
-                           qat, ep_cfg=EP, col_cfg=COL)
+                           qat, ep_cfg=EP, col_cfg=self.col)
 
     def clean_ids(self, seed, n, qat):
         """n distinct block ids without near ties of the decoded-colour argmax (oracle heads)."""
@@ -90,21 +98,23 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-@pytest.mark.parametrize("qat", [False, True])
+@pytest.mark.parametrize("qat,col,det", [(False, COL, False), (True, COL, False), (False, COL_FINE, False),
+                                         (True, COL, True)])
 @pytest.mark.parametrize("which", ["all", "bc1", "bc4"])
-def test_gradients_match_oracle(which, qat):
+def test_gradients_match_oracle(which, qat, col, det):
     # "all": the aggressive layout's one model over both textures; "bc1" / "bc4": the conservative
-    # layout's two models
-    pb = Problem(which, 3)
+    # layout's two models; det: the fixed-point grid scatter
+    pb = Problem(which, 3, col)
     ids = pb.clean_ids(4, 512, qat)
-    tr = pb.trainer(len(ids), 100)
+    tr = pb.trainer(len(ids), 100, deterministic=det)
     losses = tr.step(torch.from_numpy(ids).cuda(), 0, qat=qat).cpu().numpy()
     l_or, dge, dle, dgc, dlc, _ = pb.oracle(ids, qat)
     rel = [_rel(tr.d_ep_grid.cpu().numpy(), dge), _rel(tr.d_col_grid.cpu().numpy(), dgc),
            _rel(tr.d_ep_weights.cpu().numpy(), Problem.flat(dle).astype(np.float64)),
            _rel(tr.d_col_weights.cpu().numpy(), Problem.flat(dlc).astype(np.float64))]
-    log(f"paper layout training {which} qat={qat}: losses gpu {losses[:4]} oracle {l_or}; rel grad ep grid "
-        f"{rel[0]:.3g} col grid {rel[1]:.3g} ep weights {rel[2]:.3g} col weights {rel[3]:.3g}")
+    log(f"paper layout training {which} qat={qat} colour levels {col['n_levels']} det={det}: losses gpu "
+        f"{losses[:4]} oracle {l_or}; rel grad ep grid {rel[0]:.3g} col grid {rel[1]:.3g} ep weights {rel[2]:.3g} "
+        f"col weights {rel[3]:.3g}")
     assert losses[4] == 0
     assert np.allclose(losses[:4], l_or, rtol=1e-5, atol=1e-9)
     assert max(rel) <= 1e-4
@@ -134,10 +144,22 @@ def test_first_adam_step():
         assert np.allclose(v1, (1 - b2) * g * g, rtol=2.0 ** -20, atol=0)
 
 
+def test_deterministic_steps_repeat_bitwise():
+    pb = Problem("all", 4)
+    ids = torch.from_numpy(pb.clean_ids(5, 512, False)).cuda()
+    runs = []
+    for _ in range(2):
+        tr = pb.trainer(512, 20, deterministic=True)
+        for s in range(3):
+            tr.step(ids, s)
+        runs.append([t.clone() for t in tr.params + tr.grads])
+    assert all(torch.equal(a, b) for a, b in zip(*runs))
+
+
 def _infer_words(pb, formats, tr):
     m = ntbc.FaithfulModel(formats, pb.bw, pb.bh, tr.ep_grid, tr.col_grid, tr.ep_weights, tr.col_weights,
-                           ep_levels=EP["n_levels"], ep_base_res=EP["base_res"], col_levels=COL["n_levels"],
-                           col_base_res=COL["base_res"])
+                           ep_levels=EP["n_levels"], ep_base_res=EP["base_res"], col_levels=pb.col["n_levels"],
+                           col_base_res=pb.col["base_res"])
     return m.infer()
 
 
