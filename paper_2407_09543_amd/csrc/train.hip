@@ -827,6 +827,7 @@ struct LossArgs {
   float* losses;         // [5]
   int dsigmoid;          // write dL/dZ = dL/dY * Y (1 - Y) (the head's pre-activation) instead of dL/dY
   int tex_of[2][NTBC_MAX_TEXTURES];  // the BC1 textures, then the BC4 textures, in head order
+  int n_bc1;                         // how many BC1 textures (k_loss_grad_mixed)
 };
 
 // The gradient written for a head value y: dL/dY, or dL/dZ through the sigmoid.
@@ -1087,17 +1088,12 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
 // (same-address atomics from every wave serialise in L2).
 constexpr int kLossBlocks = 1024;  // about two resident rounds of five-wave blocks
 
-// One instance per format (CH = 3: BC1, CH = 1: BC4), so that each carries one path's registers; the
-// block has one wave per texture of that format (wave w works on texture a.tex_of[CH == 3 ? 0 : 1][w]).
+// The wave's groups of 16 positions for texture t of format CH (CH = 3: BC1, CH = 1: BC4); the loss sums
+// accumulate in le .. lcdc, non-finite gradients in bad.
 template <int CH>
-__global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a) {
-  __shared__ float part[NTBC_MAX_TEXTURES][4];
-  __shared__ int part_bad[NTBC_MAX_TEXTURES];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t = a.tex_of[CH == 3 ? 0 : 1][wave];
+__device__ __forceinline__ void loss_groups(const LossArgs& a, int t, int lane, float& le, float& lc, float& lcde,
+                                            float& lcdc, bool& bad) {
   const int64_t groups = (a.n + 15) / 16;
-  float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
-  bool bad = false;
   for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
     float de0[3] = {0, 0, 0}, de1[3] = {0, 0, 0};
     const int64_t p = grp * 16 + (lane >> 2);
@@ -1130,6 +1126,13 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
       }
     }
   }
+}
+
+// Block-reduced loss sums: one atomic add per block and loss, the skip flag when any wave saw a
+// non-finite value.
+__device__ __forceinline__ void loss_finish(const LossArgs& a, float le, float lc, float lcde, float lcdc, bool bad,
+                                            float (*part)[4], int* part_bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     le += __shfl_xor(le, off);
@@ -1157,6 +1160,31 @@ __global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a
     for (int w = 0; w < n_waves; ++w) any |= part_bad[w];
     if (any) atomicExch(&a.losses[4], 1.0f);
   }
+}
+
+// Materials of one format: the block has one wave per texture (wave w works on texture
+// a.tex_of[CH == 3 ? 0 : 1][w]).
+template <int CH>
+__global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad(LossArgs a) {
+  __shared__ float part[NTBC_MAX_TEXTURES][4];
+  __shared__ int part_bad[NTBC_MAX_TEXTURES];
+  float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
+  bool bad = false;
+  loss_groups<CH>(a, a.tex_of[CH == 3 ? 0 : 1][threadIdx.x >> 6], threadIdx.x & 63, le, lc, lcde, lcdc, bad);
+  loss_finish(a, le, lc, lcde, lcdc, bad, part, part_bad);
+}
+
+// Materials of both formats: waves 0 .. n_bc1-1 take the BC1 textures, the others the BC4 textures (a
+// wave-uniform branch), so the waves of a block read each row of the heads together.
+__global__ void __launch_bounds__(64 * NTBC_MAX_TEXTURES) k_loss_grad_mixed(LossArgs a) {
+  __shared__ float part[NTBC_MAX_TEXTURES][4];
+  __shared__ int part_bad[NTBC_MAX_TEXTURES];
+  float le = 0.0f, lc = 0.0f, lcde = 0.0f, lcdc = 0.0f;
+  bool bad = false;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (wave < a.n_bc1) loss_groups<3>(a, a.tex_of[0][wave], lane, le, lc, lcde, lcdc, bad);
+  else loss_groups<1>(a, a.tex_of[1][wave - a.n_bc1], lane, le, lc, lcde, lcdc, bad);
+  loss_finish(a, le, lc, lcde, lcdc, bad, part, part_bad);
 }
 
 // ------------------------------------------------------------------------------------------ naive loss
@@ -2410,9 +2438,11 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
     const int k = s.formats[i] == NTBC_BC1 ? 0 : 1;
     a.tex_of[k][nf[k]++] = i;
   }
+  a.n_bc1 = nf[0];
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks)));
-  if (nf[0] > 0) hipLaunchKernelGGL(k_loss_grad<3>, grid, dim3(64 * nf[0]), 0, strm, a);
-  if (nf[1] > 0) hipLaunchKernelGGL(k_loss_grad<1>, grid, dim3(64 * nf[1]), 0, strm, a);
+  if (nf[0] > 0 && nf[1] > 0) hipLaunchKernelGGL(k_loss_grad_mixed, grid, dim3(64 * (nf[0] + nf[1])), 0, strm, a);
+  else if (nf[0] > 0) hipLaunchKernelGGL(k_loss_grad<3>, grid, dim3(64 * nf[0]), 0, strm, a);
+  else hipLaunchKernelGGL(k_loss_grad<1>, grid, dim3(64 * nf[1]), 0, strm, a);
   return check_launch("k_loss_grad");
 }
 
