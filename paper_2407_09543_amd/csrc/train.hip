@@ -1544,9 +1544,9 @@ struct FwdArgs {
   const float* bias;
   int bias_off[kFMaxLayers];
   int n_layers, head_dim, n_bias;
-  int64_t bpad;               // position stride of the position-contiguous buffers
-  uint16_t* xt;               // [16*KS0][bpad] layer-0 inputs, bfloat16
-  uint16_t* ht;               // [n_hidden][HID][bpad] hidden outputs (after the ReLU), bfloat16
+  int64_t bpad;               // positions of the slice-major buffers (a multiple of kSlice)
+  uint16_t* xt;               // layer-0 inputs, 16*KS0 rows, bfloat16, slice-major
+  uint16_t* ht;               // hidden outputs (after the ReLU), n_hidden regions of HID rows, bfloat16, slice-major
   uint32_t* masks;            // per wave tile and hidden layer: HID/64 words a lane (ReLU derivative bits)
   float* y;                   // [n][y_ld] sigmoid heads
   int y_ld;
@@ -1624,11 +1624,14 @@ __device__ __forceinline__ f32x16_t facc_bias(const float* bt, int g) {
   return r;
 }
 
-// Position-contiguous bfloat16 stores ([row][bpad], 32 rows x the wave's 32 positions at a time)
-// go through a per-wave LDS patch: each lane writes its values of the 32 rows at its position (two-byte
-// LDS writes), then lane l reads row l/2, positions 16(l%2) .. +15 and stores them as two 16-byte words
-// (a wave writes 64 contiguous bytes of each row).  A wave's LDS operations complete in issue order, so
+// The weight gradient's operands (layer inputs and dZ, bfloat16) are stored slice-major: a region of
+// `rows` rows over bpad positions holds element (r, p) at ((p / kSlice) rows + r) kSlice + p % kSlice,
+// so one K slice of the weight-gradient product (all rows, kSlice positions) is one contiguous range.
+// The stores (32 rows x the wave's 32 positions at a time) go through a per-wave LDS patch: each lane
+// writes its values of the 32 rows at its position (two-byte LDS writes), then lane l reads row l/2,
+// positions 16(l%2) .. +15 and stores them as two 16-byte words.  A wave's LDS operations complete in issue order, so
 // the wave needs no barrier between its writes and its reads, nor before its next patch.
+constexpr int kSlice = 64;                           // positions per slice of the slice-major layout
 constexpr int kPatchLd = 40;                         // bfloat16 per patch row (80 bytes: the two lane
                                                      // groups' rows fall on different LDS banks)
 constexpr int kPatchBytes = 32 * kPatchLd * 2;       // per wave
@@ -1642,16 +1645,19 @@ struct FStore {
 
 __device__ __forceinline__ uint16_t fhalf(const uint32_t* w, int v) { return (uint16_t)((w[v / 2] >> (16 * (v % 2))) & 0xFFFFu); }
 
-// Reads the patch back and stores rows row0 .. row0+31 (those below n_rows) of buf.
-__device__ __forceinline__ void fpatch_out(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int row0,
+// Reads the patch back and stores rows row0 .. row0+31 (those below n_rows) of the slice-major region
+// buf of `rows` rows.
+__device__ __forceinline__ void fpatch_out(const FStore& st, uint16_t* __restrict__ buf, int rows, int row0,
                                            int n_rows) {
   const int row = st.lane >> 1, h = st.lane & 1;
   const u32x4 lo = *reinterpret_cast<const u32x4*>(st.patch + row * kPatchLd + 16 * h);
   const u32x4 hi = *reinterpret_cast<const u32x4*>(st.patch + row * kPatchLd + 16 * h + 8);
   if (row0 + row < n_rows) {
-    int stride = (int)bpad;
-    asm volatile("" : "+s"(stride));
-    uint16_t* dst = buf + (uint32_t)(row0 + row) * (uint32_t)stride + st.p0 + 16 * h;
+    int nr = rows;
+    asm volatile("" : "+s"(nr));
+    const uint32_t slice = (uint32_t)(st.p0 / kSlice);
+    uint16_t* dst = buf + (slice * (uint32_t)nr + (uint32_t)(row0 + row)) * (uint32_t)kSlice +
+                    (uint32_t)(st.p0 % kSlice) + 16 * h;
     *reinterpret_cast<u32x4*>(dst) = lo;
     *reinterpret_cast<u32x4*>(dst + 8) = hi;
   }
@@ -1659,7 +1665,7 @@ __device__ __forceinline__ void fpatch_out(const FStore& st, uint16_t* __restric
 
 // Two 16-row K-step operands (rows 32 pair + 16 u + 8g + m, m < 8, of operand x[u]) stored at the
 // lane's position: rows at or past n_rows are not stored.
-__device__ __forceinline__ void fstore_ksteps(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int pair, int g,
+__device__ __forceinline__ void fstore_ksteps(const FStore& st, uint16_t* __restrict__ buf, int rows, int pair, int g,
                                               const u32x4& x0, const u32x4& x1, int n_rows) {
   const uint32_t w0[4] = {x0[0], x0[1], x0[2], x0[3]}, w1[4] = {x1[0], x1[1], x1[2], x1[3]};
 #pragma unroll
@@ -1667,24 +1673,24 @@ __device__ __forceinline__ void fstore_ksteps(const FStore& st, uint16_t* __rest
     st.patch[(8 * g + m) * kPatchLd + st.j] = fhalf(w0, m);
     st.patch[(16 + 8 * g + m) * kPatchLd + st.j] = fhalf(w1, m);
   }
-  fpatch_out(st, buf, bpad, 32 * pair, n_rows);
+  fpatch_out(st, buf, rows, 32 * pair, n_rows);
 }
 
 // The 16 bfloat16 values of an epilogue tile (words w: value v in the half v%2 of word v/2; value v is
 // neuron 32t + 8(v/4) + 4g + v%4), zero for positions past the batch.
-__device__ __forceinline__ void fstore_tile(const FStore& st, uint16_t* __restrict__ buf, int64_t bpad, int t, int g,
+__device__ __forceinline__ void fstore_tile(const FStore& st, uint16_t* __restrict__ buf, int rows, int t, int g,
                                             const uint32_t (&w)[8], bool live) {
 #pragma unroll
   for (int v = 0; v < 16; ++v)
     st.patch[(8 * (v / 4) + 4 * g + v % 4) * kPatchLd + st.j] = live ? fhalf(w, v) : (uint16_t)0;
-  fpatch_out(st, buf, bpad, 32 * t, 1 << 30);
+  fpatch_out(st, buf, rows, 32 * t, rows);
 }
 
 // Forward epilogue of a hidden tile: ReLU (NaN kept, so a non-finite parameter reaches the gradient
 // check), the next product's two B operands, the derivative bits (z > 0) and the bfloat16 outputs
 // stored position-contiguous (zero for positions past the batch).
 __device__ __forceinline__ uint32_t fhidden_epilogue(const f32x16_t& acc, int t, int g, u32x4* lo, u32x4* hi,
-                                                     uint16_t* __restrict__ ht, int64_t bpad, const FStore& st,
+                                                     uint16_t* __restrict__ ht, int rows, const FStore& st,
                                                      bool live) {
   float r[16];
   uint32_t bits = 0;
@@ -1697,7 +1703,7 @@ __device__ __forceinline__ uint32_t fhidden_epilogue(const f32x16_t& acc, int t,
   *lo = fpack8(r);
   *hi = fpack8(r + 8);
   const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
-  fstore_tile(st, ht, bpad, t, g, w, live);
+  fstore_tile(st, ht, rows, t, g, w, live);
   return bits;
 }
 
@@ -1716,7 +1722,7 @@ __device__ __forceinline__ void fwd_hidden(const FwdArgs& a, const u32x4 (&in)[S
 #pragma unroll
     for (int u = 0; u < kFChunkTiles; ++u) {
       const int t = kFChunkTiles * tc + u;
-      word |= fhidden_epilogue(acc[u], t, g, &out[2 * t], &out[2 * t + 1], ht, a.bpad, st, live) << (16 * u);
+      word |= fhidden_epilogue(acc[u], t, g, &out[2 * t], &out[2 * t + 1], ht, 32 * T, st, live) << (16 * u);
     }
     mk[tc * 64] = word;
     fwait_dma();
@@ -1753,7 +1759,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
     x0[s] = fpack8(v);
   }
 #pragma unroll
-  for (int s = 0; s < KS0; s += 2) fstore_ksteps(st, a.xt, a.bpad, s / 2, g, x0[s], s + 1 < KS0 ? x0[s + 1] : u32x4{}, 16 * KS0);
+  for (int s = 0; s < KS0; s += 2) fstore_ksteps(st, a.xt, 16 * KS0, s / 2, g, x0[s], s + 1 < KS0 ? x0[s + 1] : u32x4{}, 16 * KS0);
   fwait_dma();
   __syncthreads();
 
@@ -1773,7 +1779,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
       for (int u = 0; u < kFChunkTiles; ++u) {
         const int t = kFChunkTiles * tc + u;
-        word |= fhidden_epilogue(acc[u], t, g, &bin[2 * t], &bin[2 * t + 1], a.ht, a.bpad, st, live) << (16 * u);
+        word |= fhidden_epilogue(acc[u], t, g, &bin[2 * t], &bin[2 * t + 1], a.ht, HID, st, live) << (16 * u);
       }
       mk[tc * 64] = word;
       fwait_dma();
@@ -1835,7 +1841,7 @@ struct BwdArgs {
   int64_t n, bpad;
   const u32x4* wpack;
   const uint32_t* masks;
-  uint16_t* dzt;              // position-contiguous bfloat16 dZ_k: rows zrow[k] .. of [rows][bpad]
+  uint16_t* dzt;              // bfloat16 dZ_k, slice-major: layer k's region (out_pad rows) starts at row zrow[k]
   int64_t zrow[kFMaxLayers];
   float* dx;                  // [n][in_dim]
   int in_dim, n_layers;
@@ -1845,14 +1851,14 @@ struct BwdArgs {
 // Backward epilogue of a tile: dZ = dH * (z > 0) (`bits`), the next product's B operands, and the
 // bfloat16 dZ stored position-contiguous.
 __device__ __forceinline__ void fbwd_epilogue(const f32x16_t& acc, uint32_t bits, int t, int g, u32x4* lo, u32x4* hi,
-                                              uint16_t* __restrict__ zt, int64_t bpad, const FStore& st, bool live) {
+                                              uint16_t* __restrict__ zt, int rows, const FStore& st, bool live) {
   float r[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) r[v] = ((bits >> v) & 1u) ? acc[v] : 0.0f;
   *lo = fpack8(r);
   *hi = fpack8(r + 8);
   const uint32_t w[8] = {(*lo)[0], (*lo)[1], (*lo)[2], (*lo)[3], (*hi)[0], (*hi)[1], (*hi)[2], (*hi)[3]};
-  fstore_tile(st, zt, bpad, t, g, w, live);
+  fstore_tile(st, zt, rows, t, g, w, live);
 }
 
 // One backward product W_k^T dZ_k over a hidden layer's rows (T tiles), K = KS steps of `in`.
@@ -1871,7 +1877,7 @@ __device__ __forceinline__ void bwd_hidden(const BwdArgs& a, const u32x4 (&in)[N
 #pragma unroll
     for (int u = 0; u < kFChunkTiles; ++u) {
       const int t = kFChunkTiles * tc + u;
-      fbwd_epilogue(acc[u], word >> (16 * u), t, g, &out[2 * t], &out[2 * t + 1], zt, a.bpad, st, live);
+      fbwd_epilogue(acc[u], word >> (16 * u), t, g, &out[2 * t], &out[2 * t + 1], zt, 32 * T, st, live);
     }
     fwait_dma();
     __syncthreads();
@@ -1905,7 +1911,7 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
     dzh[s] = fpack8(v);
   }
 #pragma unroll
-  for (int s = 0; s < KH; s += 2) fstore_ksteps(st, zh, a.bpad, s / 2, g, dzh[s], dzh[s + 1], 16 * KH);
+  for (int s = 0; s < KH; s += 2) fstore_ksteps(st, zh, 16 * KH, s / 2, g, dzh[s], dzh[s + 1], 16 * KH);
   fwait_dma();
   __syncthreads();
 
@@ -1964,8 +1970,8 @@ __global__ void __launch_bounds__(64 * kFW) __attribute__((amdgpu_waves_per_eu(2
 
 // ----------------------------------------------------------------------------- weight gradient
 struct DwJob {
-  const uint16_t* a;  // A(m, k) = a[m * bpad + k]: dZ_k rows (output neurons), rows < a_rows
-  const uint16_t* b;  // B(n, k) = b[n * bpad + k]: layer inputs, rows < b_rows
+  const uint16_t* a;  // A(m, k): dZ_k rows (output neurons), slice-major region of a_rows rows
+  const uint16_t* b;  // B(n, k): layer inputs, slice-major region of b_rows rows
   int a_rows, b_rows; // rows present in the buffers (padded, zero past the true sizes)
   int M, N;           // true output sizes
   int tiles_n, tile0; // 128-wide tiles along N; first global tile of the job
@@ -1987,11 +1993,11 @@ struct DwArgs {
 // into registers while the previous slice is multiplied from LDS, then stores them to the other LDS
 // buffer (one barrier per slice); a lane's fragment (row l%32, positions 8(l/32) .. +7 of a K-step) is
 // one 16-byte LDS read.
-constexpr int kDwK = 64;          // positions per slice
+constexpr int kDwK = kSlice;      // positions per slice (one slice of the slice-major operands)
 constexpr int kDwRow = kDwK + 8;  // LDS row stride in bfloat16 (144 bytes)
 constexpr int kDwLd = kDwK / 16;  // 16-byte loads per thread and operand
 
-__global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_train_dw(DwArgs a) {
   __shared__ __align__(16) uint16_t As[2][128][kDwRow];
   __shared__ __align__(16) uint16_t Bs[2][128][kDwRow];
   // Workgroups are dispatched round-robin over the eight XCDs; give each XCD a contiguous run of
@@ -2013,29 +2019,37 @@ __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
   const int sr = tid >> 1, sh = (tid & 1) * (kDwK / 2);
   const int arow = tm * 128 + sr, brow = tn * 128 + sr;
   const bool aok = arow < J.a_rows, bok = brow < J.b_rows;
-  const u32x4* ag = reinterpret_cast<const u32x4*>(J.a + (int64_t)(aok ? arow : 0) * a.bpad + sh);
-  const u32x4* bg = reinterpret_cast<const u32x4*>(J.b + (int64_t)(bok ? brow : 0) * a.bpad + sh);
+  // slice-major operands: slice k / kDwK of a region starts (k / kDwK) rows kDwK elements in
+  const uint16_t* ag = J.a + (int64_t)(aok ? arow : 0) * kDwK + sh;
+  const uint16_t* bg = J.b + (int64_t)(bok ? brow : 0) * kDwK + sh;
+  const int64_t astep = (int64_t)J.a_rows * kDwK, bstep = (int64_t)J.b_rows * kDwK;
   const bool sums = tn == 0;  // bias gradient: row sums of A in FP32
   float rs = 0.0f;
-  u32x4 ra[kDwLd], rb[kDwLd];
-  auto load = [&](int64_t k) {
+  // two register stages, so that two slices are in flight while one is multiplied; the loop below runs
+  // in pairs of slices so that every stage index is a compile-time constant
+  u32x4 ra[2][kDwLd], rb[2][kDwLd];
+  auto load = [&](int64_t k, int r) {
+    const u32x4* ap = reinterpret_cast<const u32x4*>(ag + (k / kDwK) * astep);
+    const u32x4* bp = reinterpret_cast<const u32x4*>(bg + (k / kDwK) * bstep);
 #pragma unroll
     for (int h = 0; h < kDwLd; ++h) {
-      ra[h] = aok ? ag[k / 8 + h] : u32x4{};
-      rb[h] = bok ? bg[k / 8 + h] : u32x4{};
+      ra[r][h] = aok ? ap[h] : u32x4{};
+      rb[r][h] = bok ? bp[h] : u32x4{};
     }
+  };
+  // the row sums are taken here, when the slice is needed anyway, not at the load (which would wait)
+  auto store = [&](int r, int buf) {
     if (sums) {
 #pragma unroll
       for (int h = 0; h < kDwLd; ++h)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rs += __uint_as_float(ra[h][e] << 16) + __uint_as_float(ra[h][e] & 0xFFFF0000u);
+        for (int e = 0; e < 4; ++e)
+          rs += __uint_as_float(ra[r][h][e] << 16) + __uint_as_float(ra[r][h][e] & 0xFFFF0000u);
     }
-  };
-  auto store = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < kDwLd; ++h) {
-      *reinterpret_cast<u32x4*>(&As[buf][sr][sh + 8 * h]) = ra[h];
-      *reinterpret_cast<u32x4*>(&Bs[buf][sr][sh + 8 * h]) = rb[h];
+      *reinterpret_cast<u32x4*>(&As[buf][sr][sh + 8 * h]) = ra[r][h];
+      *reinterpret_cast<u32x4*>(&Bs[buf][sr][sh + 8 * h]) = rb[r][h];
     }
   };
   f32x16_t acc[2][2];
@@ -2043,15 +2057,7 @@ __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj) acc[i][jj] = f32x16_t{};
-  if (k0 < k1) {
-    load(k0);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k = k0; k < k1; k += kDwK) {
-    const bool more = k + kDwK < k1;
-    if (more) load(k + kDwK);
+  auto mult = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < kDwK / 16; ++ks) {
       u32x4 af[2], bf[2];
@@ -2065,9 +2071,26 @@ __global__ void __launch_bounds__(256) k_train_dw(DwArgs a) {
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) acc[i][jj] = fmma(af[i], bf[jj], acc[i][jj]);
     }
-    if (more) store(buf ^ 1);
+  };
+  // slice k lives in LDS buffer (k - k0) / kDwK % 2; register stage 0 carries the even slices, 1 the odd
+  if (k0 < k1) {
+    load(k0, 0);
+    if (k0 + kDwK < k1) load(k0 + kDwK, 1);
+    store(0, 0);
+  }
+  __syncthreads();
+  for (int64_t k = k0; k < k1; k += 2 * kDwK) {
+    // even slice k from buffer 0; slice k + kDwK arrives in stage 1, slice k + 2 kDwK is fetched into stage 0
+    if (k + 2 * kDwK < k1) load(k + 2 * kDwK, 0);
+    mult(0);
+    if (k + kDwK < k1) store(1, 1);
     __syncthreads();
-    buf ^= 1;
+    if (k + kDwK >= k1) break;
+    // odd slice k + kDwK from buffer 1; slice k + 2 kDwK arrives in stage 0, k + 3 kDwK is fetched into stage 1
+    if (k + 3 * kDwK < k1) load(k + 3 * kDwK, 1);
+    mult(1);
+    if (k + 2 * kDwK < k1) store(0, 0);
+    __syncthreads();
   }
   float* part = a.part + ((int64_t)tile * a.splits + split) * (128 * 128);
 #pragma unroll
