@@ -436,6 +436,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-material decode")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive-approach ablation encode")
+    ap.add_argument("--no-paper-layout", action="store_true",
+                    help="skip the paper's own network layout (its inference table and training steps)")
     ap.add_argument("--copy-probe", action="store_true", help="only run the counter-calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -620,7 +622,8 @@ def main():
         "model_note": model_note,
     }
     log("the paper's own network layout on its inference-table workload")
-    result["paper_layout"] = paper_layout(args)
+    if not args.no_paper_layout:
+        result["paper_layout"] = paper_layout(args)
     if not args.no_batched:
         log("batched load-time decode of 16 materials with mip chains")
         result["batched_decode"] = batched_decode(torch, ntbc, synth)
