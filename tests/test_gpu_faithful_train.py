@@ -15,7 +15,9 @@ colour network, SELU, FP32 products; Sec. 3.2, Sec. 3.4, Sec. 4.1) against its o
   (1 - beta) g and (1 - beta2) g^2.
 * Deterministic steps repeat bitwise.
 * Training learns in both material layouts: the loss falls and the trained models' blocks (decoded by
-  ntbc_faithful_infer from the FP32 grids) beat the untrained ones in PSNR."""
+  ntbc_faithful_infer from the FP32 grids) beat the untrained ones in PSNR; after QAT in the last 10%
+  of the steps, the grids quantised to 8 bits (ntbc_quantize_grid) decode within 0.5 dB of the FP32
+  master grids."""
 import numpy as np
 import pytest
 import torch
@@ -156,10 +158,28 @@ def test_deterministic_steps_repeat_bitwise():
     assert all(torch.equal(a, b) for a, b in zip(*runs))
 
 
-def _infer_words(pb, formats, tr):
-    m = ntbc.FaithfulModel(formats, pb.bw, pb.bh, tr.ep_grid, tr.col_grid, tr.ep_weights, tr.col_weights,
+def _grid_desc(g):
+    """A model description whose grid has the shape of g (for ntbc_quantize_grid)."""
+    d = ntbc.ModelDesc()
+    d.n_levels, d.base_res, d.n_features, d.grid_dtype = g["n_levels"], g["base_res"], 2, ntbc.GRID_F32
+    d.hidden_width, d.n_hidden, d.n_textures, d.blocks_w, d.blocks_h = 64, 1, 1, 1, 1
+    d.formats[0] = BC1
+    return d
+
+
+def _infer_words(pb, formats, tr, u8=False):
+    grids = [tr.ep_grid, tr.col_grid]
+    q = [{}, {}]
+    if u8:
+        # the deployed model: both grids quantised to 8 bits per level (Sec. 3.3)
+        for k, g in enumerate((EP, pb.col)):
+            codes, scale, zero = ntbc.quantize_grid(_grid_desc(g), grids[k])
+            grids[k] = codes
+            q[k] = {"scale": scale, "zero": zero}
+    m = ntbc.FaithfulModel(formats, pb.bw, pb.bh, grids[0], grids[1], tr.ep_weights, tr.col_weights,
                            ep_levels=EP["n_levels"], ep_base_res=EP["base_res"], col_levels=pb.col["n_levels"],
-                           col_base_res=pb.col["base_res"])
+                           col_base_res=pb.col["base_res"], ep_scale=q[0].get("scale"), ep_zero=q[0].get("zero"),
+                           col_scale=q[1].get("scale"), col_zero=q[1].get("zero"))
     return m.infer()
 
 
@@ -174,17 +194,21 @@ def test_training_learns(layout):
         first = last = None
         for s in range(total):
             ids = ntbc.batch_ids(8, s, batch, pb.bw * pb.bh)
-            l = tr.step(ids, s).cpu().numpy()
+            l = tr.step(ids, s, qat=s >= total - total // 10).cpu().numpy()   # the last 10% with QAT
             assert l[4] == 0
             first = l[:4].sum() if s == 0 else first
             last = l[:4].sum()
         words = _infer_words(pb, pb.formats, tr)
+        words8 = _infer_words(pb, pb.formats, tr, u8=True)
         p0 = encode.psnr_of_words(words0, pb.tex, pb.formats, SIZE)
         p1 = encode.psnr_of_words(words, pb.tex, pb.formats, SIZE)
+        p8 = encode.psnr_of_words(words8, pb.tex, pb.formats, SIZE)
         log(f"paper layout {layout} model {which}: loss {first:.4g} -> {last:.4g}; psnr {np.round(p0, 2).tolist()} -> "
-            f"{np.round(p1, 2).tolist()}")
+            f"{np.round(p1, 2).tolist()} (FP32 grids), {np.round(p8, 2).tolist()} (8-bit grids)")
         assert last < 0.5 * first
         assert all(b > a + 3.0 for a, b in zip(p0, p1))
+        # trained with QAT at the end, the 8-bit grids decode about as well as the FP32 master grids
+        assert all(abs(b - a) < 0.5 for a, b in zip(p1, p8))
 
 
 def test_rejects():
