@@ -144,6 +144,12 @@ int ntbc_bc_encode_ref(const uint8_t* texels, int32_t width, int32_t height, int
 int ntbc_bc_decode(const uint64_t* blocks, int32_t width, int32_t height, int32_t format,
                    uint8_t* texels_out, int32_t row_pitch, void* stream);
 
+/* Block-major copy of a texture (the training targets' block_texels): blocks_out[(b * 16 + i) * channels
+ * + c] = channel c of texel i = 4y + x of block b = by * (width/4) + bx, i.e. texel (4bx + x, 4by + y);
+ * channels 3 for NTBC_BC1, 1 for NTBC_BC4.  blocks_out: uint8[(width/4)*(height/4)*16*channels]. */
+int ntbc_texels_to_blocks(const uint8_t* texels, int32_t width, int32_t height, int32_t row_pitch,
+                          int32_t format, uint8_t* blocks_out, void* stream);
+
 /* Per-block integer squared error between decoded `blocks` and `texels` -> sse_out int32[n blocks]. */
 int ntbc_block_sse(const uint64_t* blocks, const uint8_t* texels, int32_t width, int32_t height,
                    int32_t row_pitch, int32_t format, int32_t* sse_out, void* stream);
@@ -315,6 +321,10 @@ typedef struct {
   const uint64_t* ref_blocks;                 /* [n_textures][n_positions] reference BC words          */
   const uint8_t* texels[NTBC_MAX_TEXTURES];   /* per texture, row-major, tightly packed (pitch =
                                                  4*blocks_w*channels)                                   */
+  const uint8_t* block_texels[NTBC_MAX_TEXTURES]; /* optional (NULL): the same texels block-major, as
+                                                 ntbc_texels_to_blocks writes them; when set for every
+                                                 texture the losses read these (a block's 16 texels
+                                                 are one contiguous run) instead of `texels`         */
 } ntbc_targets;
 
 /* Hyper-parameters (host struct).  Paper Sec. 3.4: Adam beta1 0.9, beta2 0.999, eps 1e-15; learning

@@ -563,6 +563,32 @@ extern "C" int ntbc_bc_encode_ref(const uint8_t* texels, int32_t width, int32_t 
   return ntbc::check_launch("ntbc_bc_encode_ref");
 }
 
+// One thread per (block, texel row): the row's 4 texels (4 * ch bytes) to their place in the block-major copy.
+__global__ void __launch_bounds__(kThreads) k_texels_to_blocks(const uint8_t* __restrict__ tex, int bw, int bh, int pitch,
+                                                               int ch, uint8_t* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= (int64_t)bw * bh * 4) return;
+  const int64_t b = e >> 2;
+  const int y = (int)(e & 3);
+  const int bx = (int)(b % bw), by = (int)(b / bw);
+  const uint8_t* src = tex + (int64_t)(4 * by + y) * pitch + (int64_t)(4 * bx) * ch;
+  uint8_t* dst = out + (b * 16 + 4 * y) * ch;
+  for (int k = 0; k < 4 * ch; ++k) dst[k] = src[k];
+}
+
+extern "C" int ntbc_texels_to_blocks(const uint8_t* texels, int32_t width, int32_t height, int32_t row_pitch,
+                                     int32_t format, uint8_t* blocks_out, void* stream) {
+  int st = check_texture(texels, width, height, row_pitch, format);
+  if (st != NTBC_OK) return st;
+  NTBC_REQUIRE(blocks_out != nullptr, "blocks_out is NULL");
+  const int bw = width / 4, bh = height / 4;
+  const int64_t n = (int64_t)bw * bh * 4;
+  if (n == 0) return NTBC_OK;
+  hipLaunchKernelGGL(k_texels_to_blocks, dim3((unsigned)ntbc::ceil_div(n, kThreads)), dim3(kThreads), 0,
+                     ntbc::as_stream(stream), texels, bw, bh, row_pitch, format == NTBC_BC1 ? 3 : 1, blocks_out);
+  return ntbc::check_launch("ntbc_texels_to_blocks");
+}
+
 extern "C" int ntbc_bc_decode(const uint64_t* blocks, int32_t width, int32_t height, int32_t format,
                               uint8_t* texels_out, int32_t row_pitch, void* stream) {
   int st = check_texture(texels_out, width, height, row_pitch, format);

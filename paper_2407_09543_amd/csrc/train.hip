@@ -822,6 +822,8 @@ struct LossArgs {
   int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES], ch_off[NTBC_MAX_TEXTURES];
   const uint64_t* ref;
   const uint8_t* tex[NTBC_MAX_TEXTURES];
+  const uint8_t* btex[NTBC_MAX_TEXTURES];  // block-major copies (texel_row), used when `blocked`
+  int blocked;
   float inv_t, t2, w_e, w_c, w_cde, w_cdc;  // t2 = log2(e) / T
   float inv_ne, inv_nc;  // 1/(n E), 1/(n 16 C)
   float* losses;         // [5]
@@ -829,6 +831,16 @@ struct LossArgs {
   int tex_of[2][NTBC_MAX_TEXTURES];  // the BC1 textures, then the BC4 textures, in head order
   int n_bc1;                         // how many BC1 textures (k_loss_grad_mixed)
 };
+
+// Texel row `sub` (4 texels x CH bytes) of block id of texture t: from the block-major copy (the block's
+// texels are one contiguous run) when the targets have one, else from the row-major texture.
+template <int CH, typename Args>
+__device__ __forceinline__ const uint8_t* texel_row(const Args& a, int t, int id, int sub) {
+  if (a.blocked) return a.btex[t] + ((int64_t)id * 16 + 4 * sub) * CH;
+  const int bx = id % a.blocks_w, by = id / a.blocks_w;
+  const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
+  return a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+}
 
 // The gradient written for a head value y: dL/dY, or dL/dZ through the sigmoid.
 __device__ __forceinline__ float head_grad(const LossArgs& a, float g, float y) {
@@ -975,9 +987,7 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
       de1[ch] = a.w_e * 2.0f * d1 * a.inv_ne;
     }
   }
-  const int bx = id % a.blocks_w, by = id / a.blocks_w;
-  const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
-  const uint8_t* row = a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+  const uint8_t* row = texel_row<CH>(a, t, id, sub);
   // the lane's texel row (4 texels x CH bytes) in CH words: dword loads when the texture is 4-byte
   // aligned (the row offset always is), byte loads otherwise
   uint32_t rw[CH];
@@ -1197,6 +1207,8 @@ struct NaiveLossArgs {
   int ld, E, T, blocks_w;
   int formats[NTBC_MAX_TEXTURES], ep_off[NTBC_MAX_TEXTURES];
   const uint8_t* tex[NTBC_MAX_TEXTURES];
+  const uint8_t* btex[NTBC_MAX_TEXTURES];  // block-major copies (texel_row), used when `blocked`
+  int blocked;
   float inv_n;     // 1 / (n 16 C)
   float* losses;   // [5]
   int dsigmoid;    // write dL/dZ through the sigmoid instead of dL/dY
@@ -1220,9 +1232,7 @@ __device__ __forceinline__ void naive_texture_loss(const NaiveLossArgs& a, int64
   const bool eight = CH == 3 ? true : eh0[0] > eh1[0];
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) de0[ch] = de1[ch] = 0.0f;
-  const int bx = id % a.blocks_w, by = id / a.blocks_w;
-  const int64_t pitch = (int64_t)4 * a.blocks_w * CH;
-  const uint8_t* row = a.tex[t] + (int64_t)(4 * by + sub) * pitch + (int64_t)(4 * bx) * CH;
+  const uint8_t* row = texel_row<CH>(a, t, id, sub);
   constexpr float k255 = 1.0f / 255.0f;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
@@ -2445,7 +2455,10 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
     a.ep_off[i] = s.ep_off[i];
     a.ch_off[i] = s.ch_off[i];
     a.tex[i] = t->texels[i];
+    a.btex[i] = t->block_texels[i];
   }
+  a.blocked = 1;
+  for (int i = 0; i < s.n_textures; ++i) a.blocked &= t->block_texels[i] != nullptr;
   a.ref = t->ref_blocks;
   a.inv_t = 1.0f / temperature;
   a.t2 = (float)(1.4426950408889634 / (double)temperature);
@@ -2488,7 +2501,10 @@ int naive_loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, c
     a.formats[i] = s.formats[i];
     a.ep_off[i] = s.ep_off[i];
     a.tex[i] = t->texels[i];
+    a.btex[i] = t->block_texels[i];
   }
+  a.blocked = 1;
+  for (int i = 0; i < s.n_textures; ++i) a.blocked &= t->block_texels[i] != nullptr;
   a.inv_n = (float)(1.0 / ((double)n * 16.0 * s.channels));
   a.losses = losses;
   a.dsigmoid = dsigmoid ? 1 : 0;

@@ -70,7 +70,8 @@ class FaithfulTrainStateC(ctypes.Structure):
 
 
 class TargetsC(ctypes.Structure):
-    _fields_ = [("ref_blocks", ctypes.c_void_p), ("texels", ctypes.c_void_p * MAX_TEXTURES)]
+    _fields_ = [("ref_blocks", ctypes.c_void_p), ("texels", ctypes.c_void_p * MAX_TEXTURES),
+                ("block_texels", ctypes.c_void_p * MAX_TEXTURES)]
 
 
 class HParams(ctypes.Structure):
@@ -95,6 +96,7 @@ _SIGNATURES = {
                           ctypes.POINTER(_I64)], ctypes.c_int),
     "ntbc_workspace_size": ([ctypes.POINTER(ModelDesc), _I32, _I64, ctypes.POINTER(_SZ)], ctypes.c_int),
     "ntbc_bc_encode_ref": ([_P, _I32, _I32, _I32, _I32, _P, _P, _P], ctypes.c_int),
+    "ntbc_texels_to_blocks": ([_P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "ntbc_bc_decode": ([_P, _I32, _I32, _I32, _P, _I32, _P], ctypes.c_int),
     "ntbc_block_sse": ([_P, _P, _I32, _I32, _I32, _I32, _P, _P], ctypes.c_int),
     "ntbc_fallback": ([_P, _P, _P, _P, _I64, _F, _F, _P, _P, _P], ctypes.c_int),
@@ -489,16 +491,30 @@ class NTBCFunction(torch.autograd.Function):
         return dg, dw, None, None, None
 
 
-class Targets:
-    """Reference blocks [n_textures, n_positions] (int64) and the textures (uint8, device)."""
+def texels_to_blocks(texels: torch.Tensor, fmt: int) -> torch.Tensor:
+    """Block-major copy of a device texture: uint8 [n_blocks, 16, channels] (ntbc_texels_to_blocks)."""
+    w, h, pitch = _tex_dims(texels, fmt)
+    ch = 3 if fmt == BC1 else 1
+    out = torch.empty(((h // 4) * (w // 4), 16, ch), dtype=torch.uint8, device=texels.device)
+    _check(lib().ntbc_texels_to_blocks(_ptr(texels), w, h, pitch, fmt, _ptr(out), _stream()))
+    return out
 
-    def __init__(self, ref_blocks: torch.Tensor, textures: Sequence[torch.Tensor]):
+
+class Targets:
+    """Reference blocks [n_textures, n_positions] (int64) and the textures (uint8, device; [H, W, 3] for
+    BC1, [H, W] for BC4).  block_major: also keep block-major copies, which the losses then read."""
+
+    def __init__(self, ref_blocks: torch.Tensor, textures: Sequence[torch.Tensor], block_major: bool = True):
         self.ref_blocks = ref_blocks.contiguous()
         self.textures = [t.contiguous() for t in textures]
         self.c = TargetsC()
         self.c.ref_blocks = self.ref_blocks.data_ptr()
+        self.blocks = []
         for i, t in enumerate(self.textures):
             self.c.texels[i] = t.data_ptr()
+            if block_major:
+                self.blocks.append(texels_to_blocks(t, BC1 if t.dim() == 3 and t.shape[2] == 3 else BC4))
+                self.c.block_texels[i] = self.blocks[-1].data_ptr()
 
 
 def loss_grad(desc: ModelDesc, targets: Targets, heads: torch.Tensor, ids: torch.Tensor,

@@ -148,3 +148,15 @@ def test_block_sse_and_fallback(fmt):
     repl = sse.astype(np.float32) > np.float32(1.5) * rs.astype(np.float32) + np.float32(10.0)
     assert np.array_equal(u64(out), np.where(repl, u64(ref_w), words))
     assert int(count.item()) == int(repl.sum())
+
+
+@pytest.mark.parametrize("fmt", [1, 4])
+def test_texels_to_blocks_bit_exact(fmt):
+    # the block-major copy of the training targets equals the oracle's block split (rectangular texture)
+    rng = np.random.default_rng(12 + fmt)
+    shape = (40, 72, 3) if fmt == 1 else (40, 72)
+    tex = rng.integers(0, 256, shape, dtype=np.uint8)
+    got = ntbc.texels_to_blocks(torch.from_numpy(tex).cuda(), fmt).cpu().numpy()
+    want = bc.image_to_blocks(tex)
+    assert got.shape == (10 * 18, 16, 3 if fmt == 1 else 1)
+    assert np.array_equal(got.reshape(want.shape), want)

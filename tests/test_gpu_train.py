@@ -77,6 +77,27 @@ def test_loss_grad(which):
 
 
 @pytest.mark.parametrize("which", ["small", "mid"])
+def test_loss_block_major_targets_identical(which):
+    # the losses read the block-major copies of the targets (one contiguous run per block) or the
+    # row-major textures: the same bytes, the same arithmetic, so the same gradient bits (the loss
+    # values are sums of per-block atomic adds, whose order varies: equal to float32 rounding)
+    pb = _problem(which, 2)
+    ids, ids_d = pb.ids(6, 4096)
+    y = torch.rand((len(ids), pb.cfg.head_dim), device="cuda")
+    rows = ntbc.Targets(pb.tg_gpu.ref_blocks, pb.tg_gpu.textures, block_major=False)
+    assert len(pb.tg_gpu.blocks) == len(pb.cfg.formats) and not rows.blocks
+    la, da = ntbc.loss_grad(pb.desc, pb.tg_gpu, y, ids_d)
+    lb, db = ntbc.loss_grad(pb.desc, rows, y, ids_d)
+    assert torch.allclose(la, lb, rtol=1e-6, atol=0) and torch.equal(da, db)
+    nd = ntbc.desc_from_config(dataclasses.replace(pb.cfg, variant="naive"))
+    yn = torch.rand((len(ids), ntbc.model_sizes(nd)[1]), device="cuda")
+    for stage in (1, 2):
+        na, nda = ntbc.naive_loss_grad(nd, pb.tg_gpu, yn, ids_d, stage)
+        nb, ndb = ntbc.naive_loss_grad(nd, rows, yn, ids_d, stage)
+        assert torch.allclose(na, nb, rtol=1e-6, atol=0) and torch.equal(nda, ndb)
+
+
+@pytest.mark.parametrize("which", ["small", "mid"])
 @pytest.mark.parametrize("qat", [False, True])
 def test_backward(which, qat):
     pb = _problem(which, 3)
