@@ -16,6 +16,7 @@
 // pass recomputes the forward activations of its batch.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "device.h"
@@ -2303,7 +2304,10 @@ int coarse_levels(const Shape& s, size_t vbytes) {
 
 int64_t coarse_offset(const Shape& s, int64_t batch);
 
-int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const float* dx, float* d_grid) {
+// levels: 0 every level, 1 only the LDS-summed coarse levels, 2 only the others (atomic mode only: the
+// two parts then touch disjoint vertices and may run on different streams).
+int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const float* dx, float* d_grid,
+                 int levels = 0) {
   const Shape& s = c.s;
   const FeatArgs fa = feat_args(s, grid, qat ? c.stats() : nullptr, ids, c.n, nullptr);
   const int64_t count = s.grid_vertices * s.n_features;
@@ -2322,7 +2326,7 @@ int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const 
   }
   // coarse levels whose gradient fits in kCoarseLds of LDS are pre-aggregated per block
   const int n_coarse = coarse_levels(s, vbytes);
-  if (n_coarse > 0) {
+  if (n_coarse > 0 && levels != 2) {
     const int64_t nv = s.level_offset[n_coarse] * s.n_features;
     const size_t lds = (size_t)nv * vbytes;
     char* part = reinterpret_cast<char*>(c.ws) + coarse_offset(s, c.n);
@@ -2340,7 +2344,10 @@ int scatter_grid(Ctx& c, const float* grid, bool qat, const int32_t* ids, const 
   }
   // texel blocks: per-block sums when no fine level is finer than the texel grid
   const int64_t finest = (int64_t)s.base_res << (s.n_levels - 1);
-  if (n_coarse < s.n_levels && c.texel_blocks && c.n % 16 == 0 && finest <= s.blocks_w && finest <= s.blocks_h) {
+  if (levels == 1) {
+    // the fine levels are left to a second call
+  } else if (n_coarse < s.n_levels && c.texel_blocks && c.n % 16 == 0 && finest <= s.blocks_w &&
+             finest <= s.blocks_h) {
     const dim3 grid_dim((unsigned)ceil_div(c.n / 16 * (s.n_levels - n_coarse) * s.n_features, kBlock));
     if (c.det)
       hipLaunchKernelGGL(k_scatter_texels<unsigned long long>, grid_dim, dim3(kBlock), 0, c.strm, fa, dx, acc, n_coarse,
@@ -2702,8 +2709,40 @@ int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* we
   return check_launch("k_train_fwd");
 }
 
+// A second stream of the current device (default priority) with a fork and a join event, created on
+// first use and kept until the process ends: the grid scatter runs on it beside the weight-gradient
+// products.  `lock` is held from the fork to the join, so that calls from several host threads do not
+// interleave their uses of the two events.
+struct SideStream {
+  hipStream_t s;
+  hipEvent_t fork, join;
+  std::mutex lock;
+};
+
+int side_stream(SideStream** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static SideStream table[kMaxDevices];
+  static bool made[kMaxDevices];
+  int dev = 0;
+  NTBC_HIP(hipGetDevice(&dev));
+  NTBC_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(mu);
+  if (!made[dev]) {
+    NTBC_HIP(hipStreamCreateWithFlags(&table[dev].s, hipStreamNonBlocking));
+    NTBC_HIP(hipEventCreateWithFlags(&table[dev].fork, hipEventDisableTiming));
+    NTBC_HIP(hipEventCreateWithFlags(&table[dev].join, hipEventDisableTiming));
+    made[dev] = true;
+  }
+  *out = &table[dev];
+  return NTBC_OK;
+}
+
 // Backward of the batch from dZ of the head ([n][dz_ld]); the forward's workspace contents must be
-// current.  ADDS the gradients to d_grid and d_weights.
+// current.  ADDS the gradients to d_grid and d_weights.  The fine levels' grid scatter (FP32 atomics from
+// dX) and the weight products (from the stored activations and dZ) are independent: in atomic mode the
+// scatter runs on the side stream, forked after the coarse levels' pass and joined back before
+// returning.
 int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, const int32_t* ids, const float* dz,
                    int dz_ld, float* d_grid, float* d_weights) {
   const Shape& s = c.s;
@@ -2731,8 +2770,29 @@ int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, cons
   hipLaunchKernelGGL(bk, dim3((unsigned)(l.bpad / kFPos)), dim3(64 * kFW), lds, c.strm, b);
   int st = check_launch("k_train_bwd");
   if (st != NTBC_OK) return st;
-  st = scatter_grid(c, grid, qat, ids, b.dx, d_grid);
-  if (st != NTBC_OK) return st;
+  SideStream* side = nullptr;
+  if (!c.det) {
+    st = side_stream(&side);
+    if (st != NTBC_OK) return st;
+  }
+  std::unique_lock<std::mutex> hold;
+  if (side) {
+    hold = std::unique_lock<std::mutex>(side->lock);
+    st = scatter_grid(c, grid, qat, ids, b.dx, d_grid, 1);
+    NTBC_HIP(hipEventRecord(side->fork, c.strm));
+    NTBC_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    Ctx cs = c;
+    cs.strm = side->s;
+    if (st == NTBC_OK) st = scatter_grid(cs, grid, qat, ids, b.dx, d_grid, 2);
+    NTBC_HIP(hipEventRecord(side->join, side->s));
+    if (st != NTBC_OK) {
+      NTBC_HIP(hipStreamWaitEvent(c.strm, side->join, 0));
+      return st;
+    }
+  } else {
+    st = scatter_grid(c, grid, qat, ids, b.dx, d_grid);
+    if (st != NTBC_OK) return st;
+  }
   DwArgs d{};
   const uint16_t* xt = reinterpret_cast<const uint16_t*>(ws + l.xt);
   const uint16_t* ht = reinterpret_cast<const uint16_t*>(ws + l.ht);
@@ -2761,9 +2821,13 @@ int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, cons
   d.dbpart = reinterpret_cast<float*>(ws + l.dbpart);
   hipLaunchKernelGGL(k_train_dw, dim3((unsigned)(d.n_tiles * d.splits)), dim3(256), 0, c.strm, d);
   st = check_launch("k_train_dw");
-  if (st != NTBC_OK) return st;
-  hipLaunchKernelGGL(k_train_dw_reduce, dim3(64, (unsigned)d.n_tiles), dim3(256), 0, c.strm, d);
-  return check_launch("k_train_dw_reduce");
+  if (st == NTBC_OK) {
+    hipLaunchKernelGGL(k_train_dw_reduce, dim3(64, (unsigned)d.n_tiles), dim3(256), 0, c.strm, d);
+    st = check_launch("k_train_dw_reduce");
+  }
+  // the caller's stream waits for the scatter
+  if (side) NTBC_HIP(hipStreamWaitEvent(c.strm, side->join, 0));
+  return st;
 }
 
 // dZ = dY * Y (1 - Y) with row strides (ntbc_backward: d_heads [n][head_dim], heads [n][y_ld]).
