@@ -1097,7 +1097,20 @@ __device__ __forceinline__ void texture_loss(const LossArgs& a, int64_t p, int t
 // instead of once per texture.  A grid-stride loop over groups of 16 positions keeps the shuffles
 // uniform; the loss sums are reduced per block and added with one atomic per block and loss
 // (same-address atomics from every wave serialise in L2).
-constexpr int kLossBlocks = 1024;  // about two resident rounds of five-wave blocks
+// Blocks of the loss launches: every block resident at once (a CU holds 16 of their waves at four waves
+// per SIMD; a block has one wave per texture), so the grid-stride loop has no second, thinly filled round.
+int loss_blocks(int64_t n, int waves_per_block) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = v > 0 ? v : 256;
+    else
+      cus = 256;
+  }
+  const int64_t resident = (int64_t)cus * std::max(1, 16 / std::max(1, waves_per_block));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), resident));
+}
 
 // The wave's groups of 16 positions for texture t of format CH (CH = 3: BC1, CH = 1: BC4); the loss sums
 // accumulate in le .. lcdc, non-finite gradients in bad.
@@ -2482,7 +2495,7 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
     a.tex_of[k][nf[k]++] = i;
   }
   a.n_bc1 = nf[0];
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks)));
+  const dim3 grid((unsigned)loss_blocks(n, nf[0] + nf[1]));
   if (nf[0] > 0 && nf[1] > 0) hipLaunchKernelGGL(k_loss_grad_mixed, grid, dim3(64 * (nf[0] + nf[1])), 0, strm, a);
   else if (nf[0] > 0) hipLaunchKernelGGL(k_loss_grad<3>, grid, dim3(64 * nf[0]), 0, strm, a);
   else hipLaunchKernelGGL(k_loss_grad<1>, grid, dim3(64 * nf[1]), 0, strm, a);
@@ -2516,7 +2529,7 @@ int naive_loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, c
   a.losses = losses;
   a.dsigmoid = dsigmoid ? 1 : 0;
   a.stage = stage;
-  hipLaunchKernelGGL(k_loss_naive, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 16), kLossBlocks))),
+  hipLaunchKernelGGL(k_loss_naive, dim3((unsigned)loss_blocks(n, s.n_textures)),
                      dim3(64 * s.n_textures), 0, strm, a);
   return check_launch("k_loss_naive");
 }
