@@ -360,3 +360,39 @@ def test_fused_bf16_path_against_emulation(which, qat):
     assert dy.max() <= 1e-2 and np.percentile(dy, 99) <= 2e-3
     assert rg <= 2e-2 and rw <= 2e-2 and max(per_layer) <= 3e-2
     assert torch.equal(dw, dw2), "the weight gradient is not bitwise repeatable"
+
+
+def test_train_step_graph_replay():
+    # a bfloat16 training step captured in a HIP graph, the fine grid scatter on the library's second
+    # stream captured through its fork and join events: replayed twice (with eager work between the
+    # replays) from the starting state of two eager steps, gradients and parameters agree with the
+    # eager ones up to the FP32 atomics' order
+    pb = _problem("mid", 12)
+    _, ids_d = pb.ids(13, 2048)
+
+    def trainer():
+        return ntbc.Trainer(pb.desc, pb.grid_d, pb.flat_d, pb.tg_gpu, 2048, 100, precision=ntbc.BF16)
+    eager, graphed, warm = trainer(), trainer(), trainer()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        warm.step(ids_d, 5)  # the side stream and the kernel attributes exist before the capture
+        stream.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            graphed.step(ids_d, 5)
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a)).item()
+    for rep in range(2):
+        eager.step(ids_d, 5)
+        g.replay()
+        torch.cuda.synchronize()
+        errs = [rel(eager.d_grid, graphed.d_grid), rel(eager.d_w, graphed.d_w), rel(eager.grid, graphed.grid),
+                rel(eager.weights, graphed.weights)]
+        log(f"graph replay {rep}: rel d_grid {errs[0]:.3g} d_w {errs[1]:.3g} grid {errs[2]:.3g} weights {errs[3]:.3g}")
+        assert max(errs[:2]) < 1e-5 and max(errs[2:]) < 1e-4, (rep, errs)
+        assert torch.equal(eager.losses[4], graphed.losses[4])
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between the replays
