@@ -1507,6 +1507,7 @@ struct PackTrainArgs {
   int bias_off[kFMaxLayers];  // padded biases (floats)
   u32x4* pack;
   float* bias;
+  float* zero5;  // when set, block (0, 0) zeroes these five floats (a training step's loss sums and flag)
 };
 
 // K index of element m of K-step s in lane group g: the grid features (forward layer 0) and the head
@@ -1518,6 +1519,7 @@ __device__ __forceinline__ int fk_chained(int s, int g, int m) {
 }
 
 __global__ void __launch_bounds__(256) k_pack_train(PackTrainArgs a) {
+  if (a.zero5 != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 5) a.zero5[threadIdx.x] = 0.0f;
   const int layer = blockIdx.y >> 1;
   const bool bwd = (blockIdx.y & 1) != 0;
   if (layer >= a.n_layers) return;
@@ -2009,6 +2011,8 @@ struct DwArgs {
   int64_t bpad, K;    // K = positions (a multiple of 32)
   float* part;        // [n_tiles][splits][128 * 128]
   float* dbpart;      // [n_tiles][splits][128]
+  int assign;         // write the sums to dW and db instead of adding them
+  float* flag;        // when set: *flag = 1 if any dW or db element written is not finite
 };
 
 // Block b: tile b % n_tiles, K range b / n_tiles.  Four waves, each a 64 x 64 quadrant as 2 x 2
@@ -2133,8 +2137,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   }
 }
 
-// dW (and db) += the sum of the partial tiles over the K ranges, in K-range order; one thread per
-// element of a tile.
+// dW (and db) += the sum of the partial tiles over the K ranges, in K-range order (= with a.assign); one
+// thread per element of a tile.
 __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
   const int tile = blockIdx.y;
   int jb = 0;
@@ -2146,12 +2150,16 @@ __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
   const int e = blockIdx.x * 256 + threadIdx.x;  // gridDim.x = 64
   const int r = e / 128, col = e % 128;
   const int m = tm * 128 + r, nn = tn * 128 + col;
+  bool bad = false;
   if (m < J.M && nn < J.N) {
     float s = 0.0f;
     // unrolled so that eight loads are in flight; the additions stay in split order
 #pragma unroll 8
     for (int k = 0; k < a.splits; ++k) s += part[(int64_t)k * (128 * 128) + e];
-    J.c[(int64_t)m * J.N + nn] += s;
+    float* dst = J.c + (int64_t)m * J.N + nn;
+    const float v = a.assign ? s : *dst + s;
+    *dst = v;
+    bad = !isfinite(v);
   }
   if (tn == 0 && blockIdx.x == 0 && threadIdx.x < 128) {
     const int mr = tm * 128 + threadIdx.x;
@@ -2159,9 +2167,12 @@ __global__ void __launch_bounds__(256) k_train_dw_reduce(DwArgs a) {
       float s = 0.0f;
 #pragma unroll 8
       for (int k = 0; k < a.splits; ++k) s += a.dbpart[((int64_t)tile * a.splits + k) * 128 + threadIdx.x];
-      J.db[mr] += s;
+      const float v = a.assign ? s : J.db[mr] + s;
+      J.db[mr] = v;
+      bad |= !isfinite(v);
     }
   }
+  if (a.flag != nullptr && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicExch(a.flag, 1.0f);
 }
 
 // ------------------------------------------------------------------------------------------ batches
@@ -2454,8 +2465,9 @@ int backward(Ctx& c, const float* grid, const float* weights, bool qat, const in
 
 // dsigmoid: write dL/dZ of the head pre-activations (dL/dY * Y (1 - Y)) instead of dL/dY.
 int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, float temperature,
-              const float* lw, float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0) {
-  int st = fill(losses, 5, 0.0f, strm);
+              const float* lw, float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0,
+              bool losses_zeroed = false) {
+  const int st = losses_zeroed ? NTBC_OK : fill(losses, 5, 0.0f, strm);
   if (st != NTBC_OK) return st;
   LossArgs a{};
   a.y = heads;
@@ -2504,8 +2516,9 @@ int loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const i
 
 // Naive-approach loss (stage 1 or 2) of heads [n][ld]; dsigmoid as loss_grad.
 int naive_loss_grad(const Shape& s, const ntbc_targets* t, const float* heads, const int32_t* ids, int64_t n, int stage,
-                    float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0) {
-  int st = fill(losses, 5, 0.0f, strm);
+                    float* losses, float* dheads, hipStream_t strm, bool dsigmoid = false, int ld = 0,
+                    bool losses_zeroed = false) {
+  const int st = losses_zeroed ? NTBC_OK : fill(losses, 5, 0.0f, strm);
   if (st != NTBC_OK) return st;
   NaiveLossArgs a{};
   a.y = heads;
@@ -2667,9 +2680,10 @@ void fused_kernels(int hid, FwdKernel* fk, BwdKernel* bk) {
 }
 
 // Forward of the batch: packs the weights, then heads into y ([n][y_ld]); activations, masks and the
-// layer-0 inputs stay in the workspace for fused_backward.
+// layer-0 inputs stay in the workspace for fused_backward.  zero_losses: five floats the pack kernel
+// zeroes on the way (a training step's loss sums, so the loss needs no fill of its own).
 int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* weights, bool qat, const int32_t* ids,
-                  float* y, int y_ld) {
+                  float* y, int y_ld, float* zero_losses = nullptr) {
   const Shape& s = c.s;
   const FusedLayout l = fused_layout(s, f, c.n);
   char* ws = reinterpret_cast<char*>(c.ws);
@@ -2682,6 +2696,7 @@ int fused_forward(Ctx& c, const FusedPlan& f, const float* grid, const float* we
   pk.w = weights;
   pk.pack = reinterpret_cast<u32x4*>(ws + l.pack);
   pk.bias = reinterpret_cast<float*>(ws + l.bias);
+  pk.zero5 = zero_losses;
   hipLaunchKernelGGL(k_pack_train, dim3(64, 2 * f.L), dim3(256), 0, c.strm, pk);
   st = check_launch("k_pack_train");
   if (st != NTBC_OK) return st;
@@ -2752,12 +2767,13 @@ int side_stream(SideStream** out) {
 }
 
 // Backward of the batch from dZ of the head ([n][dz_ld]); the forward's workspace contents must be
-// current.  ADDS the gradients to d_grid and d_weights.  The fine levels' grid scatter (FP32 atomics from
+// current.  ADDS the gradients to d_grid and to d_weights, or writes d_weights (assign_dw; then dw_flag,
+// when set, becomes 1 if a weight gradient is not finite).  The fine levels' grid scatter (FP32 atomics from
 // dX) and the weight products (from the stored activations and dZ) are independent: in atomic mode the
 // scatter runs on the side stream, forked after the coarse levels' pass and joined back before
 // returning.
 int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, const int32_t* ids, const float* dz,
-                   int dz_ld, float* d_grid, float* d_weights) {
+                   int dz_ld, float* d_grid, float* d_weights, bool assign_dw = false, float* dw_flag = nullptr) {
   const Shape& s = c.s;
   const FusedLayout l = fused_layout(s, f, c.n);
   char* ws = reinterpret_cast<char*>(c.ws);
@@ -2832,6 +2848,8 @@ int fused_backward(Ctx& c, const FusedPlan& f, const float* grid, bool qat, cons
   d.K = l.bpad;
   d.part = reinterpret_cast<float*>(ws + l.part);
   d.dbpart = reinterpret_cast<float*>(ws + l.dbpart);
+  d.assign = assign_dw ? 1 : 0;
+  d.flag = dw_flag;
   hipLaunchKernelGGL(k_train_dw, dim3((unsigned)(d.n_tiles * d.splits)), dim3(256), 0, c.strm, d);
   st = check_launch("k_train_dw");
   if (st == NTBC_OK) {
@@ -2992,16 +3010,18 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
     char* ws = reinterpret_cast<char*>(c.ws);
     float* y = reinterpret_cast<float*>(ws + l.y);
     float* dz = reinterpret_cast<float*>(ws + l.dz);
-    st = fused_forward(c, f, tsd->grid, tsd->weights, qat, batch_ids, y, kFHeadLd);
+    // the pack kernel zeroes the loss sums; the weight products write d_weights (no fill) and flag a
+    // non-finite weight gradient (no separate check)
+    st = fused_forward(c, f, tsd->grid, tsd->weights, qat, batch_ids, y, kFHeadLd, losses_out);
     if (st != NTBC_OK) return st;
-    st = s.naive ? naive_loss_grad(s, t, y, batch_ids, c.n, stage, losses_out, dz, c.strm, true, kFHeadLd)
+    st = s.naive ? naive_loss_grad(s, t, y, batch_ids, c.n, stage, losses_out, dz, c.strm, true, kFHeadLd, true)
                  : loss_grad(s, t, y, batch_ids, c.n, h->temperature, h->loss_weights, losses_out, dz, c.strm, true,
-                             kFHeadLd);
+                             kFHeadLd, true);
     if (st != NTBC_OK) return st;
     st = fill(tsd->d_grid, ng, 0.0f, c.strm);
-    if (st == NTBC_OK) st = fill(tsd->d_weights, s.n_weights, 0.0f, c.strm);
     if (st != NTBC_OK) return st;
-    st = fused_backward(c, f, tsd->grid, qat, batch_ids, dz, kFHeadLd, tsd->d_grid, tsd->d_weights);
+    st = fused_backward(c, f, tsd->grid, qat, batch_ids, dz, kFHeadLd, tsd->d_grid, tsd->d_weights, true,
+                        losses_out + 4);
     if (st != NTBC_OK) return st;
   } else {
     float* y = c.ws + c.lay.y;
@@ -3017,9 +3037,9 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
     if (st != NTBC_OK) return st;
     st = backward(c, tsd->grid, tsd->weights, qat, batch_ids, tsd->d_grid, tsd->d_weights);
     if (st != NTBC_OK) return st;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 1024)), dim3(256),
+                       0, c.strm, tsd->d_weights, s.n_weights, losses_out + 4);
   }
-  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 1024)), dim3(256), 0,
-                     c.strm, tsd->d_weights, s.n_weights, losses_out + 4);
   // learning rates of this step: linear warm-up, then cosine annealing to 0
   auto lr_at = [&](double lr0) {
     if (step < h->warmup) return lr0 * (double)(step + 1) / h->warmup;

@@ -197,11 +197,14 @@ def test_quantize_grid_bit_exact():
     assert np.array_equal(codes.cpu().numpy(), c_or)
 
 
-def test_nonfinite_skips_update():
+@pytest.mark.parametrize("precision", [ntbc.FP32, ntbc.BF16])
+def test_nonfinite_skips_update(precision):
+    # BF16: the fused step, whose pack kernel clears the loss sums and the flag (the second step must
+    # report OK again) and whose weight products flag non-finite weight gradients
     pb = _problem("small", 6)
     w = pb.flat_d.clone()
     w[5] = float("nan")
-    tr = ntbc.Trainer(pb.desc, pb.grid_d, w, pb.tg_gpu, 256, 10)
+    tr = ntbc.Trainer(pb.desc, pb.grid_d, w, pb.tg_gpu, 256, 10, precision=precision)
     _, ids_d = pb.ids(8, 256)
     before = tr.grid.clone()
     losses = tr.step(ids_d, 0).cpu().numpy()
