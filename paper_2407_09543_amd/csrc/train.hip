@@ -56,8 +56,16 @@ TrainLayout train_layout(const Shape& s, int64_t batch) {
 }
 
 // ------------------------------------------------------------------------------------------ helpers
+// p[0 .. n) = v: 16-byte stores over the 16-byte aligned body, single stores for the (< 4) floats
+// before and after it.
 __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t head = std::min<int64_t>(n, (int64_t)(((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4));
+  const int64_t n4 = (n - head) / 4, done = head + 4 * n4;
+  if (t < head) p[t] = v;
+  float4* q = reinterpret_cast<float4*>(p + head);
+  for (int64_t i = t; i < n4; i += stride) q[i] = float4{v, v, v, v};
+  if (t < n - done) p[done + t] = v;
 }
 
 __device__ __forceinline__ int ordered(float f) {
@@ -1352,21 +1360,72 @@ __global__ void k_check_finite(const float* __restrict__ x, int64_t n, float* __
 
 // ------------------------------------------------------------------------------------------ Adam
 struct AdamArgs {
-  float lr, b1, b2, eps, bc1, bc2;  // bc = 1 / (1 - beta^t)
+  float b1, b2, eps, bc1, bc2;  // bc = 1 / (1 - beta^t); the learning rates come with the ranges
+
   const float* flag;                // skip when *flag != 0
 };
 
-__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
-                       int64_t n, AdamArgs a) {
+// One parameter range of an Adam launch, with its learning rate; `blocks` of the launch work on it.
+struct AdamPart {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+  int blocks;
+};
+
+__device__ __forceinline__ void adam1(float& p, float g, float& m, float& v, float lr, const AdamArgs& a) {
+  const float mi = a.b1 * m + (1.0f - a.b1) * g;
+  const float vi = a.b2 * v + (1.0f - a.b2) * g * g;
+  m = mi;
+  v = vi;
+  p -= lr * (mi * a.bc1) / (sqrtf(vi * a.bc2) + a.eps);
+}
+
+// Adam over two parameter ranges in one launch: blocks [0, x.blocks) update x, the others y (an empty
+// y has no blocks).  A range whose four arrays are 16-byte aligned moves in 16-byte words (its < 4
+// trailing elements singly), any other element by element; the arithmetic per element is the same.
+__global__ void __launch_bounds__(256) k_adam(AdamPart x, AdamPart y, AdamArgs a) {
   if (*a.flag != 0.0f) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
-    const float mi = a.b1 * m[i] + (1.0f - a.b1) * gi;
-    const float vi = a.b2 * v[i] + (1.0f - a.b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= a.lr * (mi * a.bc1) / (sqrtf(vi * a.bc2) + a.eps);
+  const bool first = blockIdx.x < (unsigned)x.blocks;
+  const AdamPart& r = first ? x : y;
+  const int64_t b = first ? blockIdx.x : blockIdx.x - x.blocks;
+  const int64_t t = b * blockDim.x + threadIdx.x, stride = (int64_t)r.blocks * blockDim.x;
+  const bool vec = ((reinterpret_cast<uintptr_t>(r.p) | reinterpret_cast<uintptr_t>(r.g) | reinterpret_cast<uintptr_t>(r.m) |
+                     reinterpret_cast<uintptr_t>(r.v)) & 15) == 0;
+  int64_t done = 0;
+  if (vec) {
+    const int64_t n4 = r.n / 4;
+    float4* p4 = reinterpret_cast<float4*>(r.p);
+    const float4* g4 = reinterpret_cast<const float4*>(r.g);
+    float4* m4 = reinterpret_cast<float4*>(r.m);
+    float4* v4 = reinterpret_cast<float4*>(r.v);
+    for (int64_t i = t; i < n4; i += stride) {
+      float4 pp = p4[i], mm = m4[i], vv = v4[i];
+      const float4 gg = g4[i];
+      adam1(pp.x, gg.x, mm.x, vv.x, r.lr, a);
+      adam1(pp.y, gg.y, mm.y, vv.y, r.lr, a);
+      adam1(pp.z, gg.z, mm.z, vv.z, r.lr, a);
+      adam1(pp.w, gg.w, mm.w, vv.w, r.lr, a);
+      p4[i] = pp;
+      m4[i] = mm;
+      v4[i] = vv;
+    }
+    done = 4 * n4;
   }
+  for (int64_t i = done + t; i < r.n; i += stride) adam1(r.p[i], r.g[i], r.m[i], r.v[i], r.lr, a);
+}
+
+// Launches k_adam over ranges x and y (y.n = 0: x alone).
+int adam(AdamPart x, AdamPart y, const AdamArgs& a, hipStream_t strm) {
+  auto blocks_of = [](int64_t n) { return n > 0 ? (int)std::min<int64_t>(ceil_div(ceil_div(n, 4), 256), 8192) : 0; };
+  x.blocks = blocks_of(x.n);
+  y.blocks = blocks_of(y.n);
+  if (x.blocks + y.blocks == 0) return NTBC_OK;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)(x.blocks + y.blocks)), dim3(256), 0, strm, x, y, a);
+  return check_launch("k_adam");
 }
 
 // ------------------------------------------------------------------------------------------ quantise
@@ -2193,7 +2252,7 @@ __global__ void k_batch_ids(uint64_t key, int32_t batch, uint64_t n_positions, i
 // ------------------------------------------------------------------------------------------ host
 int fill(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return NTBC_OK;
-  const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(n, 256), 4096);
+  const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(ceil_div(n, 4), 256), 4096);
   hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, p, n, v);
   return check_launch("k_fill");
 }
@@ -3054,24 +3113,20 @@ extern "C" int ntbc_train_step(const ntbc_model_desc* d, const ntbc_train_state*
   aa.bc1 = (float)(1.0 / (1.0 - std::pow((double)h->beta1, tt)));
   aa.bc2 = (float)(1.0 / (1.0 - std::pow((double)h->beta2, tt)));
   aa.flag = losses_out + 4;
-  aa.lr = (float)lr_at(h->lr_mlp);
+  const float lr_w = (float)lr_at(h->lr_mlp);
   if (stage == 2) {
     // only the endpoint head's rows of the last layer: W rows 0..E-1 and b[0..E-1], each contiguous
     const int last = s.n_layers - 1;
     const int64_t nw = (int64_t)s.endpoint_dim * s.layer_in[last];
-    const int64_t ranges[2][2] = {{s.w_off[last], nw}, {s.b_off[last], s.endpoint_dim}};
-    for (const auto& r : ranges)
-      hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(r[1], 256), 8192)), dim3(256), 0, c.strm,
-                         tsd->weights + r[0], tsd->d_weights + r[0], tsd->m_weights + r[0], tsd->v_weights + r[0], r[1],
-                         aa);
-    return check_launch("k_adam");
+    auto part = [&](int64_t off, int64_t n) {
+      return AdamPart{tsd->weights + off, tsd->d_weights + off, tsd->m_weights + off, tsd->v_weights + off, n, lr_w, 0};
+    };
+    return adam(part(s.w_off[last], nw), part(s.b_off[last], s.endpoint_dim), aa, c.strm);
   }
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(s.n_weights, 256), 8192)), dim3(256), 0, c.strm,
-                     tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, aa);
-  aa.lr = (float)lr_at(h->lr_grid);
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(ng, 256), 8192)), dim3(256), 0, c.strm, tsd->grid,
-                     tsd->d_grid, tsd->m_grid, tsd->v_grid, ng, aa);
-  return check_launch("k_adam");
+  // the weights and the grid in one launch, each with its learning rate
+  const AdamPart pw{tsd->weights, tsd->d_weights, tsd->m_weights, tsd->v_weights, s.n_weights, lr_w, 0};
+  const AdamPart pg{tsd->grid, tsd->d_grid, tsd->m_grid, tsd->v_grid, ng, (float)lr_at(h->lr_grid), 0};
+  return adam(pw, pg, aa, c.strm);
 }
 
 // ------------------------------------------------------------------------------------------ paper layout
@@ -3290,12 +3345,14 @@ extern "C" int ntbc_faithful_train_step(const ntbc_faithful_desc* d, const ntbc_
                {tsd->col_grid, tsd->d_col_grid, tsd->m_col_grid, tsd->v_col_grid, ngc, true},
                {tsd->ep_weights, tsd->d_ep_weights, tsd->m_ep_weights, tsd->v_ep_weights, ep.n_weights, false},
                {tsd->col_weights, tsd->d_col_weights, tsd->m_col_weights, tsd->v_col_weights, col.n_weights, false}};
-  for (const Set& q : sets) {
-    aa.lr = (float)schedule_lr(h, step, q.grid ? h->lr_grid : h->lr_mlp);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(ceil_div(q.n, 256), 8192)), dim3(256), 0, strm, q.p, q.g,
-                       q.m, q.v, q.n, aa);
+  AdamPart parts[4];
+  for (int k = 0; k < 4; ++k) {
+    const Set& q = sets[k];
+    parts[k] = AdamPart{q.p, q.g, q.m, q.v, q.n, (float)schedule_lr(h, step, q.grid ? h->lr_grid : h->lr_mlp), 0};
   }
-  return check_launch("ntbc_faithful_train_step");
+  st = adam(parts[0], parts[1], aa, strm);
+  if (st == NTBC_OK) st = adam(parts[2], parts[3], aa, strm);
+  return st;
 }
 
 extern "C" int ntbc_train_status(const float* losses, void* stream) {
