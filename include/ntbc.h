@@ -54,6 +54,12 @@ extern "C" {
 #define NTBC_ENOWORKSPACE (-5)    /* workspace NULL or smaller than ntbc_workspace_size()          */
 
 /* ---- enums ------------------------------------------------------------------------------------- */
+/* The value sets below travel as int32_t (struct fields and arguments), not as C enums, so that their
+ * width and the struct layouts are the same for every compiler; these names label them. */
+typedef int32_t ntbc_format;     /* NTBC_BC1, NTBC_BC4                                              */
+typedef int32_t ntbc_precision;  /* NTBC_FP32, NTBC_BF16, NTBC_FP8_E4M3, NTBC_FP16                  */
+typedef int32_t ntbc_grid_dtype; /* NTBC_GRID_F32, NTBC_GRID_U8                                     */
+
 #define NTBC_BC1 1
 #define NTBC_BC4 4
 
