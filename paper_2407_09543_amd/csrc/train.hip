@@ -1385,8 +1385,10 @@ __device__ __forceinline__ void adam1(float& p, float g, float& m, float& v, flo
 }
 
 // Adam over two parameter ranges in one launch: blocks [0, x.blocks) update x, the others y (an empty
-// y has no blocks).  A range whose four arrays are 16-byte aligned moves in 16-byte words (its < 4
-// trailing elements singly), any other element by element; the arithmetic per element is the same.
+// y has no blocks).  A range whose four arrays are 16-byte aligned moves in 16-byte words with
+// non-temporal loads and stores (each word is touched once a step, and streaming the grid's moments
+// through the caches would evict what the next step's kernels read), its < 4 trailing elements singly;
+// any other range element by element.  The arithmetic per element is the same either way.
 __global__ void __launch_bounds__(256) k_adam(AdamPart x, AdamPart y, AdamArgs a) {
   if (*a.flag != 0.0f) return;
   const bool first = blockIdx.x < (unsigned)x.blocks;
@@ -1397,21 +1399,22 @@ __global__ void __launch_bounds__(256) k_adam(AdamPart x, AdamPart y, AdamArgs a
                      reinterpret_cast<uintptr_t>(r.v)) & 15) == 0;
   int64_t done = 0;
   if (vec) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
     const int64_t n4 = r.n / 4;
-    float4* p4 = reinterpret_cast<float4*>(r.p);
-    const float4* g4 = reinterpret_cast<const float4*>(r.g);
-    float4* m4 = reinterpret_cast<float4*>(r.m);
-    float4* v4 = reinterpret_cast<float4*>(r.v);
+    f4* p4 = reinterpret_cast<f4*>(r.p);
+    const f4* g4 = reinterpret_cast<const f4*>(r.g);
+    f4* m4 = reinterpret_cast<f4*>(r.m);
+    f4* v4 = reinterpret_cast<f4*>(r.v);
     for (int64_t i = t; i < n4; i += stride) {
-      float4 pp = p4[i], mm = m4[i], vv = v4[i];
-      const float4 gg = g4[i];
-      adam1(pp.x, gg.x, mm.x, vv.x, r.lr, a);
-      adam1(pp.y, gg.y, mm.y, vv.y, r.lr, a);
-      adam1(pp.z, gg.z, mm.z, vv.z, r.lr, a);
-      adam1(pp.w, gg.w, mm.w, vv.w, r.lr, a);
-      p4[i] = pp;
-      m4[i] = mm;
-      v4[i] = vv;
+      const f4 p0 = __builtin_nontemporal_load(p4 + i), g0 = __builtin_nontemporal_load(g4 + i);
+      const f4 m0 = __builtin_nontemporal_load(m4 + i), v0 = __builtin_nontemporal_load(v4 + i);
+      float pp[4] = {p0.x, p0.y, p0.z, p0.w}, mm[4] = {m0.x, m0.y, m0.z, m0.w}, vv[4] = {v0.x, v0.y, v0.z, v0.w};
+      const float gg[4] = {g0.x, g0.y, g0.z, g0.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) adam1(pp[e], gg[e], mm[e], vv[e], r.lr, a);
+      __builtin_nontemporal_store(f4{pp[0], pp[1], pp[2], pp[3]}, p4 + i);
+      __builtin_nontemporal_store(f4{mm[0], mm[1], mm[2], mm[3]}, m4 + i);
+      __builtin_nontemporal_store(f4{vv[0], vv[1], vv[2], vv[3]}, v4 + i);
     }
     done = 4 * n4;
   }
