@@ -56,15 +56,17 @@ TrainLayout train_layout(const Shape& s, int64_t batch) {
 }
 
 // ------------------------------------------------------------------------------------------ helpers
-// p[0 .. n) = v: 16-byte stores over the 16-byte aligned body, single stores for the (< 4) floats
-// before and after it.
+// p[0 .. n) = v: 16-byte non-temporal stores over the 16-byte aligned body (the zeroed gradient is not
+// read before the scatter's atomics, and the stores then do not evict what the kernels between read),
+// single stores for the (< 4) floats before and after it.
 __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t head = std::min<int64_t>(n, (int64_t)(((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4));
   const int64_t n4 = (n - head) / 4, done = head + 4 * n4;
   if (t < head) p[t] = v;
-  float4* q = reinterpret_cast<float4*>(p + head);
-  for (int64_t i = t; i < n4; i += stride) q[i] = float4{v, v, v, v};
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4* q = reinterpret_cast<f4*>(p + head);
+  for (int64_t i = t; i < n4; i += stride) __builtin_nontemporal_store(f4{v, v, v, v}, q + i);
   if (t < n - done) p[done + t] = v;
 }
 
